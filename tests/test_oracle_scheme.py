@@ -1,0 +1,157 @@
+"""Pins of the oracle's whole step (Eq. fvm3 with the CLS reconstruction and
+the third-order flux).
+
+* Telescoping: on a periodic mesh the area-weighted sum of W is constant.
+* Free stream: a uniform state stays uniform on a jittered mesh.
+* Quarter-turn invariance of a whole step on a walled mesh, and rotation
+  invariance of the face fluxes for rotated reconstructions.
+* Wall fluxes: no mass, energy or tangential-momentum flux through a slip
+  wall; slip and no-slip ghosts coincide for a fluid at rest.
+* Third-order convergence on the density-advection exact solution
+  (section 4.1): the observed order rises towards 3 under refinement.
+"""
+import numpy as np
+import pytest
+
+import gks_inputs as gi
+from oracle import scheme
+
+
+def test_telescoping_conservation():
+    m = gi.jss_mesh(8, 8, 5)
+    W = gi.density_advection_ic(m)
+    s = scheme.Solver(m)
+    tot0 = (s.geo.area * W).sum(axis=1)
+    W2, _ = s.run(W, 3)
+    tot = (s.geo.area * W2).sum(axis=1)
+    assert np.abs(tot - tot0).max() < 1e-14 * np.abs(tot0).max() * 3
+
+
+def test_free_stream_preservation():
+    m = gi.jss_mesh(6, 7, 9, Lx=1.5, Ly=1.0)
+    rho, u, v, p = 1.3, 0.6, -0.9, 0.8
+    W = gi.prim_to_cons(np.full(m.nt, rho), u, v, p, 1.4)
+    s = scheme.Solver(m)
+    W2, _ = s.run(W, 2)
+    assert np.abs(W2 - W).max() < 1e-13
+
+
+def rotate_mesh(m, th):
+    c, s = np.cos(th), np.sin(th)
+    R = np.array([[c, -s], [s, c]])
+    return gi.Mesh(xy=m.xy @ R.T, tri=m.tri, edge_tag=m.edge_tag, periodic=(False, False),
+                   L=m.L, bc_table=m.bc_table), R
+
+
+def walled_state(m, seed=2):
+    rng = np.random.default_rng(seed)
+    cen = m.unwrapped_vertices().mean(axis=1)
+    rho = 1.0 + 0.1 * np.sin(3 * cen[:, 0] + 2 * cen[:, 1])
+    u = 0.3 + 0.1 * np.cos(2 * cen[:, 1])
+    v = -0.2 + 0.1 * np.sin(cen[:, 0])
+    p = 1.0 + 0.05 * rng.uniform(size=m.nt)
+    return gi.prim_to_cons(rho, u, v, p, 1.4)
+
+
+def test_step_is_quarter_turn_invariant():
+    """The CLS rows weight d2/dxdy like d2/dx2 and d2/dy2 (one row per
+    (m, n), Eq. spdConserved:1), so the least-squares problem is invariant
+    under quarter turns but not under general rotations."""
+    m = gi.jss_mesh(6, 5, 17, Lx=1.0, Ly=0.8, periodic=False,
+                    walls=((gi.BC_SLIP, None),) * 4)
+    W = walled_state(m)
+    dt = 2e-3
+    W1, _ = scheme.Solver(m).step(W, dt)
+    mr, R = rotate_mesh(m, np.pi / 2)
+    Wr = W.copy()
+    Wr[1:3] = R @ W[1:3]
+    W1r, _ = scheme.Solver(mr).step(Wr, dt)
+    back = W1r.copy()
+    back[1:3] = R.T @ W1r[1:3]
+    assert np.abs(back - W1).max() < 1e-12
+
+
+def rotate_coefficients(X, R):
+    """Coefficients of the rotated polynomials: gradients (X1, X2 = h grad)
+    turn with R, Hessians (h^2 [[X3, X4], [X4, X5]]) as R H R^T, and the
+    momentum pair of variables turns with R."""
+    Xr = X.copy()
+    g = np.einsum("ab,vbn->van", R, X[:, 0:2])
+    H = np.stack([np.stack([X[:, 2], X[:, 3]], 1), np.stack([X[:, 3], X[:, 4]], 1)], 1)  # [v,2,2,n]
+    Hr = np.einsum("ab,vbcn,dc->vadn", R, H, R)
+    Xr[:, 0:2] = g
+    Xr[:, 2], Xr[:, 3], Xr[:, 4] = Hr[:, 0, 0], Hr[:, 0, 1], Hr[:, 1, 1]
+    return _turn_momentum(Xr, R)
+
+
+def _turn_momentum(Xr, R):
+    out = Xr.copy()
+    out[1:3] = np.einsum("ab,bln->aln", R, Xr[1:3])
+    return out
+
+
+def test_face_flux_is_rotation_invariant():
+    m = gi.jss_mesh(6, 5, 17, Lx=1.0, Ly=0.8, periodic=False,
+                    walls=((gi.BC_SLIP, None),) * 4)
+    W = walled_state(m)
+    s0 = scheme.Solver(m)
+    X = s0.reconstruct(W)
+    F = s0.flux(W, X, 2e-3)
+    mr, R = rotate_mesh(m, 0.7)
+    Wr = W.copy()
+    Wr[1:3] = R @ W[1:3]
+    Fr = scheme.Solver(mr).flux(Wr, rotate_coefficients(X, R), 2e-3)
+    back = Fr.copy()
+    back[1:3] = R.T @ Fr[1:3]
+    assert np.abs(back - F).max() < 1e-13 * np.abs(F).max() * 10
+
+
+@pytest.mark.parametrize("all_quadratic", [False, True])
+def test_slip_wall_fluxes(all_quadratic):
+    """A slip-wall ghost is the mirror image of the interior side, so the
+    mirror symmetry of the flux cancels mass, energy and tangential momentum.
+    With quadratic boundary cells the second-derivative mirror rules count."""
+    m = gi.jss_mesh(5, 5, 3, Lx=1.0, Ly=1.0, periodic=False, walls=((gi.BC_SLIP, None),) * 4)
+    rng = np.random.default_rng(5)
+    W = gi.prim_to_cons(1 + 0.1 * rng.uniform(size=m.nt), 0.3 * rng.normal(size=m.nt),
+                        0.3 * rng.normal(size=m.nt), 1 + 0.1 * rng.uniform(size=m.nt), 1.4)
+    s = scheme.Solver(m, scheme.Params(all_quadratic=all_quadratic))
+    F = s.flux(W, s.reconstruct(W), 1e-3)
+    bnd = s.geo.nbr < 0
+    n = s.geo.normal[bnd]
+    Ft = -F[1, bnd] * n[:, 1] + F[2, bnd] * n[:, 0]
+    scale = np.abs(F[:, bnd]).max()
+    assert np.abs(F[0, bnd]).max() < 1e-14 * scale
+    assert np.abs(F[3, bnd]).max() < 1e-14 * scale
+    assert np.abs(Ft).max() < 1e-14 * scale
+
+
+def test_noslip_at_rest_equals_slip_for_fluid_at_rest():
+    """With no velocity anywhere both wall ghosts are the same mirror image."""
+    rng = np.random.default_rng(6)
+    fluxes = []
+    for walls in (((gi.BC_SLIP, None),) * 4, ((gi.BC_NOSLIP, (0.0, 0.0, 0.0, 0.0)),) * 4):
+        m = gi.jss_mesh(5, 5, 3, Lx=1.0, Ly=1.0, periodic=False, walls=walls)
+        W = gi.prim_to_cons(1 + 0.1 * np.sin(np.arange(m.nt)), 0.0, 0.0,
+                            1 + 0.1 * np.cos(np.arange(m.nt)), 1.4)
+        s = scheme.Solver(m)
+        fluxes.append(s.flux(W, s.reconstruct(W), 1e-3))
+    assert np.abs(fluxes[0] - fluxes[1]).max() < 1e-15 * np.abs(fluxes[0]).max() * 10
+
+
+def test_third_order_convergence():
+    errs = []
+    T = 0.05
+    for N in (8, 16, 32):
+        m = gi.jss_mesh(N, N, 2)
+        W = gi.density_advection_ic(m)
+        s = scheme.Solver(m, scheme.Params(eps=0.0))
+        nst = int(np.ceil(T / scheme.cfl_dt(s.geo, W, s.prm)))
+        with np.errstate(divide="ignore"):
+            Wn, _ = s.run(W, nst, T / nst)
+        e = np.abs(Wn[0] - gi.density_advection_exact(m, T)[0])
+        errs.append((e * s.geo.area).sum() / s.geo.area.sum())
+    o1 = np.log2(errs[0] / errs[1])
+    o2 = np.log2(errs[1] / errs[2])
+    assert o2 > o1 > 2.0
+    assert o2 > 2.45
