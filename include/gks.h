@@ -1,0 +1,217 @@
+/*
+ * gks.h -- C ABI of the third-order gas-kinetic scheme on triangle meshes
+ * (compact least-squares reconstruction + second-order-expanded BGK flux +
+ * finite-volume update), built for AMD Instinct MI355X (gfx950).
+ *
+ * Method: Li, Zhong, Zhuo, "A third order gas-kinetic scheme for
+ * unstructured grid" (arXiv 1802.00704).  Each entry point cites the
+ * passage that defines what it computes.
+ *
+ * Conventions shared by every call
+ *   - State W: cell-averaged conservative variables (rho, rho u, rho v, E)
+ *     of section 2.1 (Eq. macroVar), stored as double W[4][nt] (variable
+ *     major) in DEVICE memory, cells in the caller's triangle order.
+ *   - Reconstruction X: coefficients u_1..u_5 of the zero-mean quadratic of
+ *     Eq. quadRCP for each variable, double X[4][5][nt] in DEVICE memory:
+ *     X1 = h u_x, X2 = h u_y, X3 = h^2 u_xx, X4 = h^2 u_xy, X5 = h^2 u_yy at
+ *     the cell centroid, h = max(circumradius, sqrt(area)) (Eq. h).  Cells
+ *     with a boundary edge are linear (Eq. k_i): their X3..X5 are zero.
+ *   - Faces: face f is emitted while scanning triangles t = 0..nt-1 and
+ *     local edges e = 0..2 (edge e runs from vertex e to vertex e+1 mod 3)
+ *     whenever the triangle across the edge has a larger index or the edge
+ *     is a boundary edge.  The owner is t; the unit normal points out of the
+ *     owner.  gks_faces() returns owner/neighbour arrays.
+ *   - Fluxes F: double F[4][nf] in DEVICE memory, face order as above,
+ *     x-y frame, integrated over the time step and along the face
+ *     (sum over the two Gauss points of (S/2) times the time-integrated flux
+ *     per unit length, Eqs. fluxgauss and fvm3), positive from owner to
+ *     neighbour.
+ *   - All device work is ordered on the HIP stream given at creation (NULL =
+ *     the default stream).  Device pointers must belong to the device that
+ *     was current at creation.  Calls on one handle are not thread-safe;
+ *     distinct handles are independent.
+ *   - Every call returns GKS_OK (0) or a negative error code and never
+ *     throws; gks_last_error() gives a message for the last failure.
+ */
+#ifndef GKS_H
+#define GKS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GKS_OK        0
+#define GKS_EINVAL   -1   /* bad argument or invalid mesh                         */
+#define GKS_ENOMEM   -2   /* device or host allocation failed                     */
+#define GKS_EHIP     -3   /* a HIP runtime call failed                            */
+#define GKS_ENOCONV  -4   /* GMRES did not reach the tolerance within max_iter    */
+#define GKS_ENONPHYS -5   /* non-physical state (rho <= 0 or p <= 0)              */
+
+/* precision of the reconstruction solve */
+#define GKS_FP64   0      /* FP64 GMRES(restart) with BILU(0)                        */
+#define GKS_MIXED  1      /* FP64 flexible GMRES; FP32 SpMV and ILU in inner sweeps */
+
+/* elimination order of the BILU(0) preconditioner */
+#define GKS_ORDER_MULTICOLOR 0  /* greedy colouring, RCM order inside each colour */
+#define GKS_ORDER_RCM        1  /* reverse Cuthill-McKee (level-scheduled sweeps) */
+
+/* boundary kinds (value of gks_mesh_desc.bc_kind[row]) */
+#define GKS_BC_SLIP    1  /* inviscid wall: mirror image, normal momentum reflected      */
+#define GKS_BC_NOSLIP  2  /* wall moving with (u, v) = bc_state[row][1..2]: mirror image,
+                             ghost velocity 2 U_wall - U, density and pressure even      */
+#define GKS_BC_INFLOW  3  /* fixed state (rho, u, v, p) = bc_state[row][0..3], no slopes */
+#define GKS_BC_OUTFLOW 4  /* ghost = interior state and derivatives                      */
+
+typedef struct gks_mesh gks_mesh;   /* opaque; owns every device buffer it allocates */
+
+/* Mesh description.  Host arrays are copied at creation; the caller may free
+ * them afterwards. */
+typedef struct {
+    int32_t nv;              /* vertices                                         */
+    int32_t nt;              /* triangles (cells)                                */
+    const double*  xy;       /* host [nv][2] vertex coordinates                  */
+    const int32_t* tri;      /* host [nt][3] counter-clockwise vertex indices    */
+    const int32_t* edge_tag; /* host [nt][3] or NULL: 0 interior, else 1-based
+                                row of the boundary table for edge e of t       */
+    int32_t periodic_x;      /* nonzero: x is periodic with period Lx; vertices
+                                are identified, triangles unwrapped by the
+                                minimum image                                   */
+    int32_t periodic_y;
+    double  Lx, Ly;
+    int32_t n_bc;            /* rows of the boundary table                       */
+    const int32_t* bc_kind;  /* host [n_bc] GKS_BC_* kinds                       */
+    const double*  bc_state; /* host [n_bc][4] (rho, u, v, p) per row            */
+} gks_mesh_desc;
+
+/* Scheme and solver parameters (gks_params_default fills the paper's values). */
+typedef struct {
+    double  gamma;           /* ratio of specific heats (1.4)                    */
+    double  mu;              /* dynamic viscosity; 0 selects the inviscid
+                                collision time of Eq. tauIns, > 0 Eq. tauVis    */
+    double  tau_eps;         /* coefficient of dt in Eq. tauIns (0.01)           */
+    double  cls_w;           /* derivative weight w of Eq. A:B:b:3 (0.3)         */
+    double  cfl;             /* CFL number of the time-step rule (0.5)           */
+    double  tol;             /* relative residual ||R - K X|| / ||R|| per column */
+    int32_t restart;         /* GMRES restart length m (30), 1..64               */
+    int32_t max_iter;        /* cap on Krylov iterations per solve (500)         */
+    int32_t precision;       /* GKS_FP64 or GKS_MIXED                            */
+    int32_t ordering;        /* GKS_ORDER_MULTICOLOR or GKS_ORDER_RCM            */
+    int32_t inner_iters;     /* GKS_MIXED: FP32 preconditioned sweeps per outer
+                                iteration (4)                                   */
+    int32_t exact_time;      /* 0: time coefficients c_1..c_8 of Eq.
+                                Nomenclature2 as printed; 1: exact integrals     */
+    int32_t nonphys_fallback;/* 0: non-physical Gauss-point state -> GKS_ENONPHYS;
+                                1: that side falls back to its cell average     */
+    int32_t all_quadratic;   /* testing: quadratic reconstruction in every cell  */
+} gks_params;
+
+/* Per-solve report (one entry per conserved variable). */
+typedef struct {
+    int32_t iters[4];        /* Krylov iterations                                */
+    int32_t restarts[4];     /* restart cycles                                   */
+    double  rel_resid[4];    /* final true relative residual ||R - K X|| / ||R|| */
+    int32_t nonphys;         /* non-physical Gauss-point states met in the flux  */
+} gks_solve_info;
+
+/* Mesh statistics. */
+typedef struct {
+    int32_t nt, nf, nf_boundary;
+    int32_t n_levels;        /* dependency levels of each BILU(0) sweep          */
+    int32_t n_colors;        /* colours (multicolour order) or 0                 */
+    int32_t rcm_bandwidth;   /* max |i - j| over cell neighbours in RCM order    */
+    int64_t device_bytes;    /* device memory held by the handle                 */
+} gks_mesh_stats;
+
+/* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
+ * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour. */
+void gks_params_default(gks_params* p);
+
+/* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal
+ * equations of Eq. spdConserved:5 over the face-neighbour conditions of
+ * Eqs. spdConserved:1-3 and A:B:b:2-3; the renumbering and the BILU(0)
+ * factors of section 3.2) and upload it to the current device.
+ * Errors: GKS_EINVAL for null or inconsistent arguments, clockwise or
+ * degenerate triangles, non-manifold or untagged open edges; GKS_ENOMEM;
+ * GKS_EHIP.  On error *out is NULL. */
+int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm,
+                    void* hip_stream, gks_mesh** out);
+
+/* CLS reconstruction (section 3): X solves the normal equations for the
+ * four conserved variables with right-preconditioned restarted GMRES
+ * (FP64) or flexible GMRES with FP32 inner sweeps (GKS_MIXED), warm-started
+ * from the handle's previous solution, to the relative tolerance prm.tol.
+ * W: device [4][nt] input; X: device [4][5][nt] output (may not alias W).
+ * info may be NULL.  Synchronises the stream before returning.
+ * Errors: GKS_EINVAL, GKS_ENOCONV (X then holds the last iterate), GKS_EHIP. */
+int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info* info);
+
+/* Time-integrated third-order BGK face fluxes (section 2.2: Eqs.
+ * generalSolution, fNS, 3orderf0:2, 3orderg:2, Nomenclature1-2; collision
+ * time Eq. tauIns / tauVis) at the two Gauss points of every face, given the
+ * cell states W [4][nt], reconstruction X [4][5][nt] and the step dt > 0.
+ * F: device [4][nf] output.  Enqueued only (no synchronisation) unless a
+ * non-physical state is possible, in which case the count is checked.
+ * Errors: GKS_EINVAL, GKS_ENONPHYS (fallback disabled), GKS_EHIP. */
+int gks_flux(gks_mesh* m, const double* W, const double* X, double dt, double* F);
+
+/* One step of Eq. fvm3: dt from the CFL rule when dt <= 0 (the paper gives
+ * none: dt = CFL min_i |Omega_i| / sum_f S_f (|U_i . n_f| + c_i)), then the
+ * reconstruction, the fluxes and the update W <- W - (1/|Omega|) sum s F.
+ * W: device [4][nt], updated in place only on success.  dt_used and info may
+ * be NULL.  Synchronises the stream before returning.
+ * Errors: GKS_EINVAL, GKS_ENOCONV, GKS_ENONPHYS, GKS_EHIP (W unchanged). */
+int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info* info);
+
+/* Owner and neighbour cell of every face (host arrays of nf entries; a
+ * boundary face has neighbour -(boundary row)).  Either pointer may be NULL. */
+int gks_faces(const gks_mesh* m, int32_t* own, int32_t* nbr);
+
+/* Statistics of the handle. */
+int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st);
+
+/* Per-kernel timing with HIP events on the handle's stream (enable = 1
+ * resets and starts; 0 stops).  gks_profile_get copies up to n entries:
+ * name (static string), number of launches, total milliseconds. */
+int gks_profile_enable(gks_mesh* m, int enable);
+int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms);
+
+/* Host-only view of the per-mesh state that gks_mesh_create builds (no
+ * device is touched), for inspection and tests: faces, cell measures, the
+ * renumbering, the normal-equation matrix of Eq. spdConserved:5 and its
+ * BILU(0) factors, all in solver order.  Blocks are 5 x 5 with entry
+ * e = 5 r + c; slot arrays use the value nt for an empty slot.  The library
+ * allocates every array; release them with gks_host_free.
+ * Errors: as gks_mesh_create (GKS_EINVAL, GKS_ENOMEM). */
+typedef struct {
+    int32_t  nt, nf, n_levels, n_colors, rcm_bandwidth;
+    int32_t* own;      /* [nf] owner cell                                   */
+    int32_t* nbr;      /* [nf] neighbour cell, -(boundary row) on the boundary */
+    double*  area;     /* [nt] cell areas                                   */
+    double*  h;        /* [nt] length scales of Eq. h                        */
+    int32_t* perm;     /* [nt] solver position -> cell                       */
+    int32_t* lev_ptr;  /* [n_levels + 1] rows of each sweep level            */
+    int32_t* kcol;     /* [4][nt] column of slot s of row i (slot 0 diagonal) */
+    double*  kval;     /* [4][25][nt]                                        */
+    int32_t* lcol;     /* [3][nt] strict lower factor (unit diagonal)        */
+    double*  lval;     /* [3][25][nt]                                        */
+    int32_t* ucol;     /* [3][nt] strict upper factor                        */
+    double*  uval;     /* [3][25][nt]                                        */
+    double*  dinv;     /* [25][nt] inverted pivot blocks                     */
+} gks_host_system;
+
+int  gks_host_inspect(const gks_mesh_desc* desc, const gks_params* prm, gks_host_system* out);
+void gks_host_free(gks_host_system* s);
+
+/* Message of the last error on m (or of the last failed creation when m is
+ * NULL).  The string stays valid until the next call on the same handle. */
+const char* gks_last_error(const gks_mesh* m);
+
+/* Release every resource of the handle; NULL is a no-op. */
+void gks_destroy(gks_mesh* m);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GKS_H */

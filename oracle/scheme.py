@@ -135,25 +135,29 @@ class NonPhysical(RuntimeError):
     pass
 
 
-def face_fluxes(geo: Geometry, W, X, dt, prm: Params, bc_table=(), counters=None):
-    """Time-integrated face fluxes F [4, nf] (x-y frame, owner -> neighbour)."""
-    F = np.zeros((4, geo.nf))
-    nx, ny = geo.normal[:, 0], geo.normal[:, 1]
-    inner = geo.nbr >= 0
+def face_fluxes(geo: Geometry, W, X, dt, prm: Params, bc_table=(), counters=None, faces=None):
+    """Time-integrated face fluxes F [4, nf] (x-y frame, owner -> neighbour),
+    or F [4, len(faces)] for a subset of faces."""
+    fs = np.arange(geo.nf) if faces is None else np.asarray(faces)
+    own, nbr, tag = geo.own[fs], geo.nbr[fs], geo.tag[fs]
+    nfs = fs.size
+    F = np.zeros((4, nfs))
+    nx, ny = geo.normal[fs, 0], geo.normal[fs, 1]
+    inner = nbr >= 0
     for g in range(2):
-        pts = geo.gp[:, g]
-        Q = gp_states(geo, W, X, geo.own, pts)
+        pts = geo.gp[fs, g]
+        Q = gp_states(geo, W, X, own, pts)
         WL, dL = local_derivs(*Q, nx, ny)
         WR = np.empty_like(WL)
         dR = {key: np.empty_like(val) for key, val in dL.items()}
         fi = np.nonzero(inner)[0]
         if fi.size:
-            Qr = gp_states(geo, W, X, geo.nbr[fi], pts[fi])
+            Qr = gp_states(geo, W, X, nbr[fi], pts[fi])
             wr, dr = local_derivs(*Qr, nx[fi], ny[fi])
             WR[:, fi] = wr
             for key in dR:
                 dR[key][:, fi] = dr[key]
-        for side_W, side_d, cells, sel in ((WL, dL, geo.own, np.arange(geo.nf)), (WR, dR, geo.nbr, fi)):
+        for side_W, side_d, cells, sel in ((WL, dL, own, np.arange(nfs)), (WR, dR, nbr, fi)):
             ok = physical(side_W[:, sel], prm.gamma)
             if not np.all(ok):
                 bad = sel[~ok]
@@ -165,7 +169,7 @@ def face_fluxes(geo: Geometry, W, X, dt, prm: Params, bc_table=(), counters=None
                 for key in side_d:
                     side_d[key][:, bad] = 0.0
         for row, (kind, state) in enumerate(bc_table, start=1):
-            fb = np.nonzero((~inner) & (geo.tag == row))[0]
+            fb = np.nonzero((~inner) & (tag == row))[0]
             if fb.size:
                 wg, dg = ghost(WL[:, fb], {key: val[:, fb] for key, val in dL.items()},
                                kind, state, prm.gamma, nx[fb], ny[fb])
@@ -177,7 +181,7 @@ def face_fluxes(geo: Geometry, W, X, dt, prm: Params, bc_table=(), counters=None
         Fx = Fl.copy()
         Fx[1] = Fl[1] * nx - Fl[2] * ny
         Fx[2] = Fl[1] * ny + Fl[2] * nx
-        F += 0.5 * geo.S * Fx
+        F += 0.5 * geo.S[fs] * Fx
     return F
 
 
@@ -232,8 +236,8 @@ class Solver:
         Xf = self._lu.solve(b)
         return np.ascontiguousarray(Xf.T.reshape(4, nt, 5).transpose(0, 2, 1))
 
-    def flux(self, W, X, dt):
-        return face_fluxes(self.geo, W, X, dt, self.prm, self.bc_table, self.counters)
+    def flux(self, W, X, dt, faces=None):
+        return face_fluxes(self.geo, W, X, dt, self.prm, self.bc_table, self.counters, faces)
 
     def step(self, W, dt=None):
         if dt is None or dt <= 0:

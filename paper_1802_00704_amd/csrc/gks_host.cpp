@@ -1,0 +1,1222 @@
+// Host side of libgks: per-mesh setup (geometry, faces, CLS normal
+// equations, renumbering, BILU(0)), the GMRES drivers and the C ABI.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "gks_internal.h"
+
+using namespace gks;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                      \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess)                                                             \
+            throw Fail{GKS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
+    } while (0)
+
+// ------------------------------------------------------------------ 5x5 blocks
+using Blk = std::array<double, 25>;
+
+Blk bzero() {
+    Blk b;
+    b.fill(0.0);
+    return b;
+}
+
+Blk bmul(const Blk& a, const Blk& b) {
+    Blk c = bzero();
+    for (int i = 0; i < 5; ++i)
+        for (int k = 0; k < 5; ++k) {
+            const double aik = a[i * 5 + k];
+            for (int j = 0; j < 5; ++j) c[i * 5 + j] += aik * b[k * 5 + j];
+        }
+    return c;
+}
+
+// Gauss-Jordan inverse with partial pivoting; throws on a singular block
+Blk binv(const Blk& a) {
+    double m[5][10];
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 10; ++j) m[i][j] = j < 5 ? a[i * 5 + j] : (j - 5 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 5; ++c) {
+        int p = c;
+        for (int r = c + 1; r < 5; ++r)
+            if (std::fabs(m[r][c]) > std::fabs(m[p][c])) p = r;
+        if (!(std::fabs(m[p][c]) > 0.0)) throw Fail{GKS_EINVAL, "singular pivot block in the CLS matrix"};
+        if (p != c)
+            for (int j = 0; j < 10; ++j) std::swap(m[p][j], m[c][j]);
+        const double ip = 1.0 / m[c][c];
+        for (int j = 0; j < 10; ++j) m[c][j] *= ip;
+        for (int r = 0; r < 5; ++r)
+            if (r != c) {
+                const double f = m[r][c];
+                if (f != 0.0)
+                    for (int j = 0; j < 10; ++j) m[r][j] -= f * m[c][j];
+            }
+    }
+    Blk o;
+    for (int i = 0; i < 5; ++i)
+        for (int j = 0; j < 5; ++j) o[i * 5 + j] = m[i][j + 5];
+    return o;
+}
+
+// ------------------------------------------------------------------ geometry
+struct HostMesh {
+    int nt = 0, nf = 0;
+    std::vector<double> vx, vy;            // [nt][3] unwrapped vertex coordinates
+    std::vector<double> area, cx, cy, Ixx, Ixy, Iyy, h;
+    std::vector<int> own, nbr, loc, tag;   // faces
+    std::vector<double> nx, ny, S, gx, gy; // gx/gy [nf][2]
+    std::vector<int> kord;                 // reconstruction order k_i
+    std::vector<std::array<int, 3>> nb;    // interior neighbours per cell (face order), -1 padded
+    std::vector<std::array<int, 3>> cf;    // faces per cell (code f or ~f)
+    bool periodic[2] = {false, false};
+    double L[2] = {0, 0};
+
+    double mimg(double d, int ax) const {
+        if (periodic[ax]) d -= L[ax] * std::nearbyint(d / L[ax]);
+        return d;
+    }
+};
+
+void build_host_mesh(const gks_mesh_desc* de, const gks_params* prm, HostMesh& hm) {
+    const int nt = de->nt, nv = de->nv;
+    hm.nt = nt;
+    hm.periodic[0] = de->periodic_x != 0;
+    hm.periodic[1] = de->periodic_y != 0;
+    hm.L[0] = de->Lx;
+    hm.L[1] = de->Ly;
+    if ((hm.periodic[0] && !(de->Lx > 0)) || (hm.periodic[1] && !(de->Ly > 0)))
+        throw Fail{GKS_EINVAL, "periodic axis needs a positive period"};
+    hm.vx.resize(3 * (size_t)nt);
+    hm.vy.resize(3 * (size_t)nt);
+    hm.area.resize(nt);
+    hm.cx.resize(nt);
+    hm.cy.resize(nt);
+    hm.Ixx.resize(nt);
+    hm.Ixy.resize(nt);
+    hm.Iyy.resize(nt);
+    hm.h.resize(nt);
+    for (int t = 0; t < nt; ++t) {
+        int v[3];
+        for (int k = 0; k < 3; ++k) {
+            v[k] = de->tri[3 * (size_t)t + k];
+            if (v[k] < 0 || v[k] >= nv) throw Fail{GKS_EINVAL, "triangle vertex index out of range"};
+        }
+        if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) throw Fail{GKS_EINVAL, "degenerate triangle"};
+        const double x0 = de->xy[2 * (size_t)v[0]], y0 = de->xy[2 * (size_t)v[0] + 1];
+        double xs[3], ys[3];
+        for (int k = 0; k < 3; ++k) {
+            xs[k] = x0 + hm.mimg(de->xy[2 * (size_t)v[k]] - x0, 0);
+            ys[k] = y0 + hm.mimg(de->xy[2 * (size_t)v[k] + 1] - y0, 1);
+            hm.vx[3 * (size_t)t + k] = xs[k];
+            hm.vy[3 * (size_t)t + k] = ys[k];
+        }
+        const double a = 0.5 * ((xs[1] - xs[0]) * (ys[2] - ys[0]) - (xs[2] - xs[0]) * (ys[1] - ys[0]));
+        if (!(a > 0.0)) throw Fail{GKS_EINVAL, "triangle " + std::to_string(t) + " is clockwise or degenerate"};
+        const double cx = (xs[0] + xs[1] + xs[2]) / 3.0, cy = (ys[0] + ys[1] + ys[2]) / 3.0;
+        double ixx = 0, ixy = 0, iyy = 0;
+        for (int k = 0; k < 3; ++k) {
+            ixx += (xs[k] - cx) * (xs[k] - cx);
+            ixy += (xs[k] - cx) * (ys[k] - cy);
+            iyy += (ys[k] - cy) * (ys[k] - cy);
+        }
+        const double la = std::hypot(xs[1] - xs[0], ys[1] - ys[0]);
+        const double lb = std::hypot(xs[2] - xs[1], ys[2] - ys[1]);
+        const double lc = std::hypot(xs[0] - xs[2], ys[0] - ys[2]);
+        const double rad = la * lb * lc / (4.0 * a);
+        hm.area[t] = a;
+        hm.cx[t] = cx;
+        hm.cy[t] = cy;
+        hm.Ixx[t] = ixx / 12.0;
+        hm.Ixy[t] = ixy / 12.0;
+        hm.Iyy[t] = iyy / 12.0;
+        hm.h[t] = std::max(rad, std::sqrt(a));
+    }
+
+    // edges -> neighbours
+    struct E {
+        int64_t key;
+        int t, e;
+    };
+    std::vector<E> edges(3 * (size_t)nt);
+    for (int t = 0; t < nt; ++t)
+        for (int e = 0; e < 3; ++e) {
+            int a = de->tri[3 * (size_t)t + e], b = de->tri[3 * (size_t)t + (e + 1) % 3];
+            if (a > b) std::swap(a, b);
+            edges[3 * (size_t)t + e] = {(int64_t)a * nv + b, t, e};
+        }
+    std::sort(edges.begin(), edges.end(), [](const E& p, const E& q) {
+        return p.key < q.key || (p.key == q.key && (p.t < q.t || (p.t == q.t && p.e < q.e)));
+    });
+    std::vector<int> across(3 * (size_t)nt, -1);
+    for (size_t i = 0; i < edges.size();) {
+        size_t j = i;
+        while (j < edges.size() && edges[j].key == edges[i].key) ++j;
+        if (j - i > 2) throw Fail{GKS_EINVAL, "non-manifold edge"};
+        if (j - i == 2) {
+            if (edges[i].t == edges[i + 1].t) throw Fail{GKS_EINVAL, "triangle shares an edge with itself"};
+            across[3 * (size_t)edges[i].t + edges[i].e] = edges[i + 1].t;
+            across[3 * (size_t)edges[i + 1].t + edges[i + 1].e] = edges[i].t;
+        }
+        i = j;
+    }
+    hm.nb.assign(nt, {-1, -1, -1});
+    hm.cf.assign(nt, {0, 0, 0});
+    std::vector<int> ncf(nt, 0), nnb(nt, 0);
+    for (int t = 0; t < nt; ++t)
+        for (int e = 0; e < 3; ++e) {
+            const int o = across[3 * (size_t)t + e];
+            if (o >= 0 && o < t) continue;
+            int tg = 0;
+            if (o < 0) {
+                tg = de->edge_tag ? de->edge_tag[3 * (size_t)t + e] : 0;
+                if (tg <= 0 || tg > de->n_bc) throw Fail{GKS_EINVAL, "open edge without a valid boundary tag"};
+            }
+            const int f = (int)hm.own.size();
+            hm.own.push_back(t);
+            hm.nbr.push_back(o);
+            hm.loc.push_back(e);
+            hm.tag.push_back(tg);
+            hm.cf[t][ncf[t]++] = f;
+            if (o >= 0) {
+                hm.cf[o][ncf[o]++] = ~f;
+                hm.nb[t][nnb[t]++] = o;
+                hm.nb[o][nnb[o]++] = t;
+            }
+        }
+    hm.nf = (int)hm.own.size();
+    for (int t = 0; t < nt; ++t)
+        if (ncf[t] != 3) throw Fail{GKS_EINVAL, "cell without three faces"};
+    const int nf = hm.nf;
+    hm.nx.resize(nf);
+    hm.ny.resize(nf);
+    hm.S.resize(nf);
+    hm.gx.resize(2 * (size_t)nf);
+    hm.gy.resize(2 * (size_t)nf);
+    const double r3 = 1.0 / (2.0 * std::sqrt(3.0));
+    for (int f = 0; f < nf; ++f) {
+        const int t = hm.own[f], e = hm.loc[f];
+        const double ax = hm.vx[3 * (size_t)t + e], ay = hm.vy[3 * (size_t)t + e];
+        const double bx = hm.vx[3 * (size_t)t + (e + 1) % 3], by = hm.vy[3 * (size_t)t + (e + 1) % 3];
+        const double dx = bx - ax, dy = by - ay;
+        const double s = std::hypot(dx, dy);
+        hm.S[f] = s;
+        hm.nx[f] = dy / s;
+        hm.ny[f] = -dx / s;
+        const double mx = 0.5 * (ax + bx), my = 0.5 * (ay + by);
+        hm.gx[2 * (size_t)f] = mx - dx * r3;
+        hm.gy[2 * (size_t)f] = my - dy * r3;
+        hm.gx[2 * (size_t)f + 1] = mx + dx * r3;
+        hm.gy[2 * (size_t)f + 1] = my + dy * r3;
+    }
+    hm.kord.assign(nt, 2);
+    if (!prm->all_quadratic)
+        for (int f = 0; f < nf; ++f)
+            if (hm.nbr[f] < 0) hm.kord[hm.own[f]] = 1;
+}
+
+// ------------------------------------------------------------------ CLS normal equations
+// Per ordered neighbour pair (i, j): the weighted rows of Eqs. A:B:b:2-3.
+void pair_blocks(const HostMesh& hm, int i, int j, double w, double A[6][5], double B[6][5]) {
+    const double hi = hm.h[i], hj = hm.h[j];
+    const double dx = hm.mimg(hm.cx[j] - hm.cx[i], 0) / hi;
+    const double dy = hm.mimg(hm.cy[j] - hm.cy[i], 1) / hi;
+    const double r = hi / hj, ih2 = 1.0 / (hi * hi);
+    for (int a = 0; a < 6; ++a)
+        for (int b = 0; b < 5; ++b) A[a][b] = B[a][b] = 0.0;
+    // p = 0: cell-j means of the zero-mean basis of cell i
+    A[0][0] = dx;
+    A[0][1] = dy;
+    A[0][2] = 0.5 * (dx * dx + (hm.Ixx[j] - hm.Ixx[i]) * ih2);
+    A[0][3] = dx * dy + (hm.Ixy[j] - hm.Ixy[i]) * ih2;
+    A[0][4] = 0.5 * (dy * dy + (hm.Iyy[j] - hm.Iyy[i]) * ih2);
+    // p = 1, weight w h_i
+    A[1][0] = w;
+    A[1][2] = w * dx;
+    A[1][3] = w * dy;
+    A[2][1] = w;
+    A[2][3] = w * dx;
+    A[2][4] = w * dy;
+    B[1][0] = w * r;
+    B[2][1] = w * r;
+    // p = 2, weight (w h_i)^2
+    for (int q = 0; q < 3; ++q) {
+        A[3 + q][2 + q] = w * w;
+        B[3 + q][2 + q] = w * w * r * r;
+    }
+    if (hm.kord[i] == 1) {
+        for (int a = 3; a < 6; ++a)
+            for (int b = 0; b < 5; ++b) A[a][b] = B[a][b] = 0.0;
+        for (int a = 0; a < 6; ++a)
+            for (int b = 2; b < 5; ++b) A[a][b] = 0.0;
+    }
+    if (hm.kord[j] == 1)
+        for (int a = 0; a < 6; ++a)
+            for (int b = 2; b < 5; ++b) B[a][b] = 0.0;
+}
+
+Blk atb(const double A[6][5], const double B[6][5], double s) {
+    Blk o = bzero();
+    for (int k = 0; k < 5; ++k)
+        for (int l = 0; l < 5; ++l) {
+            double v = 0.0;
+            for (int r = 0; r < 6; ++r) v += A[r][k] * B[r][l];
+            o[k * 5 + l] = s * v;
+        }
+    return o;
+}
+
+struct Assembly {
+    std::vector<Blk> diag;                    // [nt]
+    std::vector<std::array<Blk, 3>> off;      // [nt][slot] block K_{i, nb[i][slot]}
+    std::vector<std::array<std::array<double, 5>, 3>> a0;  // [nt][slot]
+};
+
+void assemble(const HostMesh& hm, double w, Assembly& as) {
+    const int nt = hm.nt;
+    as.diag.assign(nt, bzero());
+    as.off.assign(nt, {bzero(), bzero(), bzero()});
+    as.a0.assign(nt, {});
+    for (int i = 0; i < nt; ++i)
+        for (int s = 0; s < 3; ++s) as.a0[i][s].fill(0.0);
+    auto slot_of = [&](int i, int j) {
+        for (int s = 0; s < 3; ++s)
+            if (hm.nb[i][s] == j) return s;
+        return -1;
+    };
+    for (int i = 0; i < nt; ++i)
+        for (int s = 0; s < 3; ++s) {
+            const int j = hm.nb[i][s];
+            if (j < 0) continue;
+            double A[6][5], B[6][5];
+            pair_blocks(hm, i, j, w, A, B);
+            const Blk AtA = atb(A, A, 1.0), AtB = atb(A, B, 1.0), BtB = atb(B, B, 1.0);
+            const int sj = slot_of(j, i);
+            for (int e = 0; e < 25; ++e) {
+                as.diag[i][e] += AtA[e];
+                as.off[i][s][e] -= AtB[e];
+                as.diag[j][e] += BtB[e];
+            }
+            // K_ji -= B^T A = (A^T B)^T
+            for (int k = 0; k < 5; ++k)
+                for (int l = 0; l < 5; ++l) as.off[j][sj][k * 5 + l] -= AtB[l * 5 + k];
+            for (int l = 0; l < 5; ++l) as.a0[i][s][l] = A[0][l];
+        }
+    for (int i = 0; i < nt; ++i)
+        if (hm.kord[i] == 1)
+            for (int l = 2; l < 5; ++l) as.diag[i][l * 5 + l] += 1.0;
+}
+
+// ------------------------------------------------------------------ orderings
+std::vector<int> rcm_order(const HostMesh& hm) {
+    const int nt = hm.nt;
+    std::vector<int> deg(nt);
+    for (int i = 0; i < nt; ++i) {
+        int d = 0;
+        for (int s = 0; s < 3; ++s) d += hm.nb[i][s] >= 0;
+        deg[i] = d;
+    }
+    auto less = [&](int a, int b) { return deg[a] < deg[b] || (deg[a] == deg[b] && a < b); };
+    std::vector<int> dist(nt, -1), q;
+    q.reserve(nt);
+    // breadth-first level structure of the component of root (left in q/dist);
+    // returns the eccentricity of root
+    auto bfs = [&](int root) {
+        q.clear();
+        q.push_back(root);
+        dist[root] = 0;
+        int ecc = 0;
+        for (size_t p = 0; p < q.size(); ++p) {
+            const int u = q[p];
+            for (int s = 0; s < 3; ++s) {
+                const int v = hm.nb[u][s];
+                if (v >= 0 && dist[v] < 0) {
+                    dist[v] = dist[u] + 1;
+                    ecc = std::max(ecc, dist[v]);
+                    q.push_back(v);
+                }
+            }
+        }
+        return ecc;
+    };
+    auto reset = [&]() {
+        for (int u : q) dist[u] = -1;
+    };
+    std::vector<char> seen(nt, 0);
+    std::vector<int> order;
+    order.reserve(nt);
+    for (int start = 0; start < nt; ++start) {
+        if (seen[start]) continue;
+        // George-Liu pseudo-peripheral node: start from a minimum-degree node
+        // and move to the minimum-degree node of the last level while the
+        // eccentricity grows
+        bfs(start);
+        int root = start;
+        for (int u : q)
+            if (less(u, root)) root = u;
+        reset();
+        int ecc = bfs(root);
+        for (int it = 0; it < 32; ++it) {
+            int cand = -1;
+            for (int u : q)
+                if (dist[u] == ecc && (cand < 0 || less(u, cand))) cand = u;
+            reset();
+            const int e2 = bfs(cand);
+            if (e2 > ecc) {
+                root = cand;
+                ecc = e2;
+            } else {
+                break;
+            }
+        }
+        reset();
+        // Cuthill-McKee: breadth first, unvisited neighbours by (degree, index)
+        const size_t base = order.size();
+        order.push_back(root);
+        seen[root] = 1;
+        for (size_t p = base; p < order.size(); ++p) {
+            const int u = order[p];
+            int cand[3], nc = 0;
+            for (int s = 0; s < 3; ++s) {
+                const int v = hm.nb[u][s];
+                if (v >= 0 && !seen[v]) cand[nc++] = v;
+            }
+            std::sort(cand, cand + nc, less);
+            for (int k = 0; k < nc; ++k) {
+                seen[cand[k]] = 1;
+                order.push_back(cand[k]);
+            }
+        }
+    }
+    std::reverse(order.begin(), order.end());
+    return order;
+}
+
+// ------------------------------------------------------------------ device helpers
+template <typename T>
+T* dev_upload(gks_mesh* m, const std::vector<T>& h) {
+    T* p = nullptr;
+    const size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+    hipError_t e = hipMalloc((void**)&p, bytes);
+    if (e != hipSuccess) throw Fail{GKS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    m->allocs.push_back(p);
+    m->dev_bytes += (int64_t)bytes;
+    if (!h.empty()) HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    return p;
+}
+
+template <typename T>
+T* dev_alloc(gks_mesh* m, size_t count) {
+    T* p = nullptr;
+    const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+    hipError_t e = hipMalloc((void**)&p, bytes);
+    if (e != hipSuccess) throw Fail{GKS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+    m->allocs.push_back(p);
+    m->dev_bytes += (int64_t)bytes;
+    HIPCHK(hipMemset(p, 0, bytes));
+    return p;
+}
+
+// Everything the device needs, built on the host (no HIP calls).
+struct HostSystem {
+    HostMesh hm;
+    std::vector<int> perm;                        // solver order -> cell
+    std::vector<int32_t> lev_ptr;
+    int n_levels = 0, n_colors = 0, rcm_bw = 0, nfb = 0;
+    std::vector<double> Kval, a0, Lval, Uval, Dv;
+    std::vector<int32_t> Kcol, rnb, Lcol, Ucol;
+    std::vector<int32_t> own, nbr, cface, bck;
+    std::vector<double> fgeo, gpd, cgeo, bcs;
+};
+
+std::vector<float> to32(const std::vector<double>& v) {
+    std::vector<float> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
+    return o;
+}
+
+void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S) {
+    HostMesh& hm = S.hm;
+    build_host_mesh(de, &prm, hm);
+    const int nt = hm.nt, nf = hm.nf;
+    Assembly as;
+    assemble(hm, prm.cls_w, as);
+
+    // renumbering
+    const std::vector<int> rcm = rcm_order(hm);
+    std::vector<int> pos(nt);
+    for (int p = 0; p < nt; ++p) pos[rcm[p]] = p;
+    int bw = 0;
+    for (int i = 0; i < nt; ++i)
+        for (int s = 0; s < 3; ++s)
+            if (hm.nb[i][s] >= 0) bw = std::max(bw, std::abs(pos[i] - pos[hm.nb[i][s]]));
+    S.rcm_bw = bw;
+    std::vector<int> key(nt, 0);
+    int nkeys = 0;
+    if (prm.ordering == GKS_ORDER_RCM) {
+        // dependency level of each row of the lower factor in RCM order
+        for (int p = 0; p < nt; ++p) {
+            const int i = rcm[p];
+            int lv = 0;
+            for (int s = 0; s < 3; ++s) {
+                const int j = hm.nb[i][s];
+                if (j >= 0 && pos[j] < p) lv = std::max(lv, key[j] + 1);
+            }
+            key[i] = lv;
+            nkeys = std::max(nkeys, lv + 1);
+        }
+        S.n_colors = 0;
+    } else {
+        std::vector<int> col(nt, -1);
+        for (int p = 0; p < nt; ++p) {
+            const int i = rcm[p];
+            bool used[4] = {false, false, false, false};
+            for (int s = 0; s < 3; ++s) {
+                const int j = hm.nb[i][s];
+                if (j >= 0 && col[j] >= 0) used[col[j]] = true;
+            }
+            int c = 0;
+            while (used[c]) ++c;
+            col[i] = c;
+            nkeys = std::max(nkeys, c + 1);
+        }
+        key = col;
+        S.n_colors = nkeys;
+    }
+    std::vector<int>& perm = S.perm;
+    perm = rcm;  // new -> old
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::vector<int> iperm(nt);
+    for (int p = 0; p < nt; ++p) iperm[perm[p]] = p;
+    S.lev_ptr.assign(nkeys + 1, 0);
+    for (int i = 0; i < nt; ++i) S.lev_ptr[key[i] + 1]++;
+    for (int l = 0; l < nkeys; ++l) S.lev_ptr[l + 1] += S.lev_ptr[l];
+    S.n_levels = nkeys;
+
+    // matrix in solver order: slot 0 diagonal, then neighbours, padded with the dummy row
+    const int n = nt;
+    std::vector<double>& Kval = S.Kval;
+    Kval.assign((size_t)KW * 25 * n, 0.0);
+    std::vector<int32_t>& Kcol = S.Kcol;
+    Kcol.assign((size_t)KW * n, n);
+    std::vector<double>& a0 = S.a0;
+    a0.assign((size_t)3 * 5 * n, 0.0);
+    std::vector<int32_t>& rnb = S.rnb;
+    rnb.assign((size_t)3 * n, 0);
+    for (int i = 0; i < n; ++i) {
+        const int o = perm[i];
+        Kcol[i] = i;
+        for (int e = 0; e < 25; ++e) Kval[(size_t)e * n + i] = as.diag[o][e];
+        for (int s = 0; s < 3; ++s) {
+            const int j = hm.nb[o][s];
+            rnb[(size_t)s * n + i] = j >= 0 ? j : o;
+            if (j < 0) continue;
+            Kcol[(size_t)(s + 1) * n + i] = iperm[j];
+            for (int e = 0; e < 25; ++e) Kval[((size_t)(s + 1) * 25 + e) * n + i] = as.off[o][s][e];
+            for (int l = 0; l < 5; ++l) a0[((size_t)s * 5 + l) * n + i] = as.a0[o][s][l];
+        }
+    }
+
+    // BILU(0) in solver order (row-wise IKJ elimination restricted to the pattern)
+    struct Row {
+        int nz;
+        int col[4];
+        Blk v[4];
+    };
+    std::vector<Row> rows(n);
+    for (int i = 0; i < n; ++i) {
+        Row& r = rows[i];
+        r.nz = 0;
+        for (int s = 0; s < KW; ++s) {
+            const int c = Kcol[(size_t)s * n + i];
+            if (c == n) continue;
+            r.col[r.nz] = c;
+            for (int e = 0; e < 25; ++e) r.v[r.nz][e] = Kval[((size_t)s * 25 + e) * n + i];
+            r.nz++;
+        }
+        // sort by column
+        for (int a = 1; a < r.nz; ++a)
+            for (int b = a; b > 0 && r.col[b - 1] > r.col[b]; --b) {
+                std::swap(r.col[b - 1], r.col[b]);
+                std::swap(r.v[b - 1], r.v[b]);
+            }
+    }
+    std::vector<Blk> dinv(n);
+    for (int i = 0; i < n; ++i) {
+        Row& r = rows[i];
+        for (int a = 0; a < r.nz && r.col[a] < i; ++a) {
+            const int k = r.col[a];
+            r.v[a] = bmul(r.v[a], dinv[k]);  // L_ik = A_ik U_kk^{-1}
+            const Row& rk = rows[k];
+            for (int b = 0; b < r.nz; ++b) {
+                const int j = r.col[b];
+                if (j <= k) continue;
+                for (int q = 0; q < rk.nz; ++q)
+                    if (rk.col[q] == j) {
+                        const Blk t = bmul(r.v[a], rk.v[q]);
+                        for (int e = 0; e < 25; ++e) r.v[b][e] -= t[e];
+                    }
+            }
+        }
+        int dpos = -1;
+        for (int a = 0; a < r.nz; ++a)
+            if (r.col[a] == i) dpos = a;
+        dinv[i] = binv(r.v[dpos]);
+    }
+    std::vector<double>& Lval = S.Lval;
+    std::vector<double>& Uval = S.Uval;
+    std::vector<double>& Dv = S.Dv;
+    std::vector<int32_t>& Lcol = S.Lcol;
+    std::vector<int32_t>& Ucol = S.Ucol;
+    Lval.assign((size_t)LW * 25 * n, 0.0);
+    Uval.assign((size_t)LW * 25 * n, 0.0);
+    Dv.assign((size_t)25 * n, 0.0);
+    Lcol.assign((size_t)LW * n, n);
+    Ucol.assign((size_t)LW * n, n);
+    for (int i = 0; i < n; ++i) {
+        const Row& r = rows[i];
+        int nl = 0, nu = 0;
+        for (int a = 0; a < r.nz; ++a) {
+            const int c = r.col[a];
+            if (c < i) {
+                Lcol[(size_t)nl * n + i] = c;
+                for (int e = 0; e < 25; ++e) Lval[((size_t)nl * 25 + e) * n + i] = r.v[a][e];
+                ++nl;
+            } else if (c > i) {
+                Ucol[(size_t)nu * n + i] = c;
+                for (int e = 0; e < 25; ++e) Uval[((size_t)nu * 25 + e) * n + i] = r.v[a][e];
+                ++nu;
+            }
+        }
+        for (int e = 0; e < 25; ++e) Dv[(size_t)e * n + i] = dinv[i][e];
+    }
+    // ---- face / cell arrays in device layout
+    std::vector<int32_t>& own = S.own;
+    std::vector<int32_t>& nbr = S.nbr;
+    std::vector<double>& fgeo = S.fgeo;
+    std::vector<double>& gpd = S.gpd;
+    own.assign(nf, 0);
+    nbr.assign(nf, 0);
+    fgeo.assign(3 * (size_t)nf, 0.0);
+    gpd.assign(8 * (size_t)nf, 0.0);
+    int nfb = 0;
+    for (int f = 0; f < nf; ++f) {
+        own[f] = hm.own[f];
+        nbr[f] = hm.nbr[f] >= 0 ? hm.nbr[f] : -hm.tag[f];
+        nfb += hm.nbr[f] < 0;
+        fgeo[f] = hm.nx[f];
+        fgeo[(size_t)nf + f] = hm.ny[f];
+        fgeo[2 * (size_t)nf + f] = hm.S[f];
+        for (int g = 0; g < 2; ++g) {
+            const double px = hm.gx[2 * (size_t)f + g], py = hm.gy[2 * (size_t)f + g];
+            const int o = hm.own[f];
+            gpd[(size_t)(4 * g + 0) * nf + f] = hm.mimg(px - hm.cx[o], 0) / hm.h[o];
+            gpd[(size_t)(4 * g + 1) * nf + f] = hm.mimg(py - hm.cy[o], 1) / hm.h[o];
+            const int b = hm.nbr[f];
+            if (b >= 0) {
+                gpd[(size_t)(4 * g + 2) * nf + f] = hm.mimg(px - hm.cx[b], 0) / hm.h[b];
+                gpd[(size_t)(4 * g + 3) * nf + f] = hm.mimg(py - hm.cy[b], 1) / hm.h[b];
+            }
+        }
+    }
+    S.nfb = nfb;
+    std::vector<double>& cgeo = S.cgeo;
+    std::vector<int32_t>& cface = S.cface;
+    cgeo.assign(4 * (size_t)nt, 0.0);
+    cface.assign(3 * (size_t)nt, 0);
+    for (int t = 0; t < nt; ++t) {
+        const double h = hm.h[t];
+        cgeo[t] = 1.0 / h;
+        cgeo[(size_t)nt + t] = hm.Ixx[t] / (h * h);
+        cgeo[2 * (size_t)nt + t] = hm.Ixy[t] / (h * h);
+        cgeo[3 * (size_t)nt + t] = hm.Iyy[t] / (h * h);
+        for (int k = 0; k < 3; ++k) cface[(size_t)k * nt + t] = hm.cf[t][k];
+    }
+    std::vector<int32_t>& bck = S.bck;
+    std::vector<double>& bcs = S.bcs;
+    bck.assign(de->n_bc + 1, 0);
+    bcs.assign(4 * (size_t)(de->n_bc + 1), 0.0);
+    for (int r = 0; r < de->n_bc; ++r) {
+        const int k = de->bc_kind[r];
+        if (k < GKS_BC_SLIP || k > GKS_BC_OUTFLOW) throw Fail{GKS_EINVAL, "unknown boundary kind"};
+        bck[r + 1] = k;
+        for (int q = 0; q < 4; ++q) bcs[4 * (size_t)(r + 1) + q] = de->bc_state ? de->bc_state[4 * (size_t)r + q] : 0.0;
+        if (k == GKS_BC_INFLOW && !(bcs[4 * (size_t)(r + 1)] > 0 && bcs[4 * (size_t)(r + 1) + 3] > 0))
+            throw Fail{GKS_EINVAL, "inflow state must have positive density and pressure"};
+    }
+}
+
+void setup(gks_mesh* m, const gks_mesh_desc* de) {
+    const gks_params& prm = m->prm;
+    HostSystem S;
+    build_system(de, prm, S);
+    const HostMesh& hm = S.hm;
+    const int nt = hm.nt, nf = hm.nf, n = nt;
+    m->rcm_bw = S.rcm_bw;
+    m->n_colors = S.n_colors;
+    m->n_levels = S.n_levels;
+    m->h_own = S.own;
+    m->h_nbr = S.nbr;
+    DevMesh& d = m->d;
+    d.nt = nt;
+    d.nf = nf;
+    d.n = n;
+    d.nfb = S.nfb;
+    d.lev_ptr = S.lev_ptr;
+    d.n_bc = de->n_bc;
+    d.own = dev_upload(m, S.own);
+    d.nbr = dev_upload(m, S.nbr);
+    d.fgeo = dev_upload(m, S.fgeo);
+    d.gpd = dev_upload(m, S.gpd);
+    d.area = dev_upload(m, hm.area);
+    d.cgeo = dev_upload(m, S.cgeo);
+    d.cface = dev_upload(m, S.cface);
+    d.bc_kind = dev_upload(m, S.bck);
+    d.bc_state = dev_upload(m, S.bcs);
+    std::vector<int32_t> permv(S.perm.begin(), S.perm.end());
+    d.perm = dev_upload(m, permv);
+    d.rnb = dev_upload(m, S.rnb);
+    d.a0 = dev_upload(m, S.a0);
+    d.Kval = dev_upload(m, S.Kval);
+    d.Kcol = dev_upload(m, S.Kcol);
+    d.Lval = dev_upload(m, S.Lval);
+    d.Lcol = dev_upload(m, S.Lcol);
+    d.Uval = dev_upload(m, S.Uval);
+    d.Ucol = dev_upload(m, S.Ucol);
+    d.Dinv = dev_upload(m, S.Dv);
+    if (prm.precision == GKS_MIXED) {
+        d.Kval32 = dev_upload(m, to32(S.Kval));
+        d.Lval32 = dev_upload(m, to32(S.Lval));
+        d.Uval32 = dev_upload(m, to32(S.Uval));
+        d.Dinv32 = dev_upload(m, to32(S.Dv));
+    }
+
+    // ---- work space
+    Work& w = m->w;
+    const size_t vec = (size_t)(n + 1) * CB;
+    const int mres = prm.restart;
+    w.X = dev_alloc<double>(m, vec);
+    w.R = dev_alloc<double>(m, vec);
+    w.V = dev_alloc<double>(m, vec * (mres + 1));
+    if (prm.precision == GKS_MIXED) w.Z = dev_alloc<double>(m, vec * mres);
+    w.w = dev_alloc<double>(m, vec);
+    w.t1 = dev_alloc<double>(m, vec);
+    w.t2 = dev_alloc<double>(m, vec);
+    w.t3 = dev_alloc<double>(m, vec);
+    w.nblk_red = std::max(1, std::min(1024, (n + 255) / 256));
+    w.partial = dev_alloc<double>(m, (size_t)w.nblk_red * (MAXM + 1) * NC);
+    {
+        std::vector<double> ones((size_t)(MAXM + 1) * NC, 1.0);
+        w.ones = dev_upload(m, ones);
+    }
+    w.ks = dev_alloc<KrylovState>(m, 1);
+    w.Xcell = dev_alloc<double>(m, (size_t)20 * nt);
+    w.F = dev_alloc<double>(m, (size_t)4 * nf);
+    w.Wn = dev_alloc<double>(m, (size_t)4 * nt);
+    w.dt_dev = dev_alloc<double>(m, 1);
+    w.dtpart = dev_alloc<double>(m, 1024);
+    w.counters = (int32_t*)dev_alloc<double>(m, 2);
+    HIPCHK(hipHostMalloc((void**)&w.st_host, sizeof(Status), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&w.counters_host, 4 * sizeof(int32_t), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&w.scal_host, 4 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipMemcpy(&w.ks->tol, &prm.tol, sizeof(double), hipMemcpyHostToDevice));
+    HIPCHK(hipDeviceSynchronize());
+}
+
+// ------------------------------------------------------------------ GMRES driver (FP64)
+void read_status(gks_mesh* m) {
+    HIPCHK(hipMemcpyAsync(m->w.st_host, &m->w.ks->st, sizeof(Status), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+}
+
+bool all_conv(const Status* s) {
+    for (int c = 0; c < NC; ++c)
+        if (!s->conv[c]) return false;
+    return true;
+}
+
+// Right-preconditioned restarted GMRES on the four columns in lockstep.
+// Returns GKS_OK or GKS_ENOCONV; fills info.
+int solve_gmres(gks_mesh* m, gks_solve_info* info) {
+    Work& w = m->w;
+    KrylovState* ks = w.ks;
+    const int n = m->d.n;
+    const int64_t vs = (int64_t)(n + 1) * CB;
+    const int mres = m->prm.restart;
+    int iters[NC] = {0, 0, 0, 0};
+    int cycles = 0, total = 0;
+
+    launch_dots_reduce(m, KC_DOTS, w.R, 0, 1, w.R, nullptr, ks->sq);
+    launch_ctl(m, 0);
+    launch_mask_cols(m, w.X);
+    int status = GKS_ENOCONV;
+    for (;;) {
+        launch_resid(m, w.X, w.R, w.V);
+        launch_dots_reduce(m, KC_DOTS, w.V, 0, 1, w.V, nullptr, ks->sq);
+        launch_ctl(m, 1);
+        read_status(m);
+        if (all_conv(w.st_host)) {
+            status = GKS_OK;
+            break;
+        }
+        if (total >= m->prm.max_iter) break;
+        ++cycles;
+        int k = 0;
+        while (k < mres && total < m->prm.max_iter) {
+            double* vk = w.V + (int64_t)k * vs;
+            double* vk1 = w.V + (int64_t)(k + 1) * vs;
+            launch_ilu(m, vk, &ks->scale[k][0], w.t1, w.t2, false);
+            launch_spmv64(m, w.t2, nullptr, w.w);
+            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0]);
+            launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w);
+            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0]);
+            launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1);
+            launch_dots_reduce(m, KC_DOTS, vk1, 0, 1, vk1, nullptr, ks->sq);
+            launch_ctl(m, 2);
+            ++k;
+            ++total;
+            read_status(m);
+            for (int c = 0; c < NC; ++c)
+                if (!w.st_host->conv[c]) iters[c] = total;
+            if (all_conv(w.st_host)) break;
+        }
+        launch_ctl(m, 3);
+        launch_combine(m, w.V, vs, k, &ks->y[0][0], &ks->scale[0][0], w.t1);
+        launch_ilu(m, w.t1, nullptr, w.t2, w.t3, false);
+        launch_acc(m, w.X, w.t3);
+    }
+    if (info) {
+        for (int c = 0; c < NC; ++c) {
+            info->iters[c] = iters[c];
+            info->restarts[c] = cycles;
+            const double bn = w.st_host->bnorm[c];
+            info->rel_resid[c] = bn > 0.0 ? w.st_host->beta[c] / bn : 0.0;
+        }
+    }
+    return status;
+}
+
+// Mixed precision: flexible GMRES in FP64 (Arnoldi with CGS2, Givens, true
+// residual with the FP64 matrix) preconditioned by q = inner_iters sweeps of
+// BILU(0)-preconditioned Richardson iteration on the FP32 copies of K and of
+// the factors:  z = M^-1 v;  z += M^-1 (v - K z)  (q - 1 times).
+int solve_fgmres_mixed(gks_mesh* m, gks_solve_info* info) {
+    Work& w = m->w;
+    KrylovState* ks = w.ks;
+    const int n = m->d.n;
+    const int64_t vs = (int64_t)(n + 1) * CB;
+    const int mres = m->prm.restart;
+    const int q = m->prm.inner_iters;
+    int iters[NC] = {0, 0, 0, 0};
+    int cycles = 0, total = 0;
+
+    launch_dots_reduce(m, KC_DOTS, w.R, 0, 1, w.R, nullptr, ks->sq);
+    launch_ctl(m, 0);
+    launch_mask_cols(m, w.X);
+    int status = GKS_ENOCONV;
+    for (;;) {
+        launch_resid(m, w.X, w.R, w.V);
+        launch_dots_reduce(m, KC_DOTS, w.V, 0, 1, w.V, nullptr, ks->sq);
+        launch_ctl(m, 1);
+        read_status(m);
+        if (all_conv(w.st_host)) {
+            status = GKS_OK;
+            break;
+        }
+        if (total >= m->prm.max_iter) break;
+        ++cycles;
+        int k = 0;
+        while (k < mres && total < m->prm.max_iter) {
+            double* vk = w.V + (int64_t)k * vs;
+            double* vk1 = w.V + (int64_t)(k + 1) * vs;
+            double* zk = w.Z + (int64_t)k * vs;
+            const double* sk = &ks->scale[k][0];
+            launch_ilu(m, vk, sk, w.t1, zk, true);
+            for (int j = 1; j < q; ++j) {
+                launch_resid32(m, zk, vk, sk, w.t3);
+                launch_ilu(m, w.t3, nullptr, w.t1, w.t2, true);
+                launch_acc(m, zk, w.t2);
+            }
+            launch_spmv64(m, zk, nullptr, w.w);
+            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0]);
+            launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w);
+            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0]);
+            launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1);
+            launch_dots_reduce(m, KC_DOTS, vk1, 0, 1, vk1, nullptr, ks->sq);
+            launch_ctl(m, 2);
+            ++k;
+            ++total;
+            read_status(m);
+            for (int c = 0; c < NC; ++c)
+                if (!w.st_host->conv[c]) iters[c] = total;
+            if (all_conv(w.st_host)) break;
+        }
+        launch_ctl(m, 3);
+        launch_combine(m, w.Z, vs, k, &ks->y[0][0], w.ones, w.t1);
+        launch_acc(m, w.X, w.t1);
+    }
+    if (info) {
+        for (int c = 0; c < NC; ++c) {
+            info->iters[c] = iters[c];
+            info->restarts[c] = cycles;
+            const double bn = w.st_host->bnorm[c];
+            info->rel_resid[c] = bn > 0.0 ? w.st_host->beta[c] / bn : 0.0;
+        }
+    }
+    return status;
+}
+
+int run_solve(gks_mesh* m, const double* W, gks_solve_info* info) {
+    launch_rhs(m, W);
+    if (m->prm.precision == GKS_MIXED) return solve_fgmres_mixed(m, info);
+    return solve_gmres(m, info);
+}
+
+void prof_collect(gks_mesh* m) {
+    if (m->prof.pending.empty()) return;
+    HIPCHK(hipStreamSynchronize(m->stream));
+    for (auto& p : m->prof.pending) {
+        float ms = 0.0f;
+        if (hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            m->prof.ms[p.first] += ms;
+            m->prof.launches[p.first] += 1;
+        }
+        m->prof.pool.push_back(p.second.first);
+        m->prof.pool.push_back(p.second.second);
+    }
+    m->prof.pending.clear();
+}
+
+bool params_ok(const gks_params& p) {
+    return p.gamma > 1.0 && p.cfl > 0.0 && p.tol > 0.0 && p.restart >= 1 && p.restart <= MAXM &&
+           p.max_iter >= 1 && p.mu >= 0.0 && p.tau_eps >= 0.0 && p.cls_w > 0.0 &&
+           (p.precision == GKS_FP64 || p.precision == GKS_MIXED) &&
+           (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1;
+}
+
+int fail(gks_mesh* m, const Fail& f) {
+    if (m) m->err = f.msg;
+    return f.code;
+}
+
+}  // namespace
+
+// ================================================================== C ABI
+
+extern "C" {
+
+void gks_params_default(gks_params* p) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->gamma = 1.4;
+    p->mu = 0.0;
+    p->tau_eps = 0.01;
+    p->cls_w = 0.3;
+    p->cfl = 0.5;
+    p->tol = 1e-10;
+    p->restart = 30;
+    p->max_iter = 500;
+    p->precision = GKS_FP64;
+    p->ordering = GKS_ORDER_MULTICOLOR;
+    p->inner_iters = 4;
+    p->exact_time = 0;
+    p->nonphys_fallback = 0;
+    p->all_quadratic = 0;
+}
+
+int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_stream, gks_mesh** out) {
+    if (out) *out = nullptr;
+    g_create_err.clear();
+    if (!desc || !out) {
+        g_create_err = "null descriptor or output pointer";
+        return GKS_EINVAL;
+    }
+    if (desc->nt <= 0 || desc->nv < 3 || !desc->xy || !desc->tri) {
+        g_create_err = "mesh needs nt > 0, nv >= 3 and vertex/triangle arrays";
+        return GKS_EINVAL;
+    }
+    if (desc->n_bc < 0 || (desc->n_bc > 0 && !desc->bc_kind)) {
+        g_create_err = "boundary table is inconsistent";
+        return GKS_EINVAL;
+    }
+    gks_params p;
+    if (prm)
+        p = *prm;
+    else
+        gks_params_default(&p);
+    if (!params_ok(p)) {
+        g_create_err = "invalid parameters";
+        return GKS_EINVAL;
+    }
+    gks_mesh* m = new (std::nothrow) gks_mesh();
+    if (!m) {
+        g_create_err = "out of host memory";
+        return GKS_ENOMEM;
+    }
+    m->prm = p;
+    m->stream = (hipStream_t)hip_stream;
+    try {
+        HIPCHK(hipGetDevice(&m->device));
+        setup(m, desc);
+    } catch (const Fail& f) {
+        g_create_err = f.msg;
+        const int code = f.code;
+        gks_destroy(m);
+        return code;
+    } catch (const std::bad_alloc&) {
+        g_create_err = "out of host memory";
+        gks_destroy(m);
+        return GKS_ENOMEM;
+    }
+    *out = m;
+    return GKS_OK;
+}
+
+int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info* info) {
+    if (!m) return GKS_EINVAL;
+    if (!W || !X || (const void*)W == (const void*)X) {
+        m->err = "null or aliased W / X";
+        return GKS_EINVAL;
+    }
+    try {
+        const int st = run_solve(m, W, info);
+        launch_copyout(m, m->w.X, X);
+        HIPCHK(hipStreamSynchronize(m->stream));
+        prof_collect(m);
+        if (info) info->nonphys = 0;
+        if (st != GKS_OK) m->err = "GMRES did not converge within max_iter";
+        return st;
+    } catch (const Fail& f) {
+        return fail(m, f);
+    }
+}
+
+int gks_flux(gks_mesh* m, const double* W, const double* X, double dt, double* F) {
+    if (!m) return GKS_EINVAL;
+    if (!W || !X || !F || !(dt > 0.0)) {
+        m->err = "gks_flux needs W, X, F and dt > 0";
+        return GKS_EINVAL;
+    }
+    try {
+        launch_set_scalar(m, m->w.dt_dev, dt);
+        launch_zero_i32(m, m->w.counters, 4);
+        launch_flux(m, W, X, m->w.dt_dev, F);
+        HIPCHK(hipMemcpyAsync(m->w.counters_host, m->w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+        prof_collect(m);
+        if (m->w.counters_host[0] > 0 && !m->prm.nonphys_fallback) {
+            m->err = "non-physical reconstructed state at " + std::to_string(m->w.counters_host[0]) + " Gauss points";
+            return GKS_ENONPHYS;
+        }
+        return GKS_OK;
+    } catch (const Fail& f) {
+        return fail(m, f);
+    }
+}
+
+int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info* info) {
+    if (!m) return GKS_EINVAL;
+    if (!W) {
+        m->err = "null W";
+        return GKS_EINVAL;
+    }
+    try {
+        Work& w = m->w;
+        if (dt > 0.0)
+            launch_set_scalar(m, w.dt_dev, dt);
+        else
+            launch_cfl(m, W, w.dt_dev);
+        launch_zero_i32(m, w.counters, 4);
+        const int st = run_solve(m, W, info);
+        if (st != GKS_OK) {
+            HIPCHK(hipStreamSynchronize(m->stream));
+            prof_collect(m);
+            m->err = "GMRES did not converge within max_iter";
+            return st;
+        }
+        launch_copyout(m, w.X, w.Xcell);
+        launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
+        launch_update(m, W, w.F, w.Wn);
+        HIPCHK(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(hipMemcpyAsync(w.scal_host, w.dt_dev, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+        if (info) info->nonphys = w.counters_host[0];
+        if (dt_used) *dt_used = w.scal_host[0];
+        if ((w.counters_host[0] > 0 && !m->prm.nonphys_fallback) || w.counters_host[1] > 0) {
+            prof_collect(m);
+            m->err = "non-physical state (" + std::to_string(w.counters_host[0]) + " Gauss points, " +
+                     std::to_string(w.counters_host[1]) + " updated cells)";
+            return GKS_ENONPHYS;
+        }
+        launch_copy(m, W, w.Wn, (int64_t)4 * m->d.nt);
+        HIPCHK(hipStreamSynchronize(m->stream));
+        prof_collect(m);
+        return GKS_OK;
+    } catch (const Fail& f) {
+        return fail(m, f);
+    }
+}
+
+int gks_faces(const gks_mesh* m, int32_t* own, int32_t* nbr) {
+    if (!m) return GKS_EINVAL;
+    const size_t nf = m->h_own.size();
+    if (own) std::memcpy(own, m->h_own.data(), nf * sizeof(int32_t));
+    if (nbr) std::memcpy(nbr, m->h_nbr.data(), nf * sizeof(int32_t));
+    return GKS_OK;
+}
+
+int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st) {
+    if (!m || !st) return GKS_EINVAL;
+    st->nt = m->d.nt;
+    st->nf = m->d.nf;
+    st->nf_boundary = m->d.nfb;
+    st->n_levels = m->n_levels;
+    st->n_colors = m->n_colors;
+    st->rcm_bandwidth = m->rcm_bw;
+    st->device_bytes = m->dev_bytes;
+    return GKS_OK;
+}
+
+int gks_profile_enable(gks_mesh* m, int enable) {
+    if (!m) return GKS_EINVAL;
+    try {
+        prof_collect(m);
+    } catch (const Fail& f) {
+        return fail(m, f);
+    }
+    if (enable) {
+        for (int i = 0; i < NPROF; ++i) {
+            m->prof.launches[i] = 0;
+            m->prof.ms[i] = 0.0;
+        }
+    }
+    m->prof.on = enable != 0;
+    return GKS_OK;
+}
+
+int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms) {
+    if (!m) return GKS_EINVAL;
+    try {
+        prof_collect(m);
+    } catch (const Fail& f) {
+        return fail(m, f);
+    }
+    const int k = std::min(n, (int)KC_COUNT);
+    for (int i = 0; i < k; ++i) {
+        if (names) names[i] = kc_names[i];
+        if (launches) launches[i] = m->prof.launches[i];
+        if (total_ms) total_ms[i] = m->prof.ms[i];
+    }
+    return k;
+}
+
+int gks_host_inspect(const gks_mesh_desc* desc, const gks_params* prm, gks_host_system* out) {
+    g_create_err.clear();
+    if (!desc || !out || desc->nt <= 0 || desc->nv < 3 || !desc->xy || !desc->tri) {
+        g_create_err = "invalid descriptor";
+        return GKS_EINVAL;
+    }
+    std::memset(out, 0, sizeof(*out));
+    gks_params p;
+    if (prm)
+        p = *prm;
+    else
+        gks_params_default(&p);
+    if (!params_ok(p)) {
+        g_create_err = "invalid parameters";
+        return GKS_EINVAL;
+    }
+    try {
+        HostSystem S;
+        build_system(desc, p, S);
+        const int nt = S.hm.nt, nf = S.hm.nf;
+        out->nt = nt;
+        out->nf = nf;
+        out->n_levels = S.n_levels;
+        out->n_colors = S.n_colors;
+        out->rcm_bandwidth = S.rcm_bw;
+        auto dup = [](const auto& v) {
+            using T = typename std::decay_t<decltype(v)>::value_type;
+            T* q = (T*)std::malloc(std::max<size_t>(1, v.size()) * sizeof(T));
+            if (!q) throw std::bad_alloc();
+            std::copy(v.begin(), v.end(), q);
+            return q;
+        };
+        std::vector<int32_t> perm(S.perm.begin(), S.perm.end());
+        out->own = dup(S.own);
+        out->nbr = dup(S.nbr);
+        out->area = dup(S.hm.area);
+        out->h = dup(S.hm.h);
+        out->perm = dup(perm);
+        out->lev_ptr = dup(S.lev_ptr);
+        out->kcol = dup(S.Kcol);
+        out->kval = dup(S.Kval);
+        out->lcol = dup(S.Lcol);
+        out->lval = dup(S.Lval);
+        out->ucol = dup(S.Ucol);
+        out->uval = dup(S.Uval);
+        out->dinv = dup(S.Dv);
+        (void)nf;
+    } catch (const Fail& f) {
+        g_create_err = f.msg;
+        gks_host_free(out);
+        return f.code;
+    } catch (const std::bad_alloc&) {
+        g_create_err = "out of host memory";
+        gks_host_free(out);
+        return GKS_ENOMEM;
+    }
+    return GKS_OK;
+}
+
+void gks_host_free(gks_host_system* s) {
+    if (!s) return;
+    void* ptrs[] = {s->own, s->nbr, s->area, s->h, s->perm, s->lev_ptr, s->kcol, s->kval,
+                    s->lcol, s->lval, s->ucol, s->uval, s->dinv};
+    for (void* q : ptrs) std::free(q);
+    std::memset(s, 0, sizeof(*s));
+}
+
+const char* gks_last_error(const gks_mesh* m) {
+    if (!m) return g_create_err.c_str();
+    return m->err.c_str();
+}
+
+void gks_destroy(gks_mesh* m) {
+    if (!m) return;
+    (void)hipDeviceSynchronize();
+    for (auto& p : m->prof.pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (auto e : m->prof.pool) (void)hipEventDestroy(e);
+    for (void* p : m->allocs) (void)hipFree(p);
+    if (m->w.st_host) (void)hipHostFree(m->w.st_host);
+    if (m->w.counters_host) (void)hipHostFree(m->w.counters_host);
+    if (m->w.scal_host) (void)hipHostFree(m->w.scal_host);
+    delete m;
+}
+
+}  // extern "C"

@@ -1,0 +1,180 @@
+// Internal layout of a gks_mesh handle and the kernel launchers.
+//
+// Orders: "cell order" is the caller's triangle order; "solver order" is the
+// renumbering used by the reconstruction solve (colour-major or RCM-level
+// major, RCM inside).  perm[new] = old, iperm[old] = new.
+//
+// Solver vectors are cell-major: v[(i * NC + col) * NB + l] for cell i,
+// conserved variable col (NC = 4) and coefficient l (NB = 5), so one cell's
+// 4 x 5 block is 160 contiguous bytes.  Every vector has n + 1 cells; cell n
+// is a zero dummy that padded matrix slots point at.
+//
+// Block-ELL matrices store 5 x 5 blocks entry-major: val[(slot * 25 + e) * n
+// + i], entry e = 5 r + c (row r, column c), so a wave reading one entry of
+// consecutive rows reads contiguous memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/gks.h"
+
+namespace gks {
+
+constexpr int NC = 4;             // conserved variables = right-hand-side columns
+constexpr int NB = 5;             // coefficients per cell
+constexpr int CB = NC * NB;       // doubles per cell in a solver vector
+constexpr int KW = 4;             // ELL width of K (diagonal + 3 neighbours)
+constexpr int LW = 3;             // ELL width of the strict lower / upper factors
+constexpr int MAXM = 64;          // largest GMRES restart length
+constexpr int NPROF = 24;         // profiled kernel classes
+
+struct Profile {
+    bool on = false;
+    int64_t launches[NPROF] = {0};
+    double ms[NPROF] = {0};
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> pool;
+};
+
+// Device-resident GMRES bookkeeping of one solve (one entry per column).
+// The host reads only the leading Status block.
+struct Status {
+    double est[NC];               // |g_{k+1}| / ||R_c|| (estimate of the relative residual)
+    double beta[NC];              // ||r_c|| at the start of the cycle (true residual)
+    double bnorm[NC];             // ||R_c||
+    int32_t k;                    // Arnoldi steps done in this cycle
+    int32_t conv[NC];             // 1 once the estimate meets tol
+    int32_t active[NC];           // 0 for a zero right-hand side
+};
+
+struct KrylovState {
+    Status st;
+    double tol;
+    double scale[MAXM + 1][NC];   // v_j = scale_j * V_j (basis stored unnormalised)
+    double h1[MAXM + 1][NC];      // first Gram-Schmidt pass
+    double h2[MAXM + 1][NC];      // second pass
+    double H[MAXM][MAXM + 1][NC]; // H[k][j]: column k after rotations
+    double cs[MAXM][NC], sn[MAXM][NC];
+    double g[MAXM + 1][NC];
+    double y[MAXM][NC];
+    double sq[NC];                // squared norms handed to the control kernel
+};
+
+struct DevMesh {
+    int nt = 0, nf = 0, nfb = 0;
+    // faces (face order)
+    int32_t* own = nullptr;       // [nf]
+    int32_t* nbr = nullptr;       // [nf]  >= 0 cell, < 0: -(boundary row)
+    double* fgeo = nullptr;       // [3][nf] nx, ny, S
+    double* gpd = nullptr;        // [8][nf] (dx, dy) / h of GP g, side s at 2 (2 g + s) ..
+    // cells (cell order)
+    double* area = nullptr;       // [nt]
+    double* cgeo = nullptr;       // [4][nt] 1/h, mxx, mxy, myy (second moments / h^2)
+    int32_t* cface = nullptr;     // [3][nt] face f (owner) or ~f (neighbour)
+    // boundary table
+    int32_t* bc_kind = nullptr;   // [n_bc + 1]
+    double* bc_state = nullptr;   // [n_bc + 1][4]
+    int n_bc = 0;
+    // solver (solver order)
+    int n = 0;
+    int32_t* perm = nullptr;      // [n] new -> old
+    int32_t* rnb = nullptr;       // [3][n] old index of neighbour (self if none)
+    double* a0 = nullptr;         // [3][5][n] CLS row-0 coefficients per neighbour slot
+    double* Kval = nullptr;       // [KW][25][n]
+    int32_t* Kcol = nullptr;      // [KW][n] (n = dummy)
+    float* Kval32 = nullptr;
+    double* Lval = nullptr;       // [LW][25][n] strict lower factor blocks
+    int32_t* Lcol = nullptr;
+    double* Uval = nullptr;       // [LW][25][n] strict upper factor blocks
+    int32_t* Ucol = nullptr;
+    double* Dinv = nullptr;       // [25][n] inverted pivot blocks
+    float* Lval32 = nullptr;
+    float* Uval32 = nullptr;
+    float* Dinv32 = nullptr;
+    std::vector<int32_t> lev_ptr; // host: rows of level l are [lev_ptr[l], lev_ptr[l+1])
+};
+
+struct Work {
+    double* X = nullptr;          // [n+1][CB] current solution (warm start)
+    double* R = nullptr;          // [n+1][CB] right-hand side
+    double* V = nullptr;          // [(m+1)][n+1][CB] Krylov basis
+    double* Z = nullptr;          // [m][n+1][CB] flexible GMRES: preconditioned basis
+    double* w = nullptr;          // [n+1][CB]
+    double* t1 = nullptr;         // [n+1][CB]
+    double* t2 = nullptr;         // [n+1][CB]
+    double* t3 = nullptr;         // [n+1][CB]
+    double* ones = nullptr;       // [MAXM + 1][NC] unit scale factors
+    double* partial = nullptr;    // block partial sums
+    int nblk_red = 0;             // blocks of the reduction kernels
+    KrylovState* ks = nullptr;    // device
+    Status* st_host = nullptr;    // pinned mirror of ks->st
+    double* Xcell = nullptr;      // [4][5][nt] X in cell order (gks_step)
+    double* F = nullptr;          // [4][nf]
+    double* Wn = nullptr;         // [4][nt]
+    double* dt_dev = nullptr;     // [1]
+    double* dtpart = nullptr;     // block minima of the CFL rule
+    int32_t* counters = nullptr;  // [4] nonphysical count, ...
+    int32_t* counters_host = nullptr;
+    double* scal_host = nullptr;  // pinned scalars
+};
+
+}  // namespace gks
+
+struct gks_mesh {
+    gks_params prm;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    gks::DevMesh d;
+    gks::Work w;
+    gks::Profile prof;
+    std::vector<int32_t> h_own, h_nbr;
+    int n_levels = 0, n_colors = 0, rcm_bw = 0;
+    int64_t dev_bytes = 0;
+    std::vector<void*> allocs;
+    bool have_x = false;
+    std::string err;
+};
+
+namespace gks {
+
+// kernel classes for profiling
+enum Kc {
+    KC_RHS = 0, KC_SPMV, KC_SPMV_RES, KC_ILU_FWD, KC_ILU_BWD, KC_DOTS, KC_AXPY_DOTS, KC_AXPY_NORM,
+    KC_FINAL, KC_COMBINE, KC_AXPY, KC_COPYOUT, KC_FLUX, KC_UPDATE, KC_CFL, KC_MISC,
+    KC_SPMV32, KC_ILU_FWD32, KC_ILU_BWD32, KC_COUNT
+};
+extern const char* kc_names[NPROF];
+
+// launchers (gks_kernels.hip); all enqueue on m->stream
+void launch_rhs(gks_mesh* m, const double* W);
+void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y);
+void launch_spmv32(gks_mesh* m, const double* x, const double* xscale, double* y);
+void launch_resid(gks_mesh* m, const double* x, const double* b, double* y);
+void launch_resid32(gks_mesh* m, const double* x, const double* b, const double* bscale, double* y);
+void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out, bool fp32);
+void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
+                        const double* scale, double* out);
+void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
+                 const double* w, double* out);
+void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
+                    double* out);
+void launch_acc(gks_mesh* m, double* X, const double* z);
+void launch_ctl(gks_mesh* m, int mode);
+void launch_mask_cols(gks_mesh* m, double* X);
+void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell);
+void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);
+void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
+void launch_cfl(gks_mesh* m, const double* W, double* dt_out);
+void launch_set_scalar(gks_mesh* m, double* p, double v);
+void launch_zero(gks_mesh* m, double* p, int64_t count);
+void launch_zero_i32(gks_mesh* m, int32_t* p, int count);
+void launch_copy(gks_mesh* m, double* dst, const double* src, int64_t count);
+
+void prof_begin(gks_mesh* m, int kc);
+void prof_end(gks_mesh* m, int kc);
+
+}  // namespace gks

@@ -1,0 +1,870 @@
+// HIP kernels of the reconstruction solve, the Gauss-point flux and the
+// finite-volume update, for gfx950 (wave64).
+//
+// No floating-point atomics anywhere: every reduction writes per-block
+// partial sums that a second kernel adds in a fixed order, so results are
+// bitwise reproducible run to run.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "gks_flux_device.h"
+#include "gks_internal.h"
+
+namespace gks {
+
+const char* kc_names[NPROF] = {"rhs",       "spmv",       "spmv_resid", "ilu_fwd",  "ilu_bwd",
+                               "dots",      "axpy_dots",  "axpy_norm",  "finalize", "combine",
+                               "axpy",      "copyout",    "flux",       "update",   "cfl",
+                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "", "", "", "", ""};
+
+constexpr int TPB = 256;          // threads per block of the streaming kernels
+constexpr int RED_CHUNK = 8;      // vectors per block of the dot kernel
+
+static inline int nblocks(int64_t n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
+
+// ------------------------------------------------------------------ RHS
+// R_i = sum_j a0_ij (W_j - W_i) for the four variables (Eq. A:B:b, b = C^T b)
+__global__ void __launch_bounds__(TPB) k_rhs(int n, const int32_t* __restrict__ perm,
+                                             const int32_t* __restrict__ rnb, const double* __restrict__ a0,
+                                             const double* __restrict__ W, int nt, double* __restrict__ R) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int oi = perm[i];
+    double wi[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) wi[c] = W[(int64_t)c * nt + oi];
+    double acc[NC][NB];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) acc[c][l] = 0.0;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int j = rnb[(int64_t)s * n + i];
+        double a[NB];
+#pragma unroll
+        for (int l = 0; l < NB; ++l) a[l] = a0[((int64_t)s * NB + l) * n + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double d = W[(int64_t)c * nt + j] - wi[c];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) acc[c][l] += a[l] * d;
+        }
+    }
+    double* out = R + (int64_t)i * CB;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int l = 0; l < NB; ++l) out[c * NB + l] = acc[c][l];
+}
+
+// ------------------------------------------------------------------ SpMV
+// y = K (s .* x)   or   y = b - K x   (RESID), block-ELL, thread per row.
+// In RESID mode xscale (when not null) scales b instead: y = s .* b - K x.
+template <typename T, bool RESID>
+__global__ void __launch_bounds__(TPB) k_spmv(int n, const T* __restrict__ val, const int32_t* __restrict__ col,
+                                              const double* __restrict__ x, const double* __restrict__ xscale,
+                                              const double* __restrict__ b, double* __restrict__ y) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[NC][NB];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[c][r] = 0.0;
+#pragma unroll
+    for (int s = 0; s < KW; ++s) {
+        const int j = col[(int64_t)s * n + i];
+        const double* xj = x + (int64_t)j * CB;
+        double xv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) xv[q] = xj[q];
+        T blk[25];
+#pragma unroll
+        for (int e = 0; e < 25; ++e) blk[e] = val[((int64_t)s * 25 + e) * n + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[c][r] += (double)blk[r * NB + q] * xv[c * NB + q];
+    }
+    double* yi = y + (int64_t)i * CB;
+    if (RESID) {
+        const double* bi = b + (int64_t)i * CB;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double sc = xscale ? xscale[c] : 1.0;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) yi[c * NB + r] = sc * bi[c * NB + r] - acc[c][r];
+        }
+    } else {
+        double sc[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sc[c] = xscale ? xscale[c] : 1.0;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r) yi[c * NB + r] = sc[c] * acc[c][r];
+    }
+}
+
+// ------------------------------------------------------------------ BILU(0) sweeps
+// forward  y_i = s .* v_i - sum_{k<i} L_ik y_k            (unit lower factor)
+// backward z_i = Dinv_i (y_i - sum_{j>i} U_ij z_j)
+// over the rows [r0, r1) of one dependency level.
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int r0, int r1, const T* __restrict__ Lv,
+                                                 const int32_t* __restrict__ Lc, const double* __restrict__ v,
+                                                 const double* __restrict__ vscale, double* __restrict__ y) {
+    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r1) return;
+    double acc[CB];
+    const double* vi = v + (int64_t)i * CB;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const double sc = vscale ? vscale[c] : 1.0;
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[c * NB + r] = sc * vi[c * NB + r];
+    }
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        const int k = Lc[(int64_t)s * n + i];
+        const double* yk = y + (int64_t)k * CB;
+        double yv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) yv[q] = yk[q];
+        T blk[25];
+#pragma unroll
+        for (int e = 0; e < 25; ++e) blk[e] = Lv[((int64_t)s * 25 + e) * n + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (double)blk[r * NB + q] * yv[c * NB + q];
+    }
+    double* yi = y + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) yi[q] = acc[q];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int r0, int r1, const T* __restrict__ Uv,
+                                                 const int32_t* __restrict__ Uc, const T* __restrict__ Dinv,
+                                                 const double* __restrict__ y, double* __restrict__ z) {
+    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= r1) return;
+    double acc[CB];
+    const double* yi = y + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = yi[q];
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        const int j = Uc[(int64_t)s * n + i];
+        const double* zj = z + (int64_t)j * CB;
+        double zv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) zv[q] = zj[q];
+        T blk[25];
+#pragma unroll
+        for (int e = 0; e < 25; ++e) blk[e] = Uv[((int64_t)s * 25 + e) * n + i];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (double)blk[r * NB + q] * zv[c * NB + q];
+    }
+    T d[25];
+#pragma unroll
+    for (int e = 0; e < 25; ++e) d[e] = Dinv[(int64_t)e * n + i];
+    double* zi = z + (int64_t)i * CB;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) s += (double)d[r * NB + q] * acc[c * NB + q];
+            zi[c * NB + r] = s;
+        }
+}
+
+// ------------------------------------------------------------------ reductions
+// Per-column dot products p_j = V_j . w for j in a chunk of RED_CHUNK vectors
+// (blockIdx.y selects the chunk).  Each block writes its partial sums to
+// partial[(j * NC + c) * nblk + blockIdx.x].
+__global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                              const double* __restrict__ w, double* __restrict__ partial) {
+    __shared__ double sh[RED_CHUNK * NC][TPB / 64];
+    const int j0 = blockIdx.y * RED_CHUNK;
+    const int nj = min(RED_CHUNK, nvec - j0);
+    double acc[RED_CHUNK][NC];
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) acc[j][c] = 0.0;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        double wv[CB];
+        const double* wi = w + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) wv[q] = wi[q];
+#pragma unroll
+        for (int j = 0; j < RED_CHUNK; ++j) {
+            if (j < nj) {
+                const double* vi = V + (int64_t)(j0 + j) * vstride + (int64_t)i * CB;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) acc[j][c] += vi[c * NB + l] * wv[c * NB + l];
+            }
+        }
+    }
+    // wave reduction (fixed butterfly order), then across the block's waves
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double v = acc[j][c];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) sh[j * NC + c][wid] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < nj * NC) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / 64; ++q) s += sh[threadIdx.x][q];
+        const int j = threadIdx.x / NC, c = threadIdx.x % NC;
+        partial[((int64_t)(j0 + j) * NC + c) * gridDim.x + blockIdx.x] = s;
+    }
+}
+
+// w <- w - sum_j coef_j[c] V_j   (coef_j = h[j][c] * scale[j][c]); out may alias w
+__global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                              const double* __restrict__ h, const double* __restrict__ scale,
+                                              const double* w, double* out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[CB];
+    const double* wi = w + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = wi[q];
+    for (int j = 0; j < nvec; ++j) {
+        const double* vi = V + (int64_t)j * vstride + (int64_t)i * CB;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double cf = h[j * NC + c] * scale[j * NC + c];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) acc[c * NB + l] -= cf * vi[c * NB + l];
+        }
+    }
+    double* oi = out + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) oi[q] = acc[q];
+}
+
+// out = sum_j y_j[c] scale_j[c] V_j
+__global__ void __launch_bounds__(TPB) k_combine(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                                 const double* __restrict__ y, const double* __restrict__ scale,
+                                                 double* __restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int j = 0; j < nvec; ++j) {
+        const double* vi = V + (int64_t)j * vstride + (int64_t)i * CB;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double cf = y[j * NC + c] * scale[j * NC + c];
+#pragma unroll
+            for (int l = 0; l < NB; ++l) acc[c * NB + l] += cf * vi[c * NB + l];
+        }
+    }
+    double* oi = out + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) oi[q] = acc[q];
+}
+
+// X += z
+__global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X, const double* __restrict__ z) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) X[i] += z[i];
+}
+
+// Sum partials of nval values in a fixed order: one wave per value.
+// mode 0: out[v] = sum;  mode 1: out[v] = sum * scale[v]
+__global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const double* __restrict__ partial,
+                                                      const double* __restrict__ scale, double* __restrict__ out) {
+    const int v = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (v >= nval) return;
+    double s = 0.0;
+    for (int b = lane; b < nblk; b += 64) s += partial[(int64_t)v * nblk + b];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+    if (lane == 0) out[v] = scale ? s * scale[v] : s;
+}
+
+// ------------------------------------------------------------------ GMRES bookkeeping (one wave)
+// mode 0 (BNORM):   ||R_c|| from sq, active = ||R_c|| > 0
+// mode 1 (BETA):    start of a cycle from ||r_c||^2: beta, scale_0, g, k = 0
+// mode 2 (ARNOLDI): column k of H from h1 + h2 and ||w||^2, Givens rotation,
+//                   residual estimate, k += 1
+// mode 3 (SOLVE):   y = R^{-1} g over the first k columns
+__global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restrict__ ks) {
+    const int c = threadIdx.x;
+    const int k = ks->st.k;
+    __syncthreads();
+    if (c < NC) {
+        Status& st = ks->st;
+        if (mode == 0) {
+            const double b = sqrt(ks->sq[c]);
+            st.bnorm[c] = b;
+            st.active[c] = b > 0.0;
+        } else if (mode == 1) {
+            const double b = sqrt(ks->sq[c]);
+            st.beta[c] = b;
+            ks->scale[0][c] = b > 0.0 ? 1.0 / b : 0.0;
+            for (int j = 0; j <= MAXM; ++j) ks->g[j][c] = 0.0;
+            ks->g[0][c] = b;
+            const double bn = st.bnorm[c];
+            st.est[c] = bn > 0.0 ? b / bn : 0.0;
+            st.conv[c] = (!st.active[c]) || b <= ks->tol * bn;
+        } else if (mode == 2) {
+            double col[MAXM + 1];
+            for (int j = 0; j <= k; ++j) col[j] = ks->h1[j][c] + ks->h2[j][c];
+            const double hn = sqrt(ks->sq[c]);
+            col[k + 1] = hn;
+            ks->scale[k + 1][c] = hn > 0.0 ? 1.0 / hn : 0.0;
+            for (int j = 0; j < k; ++j) {
+                const double t = ks->cs[j][c] * col[j] + ks->sn[j][c] * col[j + 1];
+                col[j + 1] = -ks->sn[j][c] * col[j] + ks->cs[j][c] * col[j + 1];
+                col[j] = t;
+            }
+            const double d = hypot(col[k], col[k + 1]);
+            double cs = 1.0, sn = 0.0;
+            if (d > 0.0) {
+                cs = col[k] / d;
+                sn = col[k + 1] / d;
+            }
+            ks->cs[k][c] = cs;
+            ks->sn[k][c] = sn;
+            col[k] = d;
+            col[k + 1] = 0.0;
+            for (int j = 0; j <= k + 1; ++j) ks->H[k][j][c] = col[j];
+            const double gk = ks->g[k][c];
+            ks->g[k + 1][c] = -sn * gk;
+            ks->g[k][c] = cs * gk;
+            const double bn = st.bnorm[c];
+            const double e = bn > 0.0 ? fabs(ks->g[k + 1][c]) / bn : 0.0;
+            st.est[c] = e;
+            st.conv[c] = (!st.active[c]) || e <= ks->tol;
+        } else if (mode == 3) {
+            for (int j = k - 1; j >= 0; --j) {
+                double s = ks->g[j][c];
+                for (int q = j + 1; q < k; ++q) s -= ks->H[q][j][c] * ks->y[q][c];
+                const double d = ks->H[j][j][c];
+                ks->y[j][c] = d != 0.0 ? s / d : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+    if (c == 0) {
+        if (mode == 1) ks->st.k = 0;
+        if (mode == 2) ks->st.k = k + 1;
+    }
+}
+
+// ------------------------------------------------------------------ layout conversion
+__global__ void __launch_bounds__(TPB) k_copyout(int n, int nt, const int32_t* __restrict__ perm,
+                                                 const double* __restrict__ Xs, double* __restrict__ Xc) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int oi = perm[i];
+    const double* xi = Xs + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) Xc[(int64_t)q * nt + oi] = xi[q];
+}
+
+__global__ void k_set(double* p, double v) { *p = v; }
+
+__global__ void __launch_bounds__(TPB) k_zero(int64_t len, double* __restrict__ p) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) p[i] = 0.0;
+}
+
+__global__ void __launch_bounds__(TPB) k_copy(int64_t len, double* __restrict__ d, const double* __restrict__ s) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < len) d[i] = s[i];
+}
+
+// zero the inactive columns of X (a zero right-hand side has X = 0)
+__global__ void __launch_bounds__(TPB) k_mask_cols(int n, double* __restrict__ X, const KrylovState* __restrict__ ks) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+        if (!ks->st.active[c])
+#pragma unroll
+            for (int l = 0; l < NB; ++l) X[(int64_t)i * CB + c * NB + l] = 0.0;
+}
+
+// ------------------------------------------------------------------ flux
+struct FluxArgs {
+    int nf, nt;
+    const int32_t* own;
+    const int32_t* nbr;
+    const double* fgeo;
+    const double* gpd;
+    const double* cgeo;
+    const int32_t* bc_kind;
+    const double* bc_state;
+    const double* W;
+    const double* X;
+    const double* dt;
+    double* F;
+    int32_t* nonphys;
+    gksdev::FluxParams fp;
+    int fallback;
+};
+
+// Cell polynomial value, gradient and Hessian at offset (dx, dy) (in units of
+// h), rotated into the face frame: Wloc and d[5][4] = n, t, nn, nt, tt.
+__device__ __forceinline__ void gp_state(const FluxArgs& a, int cell, double dx, double dy, double nx, double ny,
+                                         double Wloc[4], double d[5][4]) {
+    const int nt = a.nt;
+    const double ih = a.cgeo[cell];
+    const double mxx = a.cgeo[nt + cell], mxy = a.cgeo[2 * nt + cell], myy = a.cgeo[3 * nt + cell];
+    const double phi[5] = {dx, dy, 0.5 * (dx * dx - mxx), dx * dy - mxy, 0.5 * (dy * dy - myy)};
+    double Q[4], Qx[4], Qy[4], Qxx[4], Qxy[4], Qyy[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        double X[5];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) X[l] = a.X[(int64_t)(v * 5 + l) * nt + cell];
+        double q = a.W[(int64_t)v * nt + cell];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) q += X[l] * phi[l];
+        Q[v] = q;
+        Qx[v] = (X[0] + X[2] * dx + X[3] * dy) * ih;
+        Qy[v] = (X[1] + X[3] * dx + X[4] * dy) * ih;
+        Qxx[v] = X[2] * ih * ih;
+        Qxy[v] = X[3] * ih * ih;
+        Qyy[v] = X[4] * ih * ih;
+    }
+    const double tx = -ny, ty = nx;
+    double loc[6][4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        loc[0][v] = Q[v];
+        loc[1][v] = nx * Qx[v] + ny * Qy[v];
+        loc[2][v] = tx * Qx[v] + ty * Qy[v];
+        loc[3][v] = nx * nx * Qxx[v] + 2.0 * nx * ny * Qxy[v] + ny * ny * Qyy[v];
+        loc[4][v] = nx * tx * Qxx[v] + (nx * ty + ny * tx) * Qxy[v] + ny * ty * Qyy[v];
+        loc[5][v] = tx * tx * Qxx[v] + 2.0 * tx * ty * Qxy[v] + ty * ty * Qyy[v];
+    }
+    // rotate the momentum pair into (n, t)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        const double mx = loc[k][1], my = loc[k][2];
+        loc[k][1] = mx * nx + my * ny;
+        loc[k][2] = -mx * ny + my * nx;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        Wloc[v] = loc[0][v];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) d[k][v] = loc[k + 1][v];
+    }
+}
+
+__device__ __forceinline__ bool physical(const double W[4], double gamma) {
+    return W[0] > 0.0 && gksdev::pressure(W, gamma) > 0.0;
+}
+
+__device__ __forceinline__ void cell_average_local(const FluxArgs& a, int cell, double nx, double ny, double W[4],
+                                                   double d[5][4]) {
+    const double m0 = a.W[(int64_t)1 * a.nt + cell], m1 = a.W[(int64_t)2 * a.nt + cell];
+    W[0] = a.W[cell];
+    W[1] = m0 * nx + m1 * ny;
+    W[2] = -m0 * ny + m1 * nx;
+    W[3] = a.W[(int64_t)3 * a.nt + cell];
+#pragma unroll
+    for (int k = 0; k < 5; ++k)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) d[k][v] = 0.0;
+}
+
+// Ghost state beyond a boundary face (face frame), from the interior side.
+__device__ __forceinline__ void ghost(const FluxArgs& a, int row, const double WL[4], const double dL[5][4],
+                                      double nx, double ny, double WR[4], double dR[5][4]) {
+    const int kind = a.bc_kind[row];
+    const double* st = a.bc_state + 4 * row;
+    if (kind == GKS_BC_SLIP || kind == GKS_BC_NOSLIP) {
+        double Lm[4][4] = {{1, 0, 0, 0}, {0, -1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+        if (kind == GKS_BC_NOSLIP) {
+            const double wn = st[1] * nx + st[2] * ny;
+            const double wt = -st[1] * ny + st[2] * nx;
+            Lm[1][0] = 2.0 * wn;
+            Lm[2][0] = 2.0 * wt;
+            Lm[2][2] = -1.0;
+            Lm[3][0] = 2.0 * (wn * wn + wt * wt);
+            Lm[3][1] = -2.0 * wn;
+            Lm[3][2] = -2.0 * wt;
+        }
+        // mirror: one sign per normal differentiation (n: -, t: +, nn: +, nt: -, tt: +)
+        const double sg[5] = {-1.0, 1.0, 1.0, -1.0, 1.0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            double s = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) s += Lm[r][q] * WL[q];
+            WR[r] = s;
+#pragma unroll
+            for (int k = 0; k < 5; ++k) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t += Lm[r][q] * dL[k][q];
+                dR[k][r] = sg[k] * t;
+            }
+        }
+    } else if (kind == GKS_BC_INFLOW) {
+        const double rho = st[0], u = st[1], v = st[2], p = st[3];
+        const double mx = rho * u, my = rho * v;
+        WR[0] = rho;
+        WR[1] = mx * nx + my * ny;
+        WR[2] = -mx * ny + my * nx;
+        WR[3] = p / (a.fp.gamma - 1.0) + 0.5 * rho * (u * u + v * v);
+#pragma unroll
+        for (int k = 0; k < 5; ++k)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) dR[k][q] = 0.0;
+    } else {  // outflow: copy
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            WR[q] = WL[q];
+#pragma unroll
+            for (int k = 0; k < 5; ++k) dR[k][q] = dL[k][q];
+        }
+    }
+}
+
+// One thread per Gauss point; lanes 2f and 2f+1 hold the two points of face f.
+__global__ void __launch_bounds__(128) k_flux(FluxArgs a) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int f = (int)(t >> 1);
+    const int g = (int)(t & 1);
+    const bool valid = f < a.nf;
+    double F[4] = {0.0, 0.0, 0.0, 0.0};
+    double nx = 1.0, ny = 0.0, S = 0.0;
+    if (valid) {
+        nx = a.fgeo[f];
+        ny = a.fgeo[a.nf + f];
+        S = a.fgeo[2 * (int64_t)a.nf + f];
+        const int o = a.own[f];
+        const int nb = a.nbr[f];
+        double WL[4], dL[5][4], WR[4], dR[5][4];
+        gp_state(a, o, a.gpd[(int64_t)(4 * g + 0) * a.nf + f], a.gpd[(int64_t)(4 * g + 1) * a.nf + f], nx, ny, WL, dL);
+        int bad = 0;
+        if (!physical(WL, a.fp.gamma)) {
+            ++bad;
+            cell_average_local(a, o, nx, ny, WL, dL);
+        }
+        if (nb >= 0) {
+            gp_state(a, nb, a.gpd[(int64_t)(4 * g + 2) * a.nf + f], a.gpd[(int64_t)(4 * g + 3) * a.nf + f], nx, ny,
+                     WR, dR);
+            if (!physical(WR, a.fp.gamma)) {
+                ++bad;
+                cell_average_local(a, nb, nx, ny, WR, dR);
+            }
+        } else {
+            ghost(a, -nb, WL, dL, nx, ny, WR, dR);
+        }
+        if (bad) atomicAdd(a.nonphys, bad);
+        gksdev::gp_flux(F, WL, dL, WR, dR, *a.dt, a.fp);
+    }
+    // back to (x, y), weight S/2, sum the two Gauss points of the face
+    double Fx[4];
+    Fx[0] = 0.5 * S * F[0];
+    Fx[1] = 0.5 * S * (F[1] * nx - F[2] * ny);
+    Fx[2] = 0.5 * S * (F[1] * ny + F[2] * nx);
+    Fx[3] = 0.5 * S * F[3];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Fx[q] += __shfl_xor(Fx[q], 1, 64);
+    if (valid && g == 0) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a.F[(int64_t)q * a.nf + f] = Fx[q];
+    }
+}
+
+// ------------------------------------------------------------------ update (Eq. fvm3)
+__global__ void __launch_bounds__(TPB) k_update(int nt, int nf, const int32_t* __restrict__ cface,
+                                                const double* __restrict__ area, const double* __restrict__ W,
+                                                const double* __restrict__ F, double* __restrict__ Wn,
+                                                double gamma, int32_t* __restrict__ nonphys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int code = cface[(int64_t)k * nt + i];
+        const int f = code >= 0 ? code : ~code;
+        const double s = code >= 0 ? -1.0 : 1.0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += s * F[(int64_t)q * nf + f];
+    }
+    const double ia = 1.0 / area[i];
+    double w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        w[q] = W[(int64_t)q * nt + i] + acc[q] * ia;
+        Wn[(int64_t)q * nt + i] = w[q];
+    }
+    if (!(w[0] > 0.0 && gksdev::pressure(w, gamma) > 0.0)) atomicAdd(nonphys, 1);
+}
+
+// ------------------------------------------------------------------ CFL
+__global__ void __launch_bounds__(TPB) k_cfl(int nt, int nf, const int32_t* __restrict__ cface,
+                                             const double* __restrict__ area, const double* __restrict__ fgeo,
+                                             const double* __restrict__ W, double gamma,
+                                             double* __restrict__ partial) {
+    __shared__ double sh[TPB / 64];
+    double best = INFINITY;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+        const double rho = W[i], u = W[(int64_t)nt + i] / rho, v = W[2 * (int64_t)nt + i] / rho;
+        const double p = (gamma - 1.0) * (W[3 * (int64_t)nt + i] - 0.5 * rho * (u * u + v * v));
+        const double c = sqrt(gamma * p / rho);
+        double den = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int code = cface[(int64_t)k * nt + i];
+            const int f = code >= 0 ? code : ~code;
+            den += fgeo[2 * (int64_t)nf + f] * (fabs(u * fgeo[f] + v * fgeo[nf + f]) + c);
+        }
+        best = fmin(best, area[i] / den);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) best = fmin(best, __shfl_xor(best, off, 64));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double b = sh[0];
+        for (int q = 1; q < TPB / 64; ++q) b = fmin(b, sh[q]);
+        partial[blockIdx.x] = b;
+    }
+}
+
+__global__ void k_cfl_final(int nblk, const double* __restrict__ partial, double cfl, double* __restrict__ dt) {
+    double b = INFINITY;
+    for (int q = threadIdx.x; q < nblk; q += 64) b = fmin(b, partial[q]);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) b = fmin(b, __shfl_xor(b, off, 64));
+    if (threadIdx.x == 0) *dt = cfl * b;
+}
+
+// ================================================================== launchers
+
+void prof_begin(gks_mesh* m, int kc) {
+    if (!m->prof.on) return;
+    hipEvent_t a, b;
+    if (m->prof.pool.size() >= 2) {
+        a = m->prof.pool.back();
+        m->prof.pool.pop_back();
+        b = m->prof.pool.back();
+        m->prof.pool.pop_back();
+    } else {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    (void)hipEventRecord(a, m->stream);
+    m->prof.pending.push_back({kc, {a, b}});
+}
+
+void prof_end(gks_mesh* m, int kc) {
+    (void)kc;
+    if (!m->prof.on || m->prof.pending.empty()) return;
+    (void)hipEventRecord(m->prof.pending.back().second.second, m->stream);
+}
+
+#define PROF(kc, launch)        \
+    do {                        \
+        prof_begin(m, kc);      \
+        launch;                 \
+        prof_end(m, kc);        \
+    } while (0)
+
+void launch_rhs(gks_mesh* m, const double* W) {
+    const int n = m->d.n;
+    PROF(KC_RHS, hipLaunchKernelGGL(k_rhs, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.perm, m->d.rnb,
+                                    m->d.a0, W, m->d.nt, m->w.R));
+}
+
+void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y) {
+    const int n = m->d.n;
+    PROF(KC_SPMV, hipLaunchKernelGGL((k_spmv<double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+                                     m->d.Kval, m->d.Kcol, x, xscale, nullptr, y));
+}
+
+void launch_spmv32(gks_mesh* m, const double* x, const double* xscale, double* y) {
+    const int n = m->d.n;
+    PROF(KC_SPMV32, hipLaunchKernelGGL((k_spmv<float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+                                       m->d.Kval32, m->d.Kcol, x, xscale, nullptr, y));
+}
+
+void launch_resid(gks_mesh* m, const double* x, const double* b, double* y) {
+    const int n = m->d.n;
+    PROF(KC_SPMV_RES, hipLaunchKernelGGL((k_spmv<double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+                                         m->d.Kval, m->d.Kcol, x, nullptr, b, y));
+}
+
+void launch_resid32(gks_mesh* m, const double* x, const double* b, const double* bscale, double* y) {
+    const int n = m->d.n;
+    PROF(KC_SPMV32, hipLaunchKernelGGL((k_spmv<float, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+                                       m->d.Kval32, m->d.Kcol, x, bscale, b, y));
+}
+
+void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out, bool fp32) {
+    const int n = m->d.n;
+    const auto& lp = m->d.lev_ptr;
+    const int nl = (int)lp.size() - 1;
+    for (int l = 0; l < nl; ++l) {
+        const int r0 = lp[l], r1 = lp[l + 1];
+        if (r1 <= r0) continue;
+        if (fp32)
+            PROF(KC_ILU_FWD32, hipLaunchKernelGGL(k_ilu_fwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+                                                  n, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp));
+        else
+            PROF(KC_ILU_FWD, hipLaunchKernelGGL(k_ilu_fwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+                                                n, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp));
+    }
+    for (int l = nl - 1; l >= 0; --l) {
+        const int r0 = lp[l], r1 = lp[l + 1];
+        if (r1 <= r0) continue;
+        if (fp32)
+            PROF(KC_ILU_BWD32, hipLaunchKernelGGL(k_ilu_bwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+                                                  n, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out));
+        else
+            PROF(KC_ILU_BWD, hipLaunchKernelGGL(k_ilu_bwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+                                                n, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out));
+    }
+}
+
+// partial sums of V_j . w for j < nvec into m->w.partial, then reduce
+// (times scale_j when scale != NULL) into out[j * NC + c].
+void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
+                        const double* scale, double* out) {
+    const int n = m->d.n;
+    const int nb = m->w.nblk_red;
+    const int nch = (nvec + RED_CHUNK - 1) / RED_CHUNK;
+    PROF(kc, hipLaunchKernelGGL(k_dots, dim3(nb, nch), dim3(TPB), 0, m->stream, n, V, vstride, nvec, w,
+                                m->w.partial));
+    const int nval = nvec * NC;
+    PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3((nval + 3) / 4), dim3(TPB), 0, m->stream, nval, nb,
+                                      m->w.partial, scale, out));
+}
+
+void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
+                 const double* w, double* out) {
+    const int n = m->d.n;
+    PROF(KC_AXPY_DOTS, hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+                                          h, scale, w, out));
+}
+
+void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
+                    double* out) {
+    const int n = m->d.n;
+    PROF(KC_COMBINE, hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+                                        y, scale, out));
+}
+
+void launch_acc(gks_mesh* m, double* X, const double* z) {
+    const int64_t len = (int64_t)m->d.n * CB;
+    PROF(KC_AXPY, hipLaunchKernelGGL(k_acc, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, X, z));
+}
+
+void launch_ctl(gks_mesh* m, int mode) {
+    PROF(KC_MISC, hipLaunchKernelGGL(k_gmres_ctl, dim3(1), dim3(64), 0, m->stream, mode, m->w.ks));
+}
+
+void launch_mask_cols(gks_mesh* m, double* X) {
+    const int n = m->d.n;
+    PROF(KC_MISC, hipLaunchKernelGGL(k_mask_cols, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, X, m->w.ks));
+}
+
+void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell) {
+    const int n = m->d.n;
+    PROF(KC_COPYOUT, hipLaunchKernelGGL(k_copyout, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.nt,
+                                        m->d.perm, Xs, Xcell));
+}
+
+void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F) {
+    FluxArgs a;
+    a.nf = m->d.nf;
+    a.nt = m->d.nt;
+    a.own = m->d.own;
+    a.nbr = m->d.nbr;
+    a.fgeo = m->d.fgeo;
+    a.gpd = m->d.gpd;
+    a.cgeo = m->d.cgeo;
+    a.bc_kind = m->d.bc_kind;
+    a.bc_state = m->d.bc_state;
+    a.W = W;
+    a.X = X;
+    a.dt = dt_dev;
+    a.F = F;
+    a.nonphys = m->w.counters;
+    a.fp.gamma = m->prm.gamma;
+    a.fp.K = 2.0 / (m->prm.gamma - 1.0) - 2.0;
+    a.fp.mu = m->prm.mu;
+    a.fp.eps = m->prm.tau_eps;
+    a.fp.exact_time = m->prm.exact_time;
+    a.fallback = m->prm.nonphys_fallback;
+    const int64_t nthr = 2 * (int64_t)a.nf;
+    PROF(KC_FLUX, hipLaunchKernelGGL(k_flux, dim3(nblocks(nthr, 128)), dim3(128), 0, m->stream, a));
+}
+
+void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn) {
+    const int nt = m->d.nt;
+    PROF(KC_UPDATE, hipLaunchKernelGGL(k_update, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.nf,
+                                       m->d.cface, m->d.area, W, F, Wn, m->prm.gamma, m->w.counters + 1));
+}
+
+void launch_cfl(gks_mesh* m, const double* W, double* dt_out) {
+    const int nt = m->d.nt;
+    const int nb = std::min(1024, nblocks(nt));
+    PROF(KC_CFL, hipLaunchKernelGGL(k_cfl, dim3(nb), dim3(TPB), 0, m->stream, nt, m->d.nf, m->d.cface, m->d.area,
+                                    m->d.fgeo, W, m->prm.gamma, m->w.dtpart));
+    PROF(KC_CFL, hipLaunchKernelGGL(k_cfl_final, dim3(1), dim3(64), 0, m->stream, nb, m->w.dtpart, m->prm.cfl,
+                                    dt_out));
+}
+
+void launch_set_scalar(gks_mesh* m, double* p, double v) {
+    hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, m->stream, p, v);
+}
+
+void launch_zero(gks_mesh* m, double* p, int64_t count) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_zero, dim3(nblocks(count)), dim3(TPB), 0, m->stream, count, p);
+}
+
+__global__ void k_zero_i32(int count, int32_t* p) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0;
+}
+
+void launch_zero_i32(gks_mesh* m, int32_t* p, int count) {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, m->stream, count, p);
+}
+
+void launch_copy(gks_mesh* m, double* dst, const double* src, int64_t count) {
+    if (count <= 0) return;
+    hipLaunchKernelGGL(k_copy, dim3(nblocks(count)), dim3(TPB), 0, m->stream, count, dst, src);
+}
+
+}  // namespace gks

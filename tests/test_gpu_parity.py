@@ -1,0 +1,245 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Error measure (per the tolerance statement of the build): relative L-inf on
+each conserved component, max_i |gpu - oracle| / max_i |oracle|, maximised
+over the components.  Bars: face fluxes with identical inputs <= 1e-13; FP64
+steps <= 1e-12; reconstruction coefficients within the GMRES tolerance
+times a modest conditioning factor.
+
+Sizes: the 20 x 20 density-advection mesh of the small configuration
+(800 cells, 3 colours, ragged last blocks), walled shock-vortex and
+lid-driven meshes with every boundary kind, and the full 512 x 512 mesh
+(524,288 cells) on sampled faces and by the residual property.
+"""
+import numpy as np
+import pytest
+
+import gks_inputs as gi
+from oracle import cls as ocls
+from oracle import scheme
+
+torch = pytest.importorskip("torch")
+import paper_1802_00704_amd as g  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+def relinf(a, ref):
+    a = np.asarray(a)
+    ref = np.asarray(ref)
+    out = 0.0
+    for q in range(ref.shape[0]):
+        den = np.abs(ref[q]).max()
+        num = np.abs(a[q] - ref[q]).max()
+        out = max(out, num / den if den > 0 else num)
+    return out
+
+
+def dev(a):
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
+
+
+def sv_mesh(nx=12, ny=6, seed=3):
+    left, _ = gi.shock_vortex_states()
+    return gi.jss_mesh(nx, ny, seed, Lx=2.0, Ly=1.0, periodic=False,
+                       walls=((gi.BC_INFLOW, left), (gi.BC_OUTFLOW, None), (gi.BC_SLIP, None), (gi.BC_SLIP, None)))
+
+
+def cavity_mesh(n=8, seed=4):
+    walls = ((gi.BC_NOSLIP, (0.0, 0.0, 0.0, 0.0)),) * 3 + ((gi.BC_NOSLIP, (0.0, 1.0, 0.0, 0.0)),)
+    return gi.jss_mesh(n, n, seed, Lx=1.0, Ly=1.0, periodic=False, stretch=1.5, walls=walls)
+
+
+@pytest.fixture(scope="module")
+def adv20():
+    m = gi.jss_mesh(20, 20, 1)
+    return m, gi.density_advection_ic(m), scheme.Solver(m)
+
+
+def test_faces_match(adv20):
+    m, W, s = adv20
+    gm = g.GksMesh(m)
+    own, nbr = gm.faces()
+    assert np.array_equal(own, s.geo.own) and np.array_equal(nbr, s.geo.nbr)
+
+
+def test_flux_parity_small(adv20):
+    m, W, s = adv20
+    X = s.reconstruct(W)
+    dt = scheme.cfl_dt(s.geo, W, s.prm)
+    F_ref = s.flux(W, X, dt)
+    F = g.GksMesh(m).flux(dev(W), dev(X), dt).cpu().numpy()
+    assert relinf(F, F_ref) <= 1e-13
+
+
+@pytest.mark.parametrize("kind", ["shock_vortex", "cavity", "exact_time"])
+def test_flux_parity_boundaries_and_viscous(kind):
+    rng_X = gi.random_coefficients
+    if kind == "cavity":
+        m = cavity_mesh()
+        W = gi.cavity_ic(m)
+        W[1:3] += 0.05 * np.random.default_rng(1).normal(size=(2, m.nt))
+        prm = scheme.Params(mu=1e-3)
+        kw = dict(mu=1e-3)
+    else:
+        m = sv_mesh()
+        W = gi.shock_vortex_ic(m)
+        prm = scheme.Params(exact_time=(kind == "exact_time"))
+        kw = dict(exact_time=int(kind == "exact_time"))
+    s = scheme.Solver(m, prm)
+    X = rng_X(m.nt, seed=5, scale=0.02)
+    X[:, 2:, s.k == 1] = 0.0
+    dt = 2e-3
+    F_ref = s.flux(W, X, dt)
+    F = g.GksMesh(m, **kw).flux(dev(W), dev(X), dt).cpu().numpy()
+    assert relinf(F, F_ref) <= 1e-13
+
+
+def test_reconstruct_parity_small(adv20):
+    m, W, s = adv20
+    X_ref = s.reconstruct(W)
+    Xg, info = g.GksMesh(m, tol=1e-12).reconstruct(dev(W))
+    Xg = Xg.cpu().numpy()
+    R = s.rhs(W)
+    res = ocls.residual(s.K, R, Xg)
+    assert res.max() <= 1e-12 * 1.01
+    assert max(info["rel_resid"]) <= 1e-12
+    assert relinf(Xg, X_ref) <= 1e-10
+
+
+def test_step_parity_config1(adv20):
+    """Small configuration in full: 20 x 20, 10 steps, CFL 0.5, GMRES tol 1e-12."""
+    m, W, s = adv20
+    gm = g.GksMesh(m, tol=1e-12)
+    Wt = dev(W)
+    Wr = W.copy()
+    for _ in range(10):
+        used, info = gm.step(Wt)
+        Wr, dtr = s.step(Wr)
+        assert used == pytest.approx(dtr, rel=1e-14)
+    assert relinf(Wt.cpu().numpy(), Wr) <= 1e-12
+
+
+def test_rcm_and_multicolour_orders_agree(adv20):
+    m, W, s = adv20
+    out = []
+    for order in (g.GKS_ORDER_MULTICOLOR, g.GKS_ORDER_RCM):
+        gm = g.GksMesh(m, tol=1e-12, ordering=order)
+        Wt = dev(W)
+        for _ in range(3):
+            gm.step(Wt)
+        out.append(Wt.cpu().numpy())
+    Wr, _ = s.run(W, 3)
+    assert relinf(out[0], Wr) <= 1e-12
+    assert relinf(out[1], Wr) <= 1e-12
+
+
+@pytest.mark.parametrize("case", ["shock_vortex", "cavity"])
+def test_step_parity_walled(case):
+    if case == "cavity":
+        m = cavity_mesh(10)
+        W = gi.cavity_ic(m)
+        prm, kw = scheme.Params(mu=1e-3), dict(mu=1e-3)
+        nsteps = 4
+    else:
+        m = sv_mesh(24, 12)
+        W = gi.shock_vortex_ic(m)
+        prm, kw = scheme.Params(), {}
+        nsteps = 3
+    s = scheme.Solver(m, prm)
+    gm = g.GksMesh(m, tol=1e-12, **kw)
+    Wt = dev(W)
+    Wr = W.copy()
+    for _ in range(nsteps):
+        gm.step(Wt)
+        Wr, _ = s.step(Wr)
+    assert relinf(Wt.cpu().numpy(), Wr) <= 1e-12
+
+
+def test_conservation_and_free_stream_on_gpu():
+    m = gi.jss_mesh(32, 32, 9)
+    W = gi.density_advection_ic(m)
+    gm = g.GksMesh(m)
+    area = g.host_inspect(m)["area"]
+    Wt = dev(W)
+    for _ in range(5):
+        gm.step(Wt)
+    tot0 = (W * area).sum(axis=1)
+    tot = (Wt.cpu().numpy() * area).sum(axis=1)
+    assert np.abs(tot - tot0).max() <= 1e-13 * np.abs(tot0).max()
+    Wu = gi.prim_to_cons(np.full(m.nt, 1.2), 0.3, -0.7, 0.9, 1.4)
+    Wt = dev(Wu)
+    gm.step(Wt)
+    assert np.abs(Wt.cpu().numpy() - Wu).max() <= 1e-13
+
+
+def test_zero_rhs_columns_and_errors():
+    m = gi.jss_mesh(8, 8, 2)
+    gm = g.GksMesh(m)
+    W = gi.prim_to_cons(np.full(m.nt, 1.0), 0.0, 0.0, 1.0, 1.4)   # uniform: R = 0
+    X, info = gm.reconstruct(dev(W))
+    assert np.abs(X.cpu().numpy()).max() == 0.0
+    with pytest.raises(g.NonConvergence):
+        g.GksMesh(m, tol=1e-30, max_iter=2).reconstruct(dev(gi.density_advection_ic(m)))
+    Wbad = gi.density_advection_ic(m)
+    Wbad[0, 5] = -1.0
+    Wt = dev(Wbad)
+    before = Wt.clone()
+    with pytest.raises(g.NonPhysical):
+        gm.step(Wt)
+    assert torch.equal(Wt, before)
+
+
+@pytest.fixture(scope="module")
+def adv512():
+    m = gi.jss_mesh(512, 512, 2)
+    return m, gi.density_advection_ic(m)
+
+
+def test_full_size_flux_sampled(adv512):
+    """512 x 512 (524,288 cells): seeded coefficients, all faces on the GPU,
+    a seeded sample of faces on the oracle."""
+    m, W = adv512
+    from oracle.mesh import build_geometry
+    geo = build_geometry(m)
+    X = gi.random_coefficients(m.nt, seed=11, scale=0.002)
+    dt = 1e-3
+    F = g.GksMesh(m).flux(dev(W), dev(X), dt).cpu().numpy()
+    faces = np.random.default_rng(3).choice(geo.nf, 3000, replace=False)
+    F_ref = scheme.face_fluxes(geo, W, X, dt, scheme.Params(), faces=faces)
+    assert relinf(F[:, faces], F_ref) <= 1e-13
+
+
+def test_full_size_reconstruct_residual(adv512):
+    """512 x 512 at the bench tolerance 1e-10: the true relative residual of
+    the GPU coefficients in the oracle's own normal equations."""
+    m, W = adv512
+    from oracle.mesh import build_geometry
+    geo = build_geometry(m)
+    K, pairs = ocls.assemble(geo)
+    R = ocls.rhs(geo, pairs, W)
+    X, info = g.GksMesh(m, tol=1e-10).reconstruct(dev(W))
+    res = ocls.residual(K, R, X.cpu().numpy())
+    assert res.max() <= 1e-10 * 1.01
+
+
+@pytest.mark.parametrize("case", ["advection", "shock_vortex"])
+def test_mixed_precision_step_parity(case):
+    """FP32 inner sweeps inside FP64 flexible GMRES: W within 1e-9 of the
+    oracle and the true residual at the requested 1e-10."""
+    if case == "advection":
+        m = gi.jss_mesh(24, 24, 7)
+        W = gi.density_advection_ic(m)
+    else:
+        m = sv_mesh(24, 12)
+        W = gi.shock_vortex_ic(m)
+    s = scheme.Solver(m)
+    gm = g.GksMesh(m, tol=1e-10, precision=g.GKS_MIXED)
+    Wt = dev(W)
+    Wr = W.copy()
+    for _ in range(3):
+        used, info = gm.step(Wt)
+        assert max(info["rel_resid"]) <= 1e-10
+        Wr, _ = s.step(Wr, used)
+    assert relinf(Wt.cpu().numpy(), Wr) <= 1e-9

@@ -1,0 +1,166 @@
+"""CPU checks of the library's host side (no GPU needed).
+
+* libgks.so loads and exports every function include/gks.h declares.
+* gks_host_inspect: faces, cell areas and h equal the oracle's; the
+  normal-equation matrix equals the oracle's assembly entry by entry; the
+  renumbering is a permutation whose levels respect the sweep dependencies;
+  the BILU(0) factors reproduce K on its pattern ((L + I)(D + U) = K there).
+* Invalid meshes are rejected with GKS_EINVAL.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import gks_inputs as gi
+import paper_1802_00704_amd as g
+from paper_1802_00704_amd import _lib
+from oracle import cls
+from oracle.mesh import build_geometry
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "gks.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(gks_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_function():
+    L = g.lib()
+    names = header_functions()
+    assert len(names) >= 13
+    for name in names:
+        assert hasattr(L, name), name
+    assert set(names) == set(_lib.EXPORTS)
+
+
+def meshes():
+    yield "periodic", gi.jss_mesh(9, 7, 4, Lx=2.0, Ly=1.5)
+    yield "walled", gi.jss_mesh(8, 5, 6, Lx=2.0, Ly=1.0, periodic=False,
+                                walls=((gi.BC_INFLOW, (1.0, 1.3, 0.0, 1.0)), (gi.BC_OUTFLOW, None),
+                                       (gi.BC_SLIP, None), (gi.BC_SLIP, None)))
+    yield "stretched", gi.jss_mesh(8, 8, 7, Lx=1.0, Ly=1.0, periodic=False, stretch=1.5,
+                                   walls=((gi.BC_NOSLIP, (0, 0, 0, 0)),) * 3 + ((gi.BC_NOSLIP, (0, 1, 0, 0)),))
+
+
+def to_cell_order(hs):
+    """K of the library as a scipy matrix in cell order."""
+    nt = hs["nt"]
+    perm = hs["perm"]
+    rows, cols, vals = [], [], []
+    for s in range(4):
+        for i in range(nt):
+            j = hs["kcol"][s, i]
+            if j == nt:
+                continue
+            blk = hs["kval"][s, :, i].reshape(5, 5)
+            oi, oj = perm[i], perm[j]
+            r, c = np.meshgrid(5 * oi + np.arange(5), 5 * oj + np.arange(5), indexing="ij")
+            rows.append(r.ravel())
+            cols.append(c.ravel())
+            vals.append(blk.ravel())
+    return sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                         shape=(5 * nt, 5 * nt)).tocsr()
+
+
+@pytest.mark.parametrize("name,mesh", list(meshes()))
+@pytest.mark.parametrize("ordering", [g.GKS_ORDER_MULTICOLOR, g.GKS_ORDER_RCM])
+def test_host_system_matches_oracle(name, mesh, ordering):
+    hs = g.host_inspect(mesh, ordering=ordering)
+    geo = build_geometry(mesh)
+    assert hs["nt"] == geo.nt and hs["nf"] == geo.nf
+    assert np.array_equal(hs["own"], geo.own)
+    exp_nbr = np.where(geo.nbr >= 0, geo.nbr, -geo.tag)
+    assert np.array_equal(hs["nbr"], exp_nbr)
+    assert np.allclose(hs["area"], geo.area, rtol=1e-14)
+    assert np.allclose(hs["h"], geo.h, rtol=1e-14)
+    K_ref, _ = cls.assemble(geo)
+    K = to_cell_order(hs)
+    diff = abs(K - K_ref).max()
+    assert diff <= 1e-14 * abs(K_ref).max()
+
+
+@pytest.mark.parametrize("ordering", [g.GKS_ORDER_MULTICOLOR, g.GKS_ORDER_RCM])
+def test_ordering_and_levels(ordering):
+    mesh = gi.jss_mesh(12, 10, 3)
+    hs = g.host_inspect(mesh, ordering=ordering)
+    nt = hs["nt"]
+    perm = hs["perm"]
+    assert np.array_equal(np.sort(perm), np.arange(nt))
+    lev = np.zeros(nt, dtype=int)
+    lp = hs["lev_ptr"]
+    assert lp[0] == 0 and lp[-1] == nt and np.all(np.diff(lp) >= 0)
+    for l in range(len(lp) - 1):
+        lev[lp[l]:lp[l + 1]] = l
+    # every strict-lower entry comes from an earlier level, every strict-upper one from a later level
+    for s in range(3):
+        for i in range(nt):
+            k = hs["lcol"][s, i]
+            if k != nt:
+                assert k < i and lev[k] < lev[i]
+            j = hs["ucol"][s, i]
+            if j != nt:
+                assert j > i and lev[j] > lev[i]
+    if ordering == g.GKS_ORDER_MULTICOLOR:
+        assert 2 <= hs["n_colors"] <= 4 and hs["n_levels"] == hs["n_colors"]
+    else:
+        assert hs["n_levels"] > 4
+
+
+@pytest.mark.parametrize("ordering", [g.GKS_ORDER_MULTICOLOR, g.GKS_ORDER_RCM])
+def test_bilu0_reproduces_K_on_its_pattern(ordering):
+    mesh = gi.jss_mesh(8, 6, 5, Lx=1.0, Ly=1.0, periodic=False)
+    hs = g.host_inspect(mesh, ordering=ordering)
+    nt = hs["nt"]
+    blk = lambda arr, s, i: arr[s, :, i].reshape(5, 5)
+    L = {}
+    U = {}
+    D = {}
+    for i in range(nt):
+        D[i] = np.linalg.inv(hs["dinv"][:, i].reshape(5, 5))
+        for s in range(3):
+            if hs["lcol"][s, i] != nt:
+                L[(i, hs["lcol"][s, i])] = blk(hs["lval"], s, i)
+            if hs["ucol"][s, i] != nt:
+                U[(i, hs["ucol"][s, i])] = blk(hs["uval"], s, i)
+    # (I + L)(D + U) restricted to the pattern of K
+    upper = lambda k, j: D[k] if k == j else U.get((k, j))
+    worst = 0.0
+    scale = np.abs(hs["kval"]).max()
+    for i in range(nt):
+        for s in range(4):
+            j = hs["kcol"][s, i]
+            if j == nt:
+                continue
+            M = upper(i, j).copy() if upper(i, j) is not None else np.zeros((5, 5))
+            for (a, k), Lik in L.items():
+                if a != i:
+                    continue
+                ukj = upper(k, j)
+                if ukj is not None:
+                    M += Lik @ ukj
+            worst = max(worst, np.abs(M - blk(hs["kval"], s, i)).max())
+    assert worst < 1e-13 * scale
+
+
+def test_invalid_meshes_are_rejected():
+    m = gi.jss_mesh(4, 4, 1)
+    bad = gi.Mesh(xy=m.xy, tri=m.tri[:, ::-1].copy(), edge_tag=m.edge_tag, periodic=m.periodic, L=m.L)
+    with pytest.raises(g.GksError) as e:
+        g.host_inspect(bad)
+    assert e.value.code == _lib.GKS_EINVAL and "clockwise" in str(e.value)
+    walled = gi.jss_mesh(4, 4, 1, periodic=False)
+    untagged = gi.Mesh(xy=walled.xy, tri=walled.tri, edge_tag=np.zeros_like(walled.edge_tag),
+                       periodic=(False, False), L=walled.L, bc_table=walled.bc_table)
+    with pytest.raises(g.GksError):
+        g.host_inspect(untagged)
+    nonmanifold = gi.Mesh(xy=m.xy, tri=np.concatenate([m.tri, m.tri[:1]]), edge_tag=np.zeros((m.nt + 1, 3), np.int32),
+                          periodic=m.periodic, L=m.L)
+    with pytest.raises(g.GksError):
+        g.host_inspect(nonmanifold)
+    with pytest.raises(g.GksError):
+        g.host_inspect(m, restart=0)
