@@ -1,0 +1,207 @@
+"""Throughput benchmark of the third-order gas-kinetic step on one MI355X.
+
+One step = CFL time step + CLS reconstruction solve (to relative residual
+1e-10) + Gauss-point BGK fluxes + finite-volume update, i.e. one pass of
+the whole hot path, on seeded synthetic input already resident in HBM.
+
+Default workload: the shock-vortex interaction on the jittered split-square
+mesh of 1000 x 500 squares on [0, 2] x [0, 1] (1,000,000 triangles), run in
+the mixed form (FP64 flexible GMRES with FP32 inner BILU(0)/SpMV sweeps) and
+in the plain FP64 form.  The headline value is the mixed form's
+cell-steps/s; the FP64 form is reported beside it.
+
+Prints ONE JSON line.  The roofline entry is for the kernel class with the
+largest share of the timed region, measured with HIP events on the
+library's stream during the timed steps; the CPU baseline is the oracle on a
+bounded sample of the same workload family.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "cell-steps/s at 1M tris, mixed vs FP64 at resid 1e-10; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+FP64_VALU_PEAK_TFLOPS = 78.6
+
+
+def workload(name: str):
+    import gks_inputs as gi
+    if name == "shock_vortex_1m":
+        left, _ = gi.shock_vortex_states()
+        walls = ((gi.BC_INFLOW, left), (gi.BC_OUTFLOW, None), (gi.BC_SLIP, None), (gi.BC_SLIP, None))
+        m = gi.jss_mesh(1000, 500, 3, Lx=2.0, Ly=1.0, periodic=False, walls=walls)
+        W = gi.shock_vortex_ic(m)
+        desc = ("shock-vortex (Ma 1.1 stationary shock, vortex 0.3/0.05), JSS 1000x500 on [0,2]x[0,1], "
+                "1,000,000 triangles, inviscid, CFL 0.5, CLS tol 1e-10")
+        return m, W, desc, {}
+    if name == "advection_512":
+        m = gi.jss_mesh(512, 512, 2)
+        W = gi.density_advection_ic(m)
+        desc = "density advection, periodic JSS 512x512 on [0,2]^2, 524,288 triangles, CFL 0.5, CLS tol 1e-10"
+        return m, W, desc, {}
+    raise SystemExit("unknown workload %r" % name)
+
+
+def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
+    """The oracle (plain FP64 NumPy/SciPy, single thread) on a bounded sample:
+    the same workload family on a smaller mesh, timed over whole steps."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    import gks_inputs as gi
+    from oracle import scheme
+    if name == "shock_vortex_1m":
+        left, _ = gi.shock_vortex_states()
+        walls = ((gi.BC_INFLOW, left), (gi.BC_OUTFLOW, None), (gi.BC_SLIP, None), (gi.BC_SLIP, None))
+        m = gi.jss_mesh(100, 50, 3, Lx=2.0, Ly=1.0, periodic=False, walls=walls)
+        W = gi.shock_vortex_ic(m)
+        sample = "shock-vortex JSS 100x50 (10,000 triangles), same family at 10x coarser h"
+        prm = scheme.Params(fallback=True)
+    else:
+        m = gi.jss_mesh(64, 64, 2)
+        W = gi.density_advection_ic(m)
+        sample = "density advection JSS 64x64 (8,192 triangles)"
+        prm = scheme.Params()
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        s = scheme.Solver(m, prm)
+        s.step(W)  # factorisation of the CLS matrix (setup, not timed)
+        steps = 0
+        t0 = time.perf_counter()
+        while True:
+            W, _ = s.step(W)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el >= budget_s or steps >= 50:
+                break
+    finally:
+        if ctx is not None:
+            ctx.unregister() if hasattr(ctx, "unregister") else None
+    return {"value": m.nt * steps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%s, %d steps in %.1f s" % (sample, steps, el)}
+
+
+def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool):
+    import torch
+    import paper_1802_00704_amd as g
+    t0 = time.perf_counter()
+    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    W = torch.tensor(W0, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        gm.step(W)
+    torch.cuda.synchronize()
+    if profile:
+        gm.profile(True)
+    lat = []
+    iters = []
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        t = time.perf_counter()
+        used, info = gm.step(W)
+        lat.append(time.perf_counter() - t)
+        iters.append(max(info["iters"]))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof = gm.profile_get() if profile else {}
+    gm.profile(False)
+    stats = gm.stats()
+    gm.close()
+    lat_ms = np.array(lat) * 1e3
+    return {
+        "value": m.nt * steps / elapsed,
+        "ms_per_step": elapsed * 1e3 / steps,
+        "step_ms_p50": float(np.percentile(lat_ms, 50)),
+        "step_ms_p99": float(np.percentile(lat_ms, 99)),
+        "krylov_iters_per_step": float(np.mean(iters)),
+        "setup_s": setup_s,
+        "stats": stats,
+        "profile": prof,
+        "elapsed_s": elapsed,
+    }
+
+
+def roofline(prof: dict, elapsed_s: float):
+    if not prof:
+        return None
+    tot = sum(v["ms"] for v in prof.values())
+    name, d = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    if d["ms"] <= 0 or d["bytes"] <= 0:
+        return None
+    achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+    shares = {k: round(v["ms"] / tot, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]) if v["ms"] > 0}
+    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 2),
+            "bytes_per_launch": d["bytes"] / max(1, d["launches"]),
+            "time_share": shares, "kernel_time_fraction_of_steps": round(tot * 1e-3 / elapsed_s, 4)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="shock_vortex_1m", choices=["shock_vortex_1m", "advection_512"])
+    ap.add_argument("--forms", default="mixed,fp64")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one MI355X only; multi-GPU runs are not part of this build "
+              "(requested --gpus %d)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1802_00704_amd as g
+    m, W0, desc, _ = workload(args.workload)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    res = {}
+    for f in forms:
+        prec = g.GKS_MIXED if f == "mixed" else g.GKS_FP64
+        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile)
+        print("# %s: %.4g cell-steps/s, %.3f ms/step, %.1f Krylov iterations/step" %
+              (f, res[f]["value"], res[f]["ms_per_step"], res[f]["krylov_iters_per_step"]), file=sys.stderr,
+              flush=True)
+    head = forms[0]
+    r = res[head]
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload)
+    out = {
+        "metric": METRIC,
+        "value": r["value"],
+        "unit": "cell-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32" if head == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "form": head,
+                   "solver": "multicolour BILU(0); FP64 FGMRES(30) with 4 FP32 inner sweeps" if head == "mixed"
+                   else "multicolour BILU(0); FP64 GMRES(30)",
+                   "cells": m.nt},
+        "roofline": roofline(r["profile"], r["elapsed_s"]),
+        "cpu_baseline": cpu,
+        "forms": {f: {k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s")}
+                  for f in forms},
+        "latency_ms": {"step_p50": r["step_ms_p50"], "step_p99": r["step_ms_p99"]},
+        "device": torch.cuda.get_device_name(0),
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

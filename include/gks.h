@@ -172,10 +172,15 @@ int gks_faces(const gks_mesh* m, int32_t* own, int32_t* nbr);
 int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st);
 
 /* Per-kernel timing with HIP events on the handle's stream (enable = 1
- * resets and starts; 0 stops).  gks_profile_get copies up to n entries:
- * name (static string), number of launches, total milliseconds. */
+ * resets and starts; 0 stops).  gks_profile_get copies up to n entries per
+ * kernel class: name (static string), number of launches, total
+ * milliseconds and total algorithmic bytes (the bytes the launches must
+ * move: stored matrix blocks and indices, each input block read once and
+ * each output block written once).  Any output pointer may be NULL.
+ * Returns the number of classes copied or a negative error. */
 int gks_profile_enable(gks_mesh* m, int enable);
-int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms);
+int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms,
+                    double* total_bytes);
 
 /* Host-only view of the per-mesh state that gks_mesh_create builds (no
  * device is touched), for inspection and tests: faces, cell measures, the

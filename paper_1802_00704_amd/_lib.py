@@ -103,7 +103,7 @@ def lib():
         L.gks_profile_enable.argtypes = [vp, C.c_int]
         L.gks_profile_enable.restype = C.c_int
         L.gks_profile_get.argtypes = [vp, C.c_int, C.POINTER(C.c_char_p), C.POINTER(C.c_int64),
-                                      C.POINTER(C.c_double)]
+                                      C.POINTER(C.c_double), C.POINTER(C.c_double)]
         L.gks_profile_get.restype = C.c_int
         L.gks_host_inspect.argtypes = [C.POINTER(MeshDesc), C.POINTER(Params), C.POINTER(HostSystem)]
         L.gks_host_inspect.restype = C.c_int
@@ -269,7 +269,9 @@ class GksMesh:
         names = (C.c_char_p * n)()
         launches = (C.c_int64 * n)()
         ms = (C.c_double * n)()
-        k = lib().gks_profile_get(self._h, n, names, launches, ms)
+        by = (C.c_double * n)()
+        k = lib().gks_profile_get(self._h, n, names, launches, ms, by)
         if k < 0:
             _check(k, self._h)
-        return {names[i].decode(): (int(launches[i]), float(ms[i])) for i in range(k) if names[i]}
+        return {names[i].decode(): {"launches": int(launches[i]), "ms": float(ms[i]), "bytes": float(by[i])}
+                for i in range(k) if names[i]}

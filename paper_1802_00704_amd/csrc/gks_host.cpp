@@ -4,6 +4,7 @@
 
 #include <algorithm>
 #include <array>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -21,6 +22,20 @@ using namespace gks;
 namespace {
 
 thread_local std::string g_create_err;
+
+// GKS_VERBOSE=1 prints the duration of each setup phase to stderr.
+struct PhaseTimer {
+    bool on;
+    std::chrono::steady_clock::time_point t0;
+    PhaseTimer() : on(std::getenv("GKS_VERBOSE") != nullptr), t0(std::chrono::steady_clock::now()) {}
+    void mark(const char* what) {
+        if (!on) return;
+        const auto t1 = std::chrono::steady_clock::now();
+        std::fprintf(stderr, "[gks] %-22s %8.1f ms\n", what,
+                     std::chrono::duration<double, std::milli>(t1 - t0).count());
+        t0 = t1;
+    }
+};
 
 struct Fail {
     int code;
@@ -117,13 +132,23 @@ void build_host_mesh(const gks_mesh_desc* de, const gks_params* prm, HostMesh& h
     hm.Ixy.resize(nt);
     hm.Iyy.resize(nt);
     hm.h.resize(nt);
+    int bad_tri = -1, bad_kind = 0;
+#pragma omp parallel for schedule(static)
     for (int t = 0; t < nt; ++t) {
         int v[3];
+        bool ok = true;
         for (int k = 0; k < 3; ++k) {
             v[k] = de->tri[3 * (size_t)t + k];
-            if (v[k] < 0 || v[k] >= nv) throw Fail{GKS_EINVAL, "triangle vertex index out of range"};
+            if (v[k] < 0 || v[k] >= nv) ok = false;
         }
-        if (v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) throw Fail{GKS_EINVAL, "degenerate triangle"};
+        if (!ok || v[0] == v[1] || v[1] == v[2] || v[0] == v[2]) {
+#pragma omp critical
+            if (bad_tri < 0 || t < bad_tri) {
+                bad_tri = t;
+                bad_kind = 1;
+            }
+            continue;
+        }
         const double x0 = de->xy[2 * (size_t)v[0]], y0 = de->xy[2 * (size_t)v[0] + 1];
         double xs[3], ys[3];
         for (int k = 0; k < 3; ++k) {
@@ -133,7 +158,14 @@ void build_host_mesh(const gks_mesh_desc* de, const gks_params* prm, HostMesh& h
             hm.vy[3 * (size_t)t + k] = ys[k];
         }
         const double a = 0.5 * ((xs[1] - xs[0]) * (ys[2] - ys[0]) - (xs[2] - xs[0]) * (ys[1] - ys[0]));
-        if (!(a > 0.0)) throw Fail{GKS_EINVAL, "triangle " + std::to_string(t) + " is clockwise or degenerate"};
+        if (!(a > 0.0)) {
+#pragma omp critical
+            if (bad_tri < 0 || t < bad_tri) {
+                bad_tri = t;
+                bad_kind = 2;
+            }
+            continue;
+        }
         const double cx = (xs[0] + xs[1] + xs[2]) / 3.0, cy = (ys[0] + ys[1] + ys[2]) / 3.0;
         double ixx = 0, ixy = 0, iyy = 0;
         for (int k = 0; k < 3; ++k) {
@@ -152,6 +184,10 @@ void build_host_mesh(const gks_mesh_desc* de, const gks_params* prm, HostMesh& h
         hm.Ixy[t] = ixy / 12.0;
         hm.Iyy[t] = iyy / 12.0;
         hm.h[t] = std::max(rad, std::sqrt(a));
+    }
+    if (bad_tri >= 0) {
+        if (bad_kind == 1) throw Fail{GKS_EINVAL, "triangle " + std::to_string(bad_tri) + " has an invalid or repeated vertex"};
+        throw Fail{GKS_EINVAL, "triangle " + std::to_string(bad_tri) + " is clockwise or degenerate"};
     }
 
     // edges -> neighbours
@@ -293,39 +329,36 @@ struct Assembly {
     std::vector<std::array<std::array<double, 5>, 3>> a0;  // [nt][slot]
 };
 
+// Row i of the normal equations gathers the rows of the pairs (i, j) (cell i
+// reconstructed, blocks A_ij, B_ij) and (j, i) (cell i as the neighbour,
+// blocks A_ji, B_ji) over its face neighbours j:
+//   K_ii = sum_j A_ij^T A_ij + B_ji^T B_ji,   K_ij = -A_ij^T B_ij - B_ji^T A_ji.
 void assemble(const HostMesh& hm, double w, Assembly& as) {
     const int nt = hm.nt;
-    as.diag.assign(nt, bzero());
-    as.off.assign(nt, {bzero(), bzero(), bzero()});
-    as.a0.assign(nt, {});
-    for (int i = 0; i < nt; ++i)
-        for (int s = 0; s < 3; ++s) as.a0[i][s].fill(0.0);
-    auto slot_of = [&](int i, int j) {
-        for (int s = 0; s < 3; ++s)
-            if (hm.nb[i][s] == j) return s;
-        return -1;
-    };
-    for (int i = 0; i < nt; ++i)
+    as.diag.resize(nt);
+    as.off.resize(nt);
+    as.a0.resize(nt);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < nt; ++i) {
+        Blk d = bzero();
         for (int s = 0; s < 3; ++s) {
+            as.off[i][s] = bzero();
+            as.a0[i][s].fill(0.0);
             const int j = hm.nb[i][s];
             if (j < 0) continue;
-            double A[6][5], B[6][5];
+            double A[6][5], B[6][5], Aj[6][5], Bj[6][5];
             pair_blocks(hm, i, j, w, A, B);
-            const Blk AtA = atb(A, A, 1.0), AtB = atb(A, B, 1.0), BtB = atb(B, B, 1.0);
-            const int sj = slot_of(j, i);
-            for (int e = 0; e < 25; ++e) {
-                as.diag[i][e] += AtA[e];
-                as.off[i][s][e] -= AtB[e];
-                as.diag[j][e] += BtB[e];
-            }
-            // K_ji -= B^T A = (A^T B)^T
+            pair_blocks(hm, j, i, w, Aj, Bj);
+            const Blk AtA = atb(A, A, 1.0), AtB = atb(A, B, 1.0), BjtBj = atb(Bj, Bj, 1.0), AjtBj = atb(Aj, Bj, 1.0);
+            for (int e = 0; e < 25; ++e) d[e] += AtA[e] + BjtBj[e];
             for (int k = 0; k < 5; ++k)
-                for (int l = 0; l < 5; ++l) as.off[j][sj][k * 5 + l] -= AtB[l * 5 + k];
+                for (int l = 0; l < 5; ++l) as.off[i][s][k * 5 + l] = -AtB[k * 5 + l] - AjtBj[l * 5 + k];
             for (int l = 0; l < 5; ++l) as.a0[i][s][l] = A[0][l];
         }
-    for (int i = 0; i < nt; ++i)
         if (hm.kord[i] == 1)
-            for (int l = 2; l < 5; ++l) as.diag[i][l * 5 + l] += 1.0;
+            for (int l = 2; l < 5; ++l) d[l * 5 + l] += 1.0;
+        as.diag[i] = d;
+    }
 }
 
 // ------------------------------------------------------------------ orderings
@@ -457,11 +490,14 @@ std::vector<float> to32(const std::vector<double>& v) {
 }
 
 void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S) {
+    PhaseTimer pt;
     HostMesh& hm = S.hm;
     build_host_mesh(de, &prm, hm);
+    pt.mark("geometry + faces");
     const int nt = hm.nt, nf = hm.nf;
     Assembly as;
     assemble(hm, prm.cls_w, as);
+    pt.mark("CLS assembly");
 
     // renumbering
     const std::vector<int> rcm = rcm_order(hm);
@@ -514,6 +550,7 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     for (int l = 0; l < nkeys; ++l) S.lev_ptr[l + 1] += S.lev_ptr[l];
     S.n_levels = nkeys;
 
+    pt.mark("ordering");
     // matrix in solver order: slot 0 diagonal, then neighbours, padded with the dummy row
     const int n = nt;
     std::vector<double>& Kval = S.Kval;
@@ -524,6 +561,7 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     a0.assign((size_t)3 * 5 * n, 0.0);
     std::vector<int32_t>& rnb = S.rnb;
     rnb.assign((size_t)3 * n, 0);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         const int o = perm[i];
         Kcol[i] = i;
@@ -538,51 +576,64 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         }
     }
 
-    // BILU(0) in solver order (row-wise IKJ elimination restricted to the pattern)
-    struct Row {
-        int nz;
-        int col[4];
-        Blk v[4];
-    };
-    std::vector<Row> rows(n);
+    pt.mark("ELL matrix");
+    // BILU(0) in solver order: row-wise IKJ elimination restricted to the
+    // pattern.  Rows of one level only read rows of earlier levels, so each
+    // level is factored in parallel.
+    std::vector<Blk> rv((size_t)KW * n);
+    std::vector<int> rc((size_t)KW * n), rnz(n);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
-        Row& r = rows[i];
-        r.nz = 0;
-        for (int s = 0; s < KW; ++s) {
-            const int c = Kcol[(size_t)s * n + i];
+        int nz = 0;
+        for (int s2 = 0; s2 < KW; ++s2) {
+            const int c = Kcol[(size_t)s2 * n + i];
             if (c == n) continue;
-            r.col[r.nz] = c;
-            for (int e = 0; e < 25; ++e) r.v[r.nz][e] = Kval[((size_t)s * 25 + e) * n + i];
-            r.nz++;
+            rc[(size_t)KW * i + nz] = c;
+            Blk& dst = rv[(size_t)KW * i + nz];
+            for (int e = 0; e < 25; ++e) dst[e] = Kval[((size_t)s2 * 25 + e) * n + i];
+            ++nz;
         }
-        // sort by column
-        for (int a = 1; a < r.nz; ++a)
-            for (int b = a; b > 0 && r.col[b - 1] > r.col[b]; --b) {
-                std::swap(r.col[b - 1], r.col[b]);
-                std::swap(r.v[b - 1], r.v[b]);
+        for (int a = 1; a < nz; ++a)
+            for (int b = a; b > 0 && rc[(size_t)KW * i + b - 1] > rc[(size_t)KW * i + b]; --b) {
+                std::swap(rc[(size_t)KW * i + b - 1], rc[(size_t)KW * i + b]);
+                std::swap(rv[(size_t)KW * i + b - 1], rv[(size_t)KW * i + b]);
             }
+        rnz[i] = nz;
     }
     std::vector<Blk> dinv(n);
-    for (int i = 0; i < n; ++i) {
-        Row& r = rows[i];
-        for (int a = 0; a < r.nz && r.col[a] < i; ++a) {
-            const int k = r.col[a];
-            r.v[a] = bmul(r.v[a], dinv[k]);  // L_ik = A_ik U_kk^{-1}
-            const Row& rk = rows[k];
-            for (int b = 0; b < r.nz; ++b) {
-                const int j = r.col[b];
-                if (j <= k) continue;
-                for (int q = 0; q < rk.nz; ++q)
-                    if (rk.col[q] == j) {
-                        const Blk t = bmul(r.v[a], rk.v[q]);
-                        for (int e = 0; e < 25; ++e) r.v[b][e] -= t[e];
-                    }
+    int singular = -1;
+    for (size_t l = 0; l + 1 < S.lev_ptr.size(); ++l) {
+#pragma omp parallel for schedule(static)
+        for (int i = S.lev_ptr[l]; i < S.lev_ptr[l + 1]; ++i) {
+            const int* ci = &rc[(size_t)KW * i];
+            Blk* vi = &rv[(size_t)KW * i];
+            const int nz = rnz[i];
+            for (int a = 0; a < nz && ci[a] < i; ++a) {
+                const int k = ci[a];
+                vi[a] = bmul(vi[a], dinv[k]);  // L_ik = A_ik U_kk^{-1}
+                const int* ck = &rc[(size_t)KW * k];
+                const Blk* vk = &rv[(size_t)KW * k];
+                for (int b2 = 0; b2 < nz; ++b2) {
+                    const int j = ci[b2];
+                    if (j <= k) continue;
+                    for (int q = 0; q < rnz[k]; ++q)
+                        if (ck[q] == j) {
+                            const Blk t = bmul(vi[a], vk[q]);
+                            for (int e = 0; e < 25; ++e) vi[b2][e] -= t[e];
+                        }
+                }
+            }
+            int dpos = -1;
+            for (int a = 0; a < nz; ++a)
+                if (ci[a] == i) dpos = a;
+            try {
+                dinv[i] = binv(vi[dpos]);
+            } catch (const Fail&) {
+#pragma omp critical
+                singular = i;
             }
         }
-        int dpos = -1;
-        for (int a = 0; a < r.nz; ++a)
-            if (r.col[a] == i) dpos = a;
-        dinv[i] = binv(r.v[dpos]);
+        if (singular >= 0) throw Fail{GKS_EINVAL, "singular pivot block in the CLS matrix"};
     }
     std::vector<double>& Lval = S.Lval;
     std::vector<double>& Uval = S.Uval;
@@ -594,23 +645,26 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     Dv.assign((size_t)25 * n, 0.0);
     Lcol.assign((size_t)LW * n, n);
     Ucol.assign((size_t)LW * n, n);
+#pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
-        const Row& r = rows[i];
+        const int* ci = &rc[(size_t)KW * i];
+        const Blk* vi = &rv[(size_t)KW * i];
         int nl = 0, nu = 0;
-        for (int a = 0; a < r.nz; ++a) {
-            const int c = r.col[a];
+        for (int a = 0; a < rnz[i]; ++a) {
+            const int c = ci[a];
             if (c < i) {
                 Lcol[(size_t)nl * n + i] = c;
-                for (int e = 0; e < 25; ++e) Lval[((size_t)nl * 25 + e) * n + i] = r.v[a][e];
+                for (int e = 0; e < 25; ++e) Lval[((size_t)nl * 25 + e) * n + i] = vi[a][e];
                 ++nl;
             } else if (c > i) {
                 Ucol[(size_t)nu * n + i] = c;
-                for (int e = 0; e < 25; ++e) Uval[((size_t)nu * 25 + e) * n + i] = r.v[a][e];
+                for (int e = 0; e < 25; ++e) Uval[((size_t)nu * 25 + e) * n + i] = vi[a][e];
                 ++nu;
             }
         }
         for (int e = 0; e < 25; ++e) Dv[(size_t)e * n + i] = dinv[i][e];
     }
+    pt.mark("BILU(0)");
     // ---- face / cell arrays in device layout
     std::vector<int32_t>& own = S.own;
     std::vector<int32_t>& nbr = S.nbr;
@@ -1110,13 +1164,16 @@ int gks_profile_enable(gks_mesh* m, int enable) {
         for (int i = 0; i < NPROF; ++i) {
             m->prof.launches[i] = 0;
             m->prof.ms[i] = 0.0;
+            m->prof.bytes[i] = 0.0;
+            m->prof.flops[i] = 0.0;
         }
     }
     m->prof.on = enable != 0;
     return GKS_OK;
 }
 
-int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms) {
+int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms,
+                    double* total_bytes) {
     if (!m) return GKS_EINVAL;
     try {
         prof_collect(m);
@@ -1128,6 +1185,7 @@ int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, d
         if (names) names[i] = kc_names[i];
         if (launches) launches[i] = m->prof.launches[i];
         if (total_ms) total_ms[i] = m->prof.ms[i];
+        if (total_bytes) total_bytes[i] = m->prof.bytes[i];
     }
     return k;
 }

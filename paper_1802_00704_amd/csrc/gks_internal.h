@@ -36,6 +36,8 @@ struct Profile {
     bool on = false;
     int64_t launches[NPROF] = {0};
     double ms[NPROF] = {0};
+    double bytes[NPROF] = {0};    // algorithmic bytes (what each launch must move)
+    double flops[NPROF] = {0};
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> pool;
 };
@@ -174,7 +176,7 @@ void launch_zero(gks_mesh* m, double* p, int64_t count);
 void launch_zero_i32(gks_mesh* m, int32_t* p, int count);
 void launch_copy(gks_mesh* m, double* dst, const double* src, int64_t count);
 
-void prof_begin(gks_mesh* m, int kc);
+void prof_begin(gks_mesh* m, int kc, double bytes = 0.0, double flops = 0.0);
 void prof_end(gks_mesh* m, int kc);
 
 }  // namespace gks

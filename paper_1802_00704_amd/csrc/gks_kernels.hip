@@ -671,8 +671,10 @@ __global__ void k_cfl_final(int nblk, const double* __restrict__ partial, double
 
 // ================================================================== launchers
 
-void prof_begin(gks_mesh* m, int kc) {
+void prof_begin(gks_mesh* m, int kc, double bytes, double flops) {
     if (!m->prof.on) return;
+    m->prof.bytes[kc] += bytes;
+    m->prof.flops[kc] += flops;
     hipEvent_t a, b;
     if (m->prof.pool.size() >= 2) {
         a = m->prof.pool.back();
@@ -693,40 +695,49 @@ void prof_end(gks_mesh* m, int kc) {
     (void)hipEventRecord(m->prof.pending.back().second.second, m->stream);
 }
 
-#define PROF(kc, launch)        \
-    do {                        \
-        prof_begin(m, kc);      \
-        launch;                 \
-        prof_end(m, kc);        \
+// Algorithmic bytes per row of the solver kernels (four columns, FP64
+// vectors of 160 bytes per cell): matrix blocks and indices as stored, each
+// input vector block read once, each output block written once.
+constexpr double VB = CB * 8.0;
+inline double spmv_bytes(int n, int esz, bool resid) { return n * (KW * 25.0 * esz + KW * 4.0 + (resid ? 3 : 2) * VB); }
+inline double ilu_fwd_bytes(int rows, int esz) { return rows * (LW * 25.0 * esz + LW * 4.0 + 3 * VB); }
+inline double ilu_bwd_bytes(int rows, int esz) { return rows * (LW * 25.0 * esz + LW * 4.0 + 25.0 * esz + 3 * VB); }
+
+#define PROFB(kc, bytes, ...)        \
+    do {                             \
+        prof_begin(m, kc, bytes);    \
+        __VA_ARGS__;                 \
+        prof_end(m, kc);             \
     } while (0)
+#define PROF(kc, ...) PROFB(kc, 0.0, __VA_ARGS__)
 
 void launch_rhs(gks_mesh* m, const double* W) {
     const int n = m->d.n;
-    PROF(KC_RHS, hipLaunchKernelGGL(k_rhs, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.perm, m->d.rnb,
+    PROFB(KC_RHS, n * (3 * (4.0 + 40.0) + 4.0 + 4 * 8.0 * 4 + VB), hipLaunchKernelGGL(k_rhs, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.perm, m->d.rnb,
                                     m->d.a0, W, m->d.nt, m->w.R));
 }
 
 void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y) {
     const int n = m->d.n;
-    PROF(KC_SPMV, hipLaunchKernelGGL((k_spmv<double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+    PROFB(KC_SPMV, spmv_bytes(n, 8, false), hipLaunchKernelGGL((k_spmv<double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
                                      m->d.Kval, m->d.Kcol, x, xscale, nullptr, y));
 }
 
 void launch_spmv32(gks_mesh* m, const double* x, const double* xscale, double* y) {
     const int n = m->d.n;
-    PROF(KC_SPMV32, hipLaunchKernelGGL((k_spmv<float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+    PROFB(KC_SPMV32, spmv_bytes(n, 4, false), hipLaunchKernelGGL((k_spmv<float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
                                        m->d.Kval32, m->d.Kcol, x, xscale, nullptr, y));
 }
 
 void launch_resid(gks_mesh* m, const double* x, const double* b, double* y) {
     const int n = m->d.n;
-    PROF(KC_SPMV_RES, hipLaunchKernelGGL((k_spmv<double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+    PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
                                          m->d.Kval, m->d.Kcol, x, nullptr, b, y));
 }
 
 void launch_resid32(gks_mesh* m, const double* x, const double* b, const double* bscale, double* y) {
     const int n = m->d.n;
-    PROF(KC_SPMV32, hipLaunchKernelGGL((k_spmv<float, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+    PROFB(KC_SPMV32, spmv_bytes(n, 4, true), hipLaunchKernelGGL((k_spmv<float, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
                                        m->d.Kval32, m->d.Kcol, x, bscale, b, y));
 }
 
@@ -738,20 +749,20 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         if (fp32)
-            PROF(KC_ILU_FWD32, hipLaunchKernelGGL(k_ilu_fwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+            PROFB(KC_ILU_FWD32, ilu_fwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_fwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
                                                   n, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp));
         else
-            PROF(KC_ILU_FWD, hipLaunchKernelGGL(k_ilu_fwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+            PROFB(KC_ILU_FWD, ilu_fwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_fwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
                                                 n, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         if (fp32)
-            PROF(KC_ILU_BWD32, hipLaunchKernelGGL(k_ilu_bwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+            PROFB(KC_ILU_BWD32, ilu_bwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_bwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
                                                   n, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out));
         else
-            PROF(KC_ILU_BWD, hipLaunchKernelGGL(k_ilu_bwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
+            PROFB(KC_ILU_BWD, ilu_bwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_bwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
                                                 n, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out));
     }
 }
@@ -763,7 +774,7 @@ void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, i
     const int n = m->d.n;
     const int nb = m->w.nblk_red;
     const int nch = (nvec + RED_CHUNK - 1) / RED_CHUNK;
-    PROF(kc, hipLaunchKernelGGL(k_dots, dim3(nb, nch), dim3(TPB), 0, m->stream, n, V, vstride, nvec, w,
+    PROFB(kc, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_dots, dim3(nb, nch), dim3(TPB), 0, m->stream, n, V, vstride, nvec, w,
                                 m->w.partial));
     const int nval = nvec * NC;
     PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3((nval + 3) / 4), dim3(TPB), 0, m->stream, nval, nb,
@@ -773,20 +784,20 @@ void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, i
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
                  const double* w, double* out) {
     const int n = m->d.n;
-    PROF(KC_AXPY_DOTS, hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
                                           h, scale, w, out));
 }
 
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out) {
     const int n = m->d.n;
-    PROF(KC_COMBINE, hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+    PROFB(KC_COMBINE, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
                                         y, scale, out));
 }
 
 void launch_acc(gks_mesh* m, double* X, const double* z) {
     const int64_t len = (int64_t)m->d.n * CB;
-    PROF(KC_AXPY, hipLaunchKernelGGL(k_acc, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, X, z));
+    PROFB(KC_AXPY, (double)len * 24.0, hipLaunchKernelGGL(k_acc, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, X, z));
 }
 
 void launch_ctl(gks_mesh* m, int mode) {
@@ -800,7 +811,7 @@ void launch_mask_cols(gks_mesh* m, double* X) {
 
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell) {
     const int n = m->d.n;
-    PROF(KC_COPYOUT, hipLaunchKernelGGL(k_copyout, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.nt,
+    PROFB(KC_COPYOUT, (double)n * (4.0 + 2 * VB), hipLaunchKernelGGL(k_copyout, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.nt,
                                         m->d.perm, Xs, Xcell));
 }
 
@@ -827,12 +838,12 @@ void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt
     a.fp.exact_time = m->prm.exact_time;
     a.fallback = m->prm.nonphys_fallback;
     const int64_t nthr = 2 * (int64_t)a.nf;
-    PROF(KC_FLUX, hipLaunchKernelGGL(k_flux, dim3(nblocks(nthr, 128)), dim3(128), 0, m->stream, a));
+    PROFB(KC_FLUX, (double)a.nf * (2 * (32.0 + 160.0 + 32.0) + 8.0 + 24.0 + 64.0 + 32.0), hipLaunchKernelGGL(k_flux, dim3(nblocks(nthr, 128)), dim3(128), 0, m->stream, a));
 }
 
 void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn) {
     const int nt = m->d.nt;
-    PROF(KC_UPDATE, hipLaunchKernelGGL(k_update, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.nf,
+    PROFB(KC_UPDATE, (double)nt * (12.0 + 8.0 + 64.0 + 3 * 32.0), hipLaunchKernelGGL(k_update, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.nf,
                                        m->d.cface, m->d.area, W, F, Wn, m->prm.gamma, m->w.counters + 1));
 }
 
