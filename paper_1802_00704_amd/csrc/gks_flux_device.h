@@ -24,10 +24,14 @@
 
 #include <hip/hip_runtime.h>
 
+// Callable from host code too, so a CPU build of this file can be checked
+// against the oracle without a GPU.
+#define GKS_HD __host__ __device__ __forceinline__
+
 namespace gksdev {
 
 constexpr int PD = 7;   // u and v exponents 0..6
-constexpr int PC = 3;   // xi^2 exponents 0..2
+constexpr int PC = 3;   // xi^2 exponents 0..2 (products of two slope polynomials)
 
 struct VPoly {
     double c[PD][PD][PC];
@@ -39,30 +43,30 @@ constexpr int TA[6] = {0, 1, 0, 2, 0, 0};
 constexpr int TB[6] = {0, 0, 1, 0, 2, 0};
 constexpr int TC[6] = {0, 0, 0, 0, 0, 1};
 
-__device__ __forceinline__ double psi_coef(const double a[4], int i) {
+GKS_HD double psi_coef(const double a[4], int i) {
     return i < 3 ? a[i] : 0.5 * a[3];
 }
 
 template <int D>
-__device__ __forceinline__ void vp_zero(VPoly& P) {
+GKS_HD void vp_zero(VPoly& P) {
 #pragma unroll
     for (int a = 0; a <= D; ++a)
 #pragma unroll
         for (int b = 0; b <= D - a; ++b)
 #pragma unroll
-            for (int c = 0; 2 * c <= D - a - b; ++c) P.c[a][b][c] = 0.0;
+            for (int c = 0; 2 * c <= D - a - b && c < PC; ++c) P.c[a][b][c] = 0.0;
 }
 
 // P += s u^EU v^EV (a.psi)
 template <int EU, int EV>
-__device__ __forceinline__ void vp_add1(VPoly& P, double s, const double a[4]) {
+GKS_HD void vp_add1(VPoly& P, double s, const double a[4]) {
 #pragma unroll
     for (int i = 0; i < 6; ++i) P.c[TA[i] + EU][TB[i] + EV][TC[i]] += s * psi_coef(a, i);
 }
 
 // P += s u^EU v^EV (a.psi)(b.psi)
 template <int EU, int EV>
-__device__ __forceinline__ void vp_add2(VPoly& P, double s, const double a[4], const double b[4]) {
+GKS_HD void vp_add2(VPoly& P, double s, const double a[4], const double b[4]) {
     double sa[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) sa[i] = s * psi_coef(a, i);
@@ -83,7 +87,7 @@ struct Mom {
 
 // <u^n> for n = 0..N on the full line: <u^{n+2}> = U <u^{n+1}> + (n+1)/(2 lam) <u^n>
 template <int N>
-__device__ __forceinline__ void line_moments(double* m, double U, double lam, double m0, double m1) {
+GKS_HD void line_moments(double* m, double U, double lam, double m0, double m1) {
     const double il = 0.5 / lam;
     m[0] = m0;
     m[1] = m1;
@@ -91,7 +95,7 @@ __device__ __forceinline__ void line_moments(double* m, double U, double lam, do
     for (int n = 0; n + 2 <= N; ++n) m[n + 2] = U * m[n + 1] + (n + 1) * il * m[n];
 }
 
-__device__ __forceinline__ void xi_moments(double* x, double lam, double K) {
+GKS_HD void xi_moments(double* x, double lam, double K) {
     const double il = 0.5 / lam;
     x[0] = 1.0;
     x[1] = K * il;
@@ -103,7 +107,7 @@ struct Prim {
     double rho, U, V, lam;
 };
 
-__device__ __forceinline__ Prim primitives(const double W[4], double K) {
+GKS_HD Prim primitives(const double W[4], double K) {
     Prim p;
     p.rho = W[0];
     const double ir = 1.0 / W[0];
@@ -114,7 +118,7 @@ __device__ __forceinline__ Prim primitives(const double W[4], double K) {
 }
 
 template <int NU>
-__device__ __forceinline__ void full_moments(Mom& M, const Prim& p, double K) {
+GKS_HD void full_moments(Mom& M, const Prim& p, double K) {
     line_moments<NU>(M.u, p.U, p.lam, 1.0, p.U);
     line_moments<NU>(M.v, p.V, p.lam, 1.0, p.V);
     xi_moments(M.x, p.lam, K);
@@ -122,7 +126,7 @@ __device__ __forceinline__ void full_moments(Mom& M, const Prim& p, double K) {
 
 // half line: u > 0 for sign = +1, u < 0 for sign = -1
 template <int NU>
-__device__ __forceinline__ void half_moments(Mom& M, const Prim& p, double K, double sign) {
+GKS_HD void half_moments(Mom& M, const Prim& p, double K, double sign) {
     const double sl = sqrt(p.lam);
     const double m0 = 0.5 * erfc(-sign * sl * p.U);
     const double m1 = p.U * m0 + sign * exp(-p.lam * p.U * p.U) / (2.0 * sqrt(M_PI * p.lam));
@@ -133,7 +137,7 @@ __device__ __forceinline__ void half_moments(Mom& M, const Prim& p, double K, do
 
 // D_alpha = <psi_alpha P> for a polynomial of degree <= D
 template <int D>
-__device__ __forceinline__ void psi_moments(double out[4], const VPoly& P, const Mom& M) {
+GKS_HD void psi_moments(double out[4], const VPoly& P, const Mom& M) {
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
@@ -142,7 +146,7 @@ __device__ __forceinline__ void psi_moments(double out[4], const VPoly& P, const
         for (int b = 0; b <= D - a; ++b) {
             double q0 = 0.0, q1 = 0.0;
 #pragma unroll
-            for (int c = 0; 2 * c <= D - a - b; ++c) {
+            for (int c = 0; 2 * c <= D - a - b && c < PC; ++c) {
                 q0 += P.c[a][b][c] * M.x[c];
                 q1 += P.c[a][b][c] * M.x[c + 1];
             }
@@ -164,7 +168,7 @@ __device__ __forceinline__ void psi_moments(double out[4], const VPoly& P, const
 
 // F_alpha += s <u psi_alpha P> for a polynomial of degree <= D (D <= 6)
 template <int D>
-__device__ __forceinline__ void flux_moments(double F[4], double s, const VPoly& P, const Mom& M) {
+GKS_HD void flux_moments(double F[4], double s, const VPoly& P, const Mom& M) {
     double f0 = 0.0, f1 = 0.0, f2 = 0.0, f3 = 0.0;
 #pragma unroll
     for (int a = 0; a <= D; ++a) {
@@ -173,7 +177,7 @@ __device__ __forceinline__ void flux_moments(double F[4], double s, const VPoly&
         for (int b = 0; b <= D - a; ++b) {
             double q0 = 0.0, q1 = 0.0;
 #pragma unroll
-            for (int c = 0; 2 * c <= D - a - b; ++c) {
+            for (int c = 0; 2 * c <= D - a - b && c < PC; ++c) {
                 q0 += P.c[a][b][c] * M.x[c];
                 q1 += P.c[a][b][c] * M.x[c + 1];
             }
@@ -194,7 +198,7 @@ __device__ __forceinline__ void flux_moments(double F[4], double s, const VPoly&
 }
 
 // Closed-form solution a of rho <psi (a.psi)> = D for a full Maxwellian.
-__device__ __forceinline__ void slope_solve(double a[4], const double D[4], const Prim& p, double K) {
+GKS_HD void slope_solve(double a[4], const double D[4], const Prim& p, double K) {
     const double ir = 1.0 / p.rho;
     const double R2 = (D[1] - p.U * D[0]) * ir;
     const double R3 = (D[2] - p.V * D[0]) * ir;
@@ -215,7 +219,7 @@ struct Slopes {
 // a22 from d^2 g = g (a a + a_ij); A and its x-, y-, t-derivatives from the
 // Euler-level compatibility <psi (u a1 + v a2 + A)> = 0 differentiated.
 template <bool WITH_AT>
-__device__ __forceinline__ void side_slopes(Slopes& s, const double d[5][4], const Prim& p, const Mom& M,
+GKS_HD void side_slopes(Slopes& s, const double d[5][4], const Prim& p, const Mom& M,
                                             double K) {
     VPoly P;
     double D[4];
@@ -296,7 +300,7 @@ struct PolyCoef {
 
 // P of the header comment for one distribution.
 template <bool EQ>
-__device__ __forceinline__ void build_poly(VPoly& P, const Slopes& s, const PolyCoef& k) {
+GKS_HD void build_poly(VPoly& P, const Slopes& s, const PolyCoef& k) {
     vp_zero<6>(P);
     P.c[0][0][0] = k.c0;
     vp_add1<1, 0>(P, k.cr, s.a1);
@@ -323,7 +327,7 @@ struct TimeInt {
     double T[9];
 };
 
-__device__ __forceinline__ TimeInt time_integrals(double dt, double tau, bool exact) {
+GKS_HD TimeInt time_integrals(double dt, double tau, bool exact) {
     TimeInt r;
     const double e = exp(-dt / tau);
     const double t2 = tau * tau, t3 = t2 * tau, d2 = dt * dt;
@@ -345,7 +349,7 @@ __device__ __forceinline__ TimeInt time_integrals(double dt, double tau, bool ex
     return r;
 }
 
-__device__ __forceinline__ double pressure(const double W[4], double gamma) {
+GKS_HD double pressure(const double W[4], double gamma) {
     return (gamma - 1.0) * (W[3] - 0.5 * (W[1] * W[1] + W[2] * W[2]) / W[0]);
 }
 
@@ -356,7 +360,7 @@ struct FluxParams {
 
 // Time-integrated flux per unit length at one Gauss point (local frame).
 // dL / dR: derivatives n, t, nn, nt, tt of each side (local frame).
-__device__ __forceinline__ void gp_flux(double F[4], const double WL[4], const double dL[5][4],
+GKS_HD void gp_flux(double F[4], const double WL[4], const double dL[5][4],
                                         const double WR[4], const double dR[5][4], double dt,
                                         const FluxParams& fp) {
     const double K = fp.K;

@@ -1063,6 +1063,8 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
         return st;
     } catch (const Fail& f) {
         return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
     }
 }
 
@@ -1087,6 +1089,8 @@ int gks_flux(gks_mesh* m, const double* W, const double* X, double dt, double* F
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
     }
 }
 
@@ -1130,6 +1134,8 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
     }
 }
 
@@ -1159,6 +1165,8 @@ int gks_profile_enable(gks_mesh* m, int enable) {
         prof_collect(m);
     } catch (const Fail& f) {
         return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
     }
     if (enable) {
         for (int i = 0; i < NPROF; ++i) {
@@ -1179,6 +1187,8 @@ int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, d
         prof_collect(m);
     } catch (const Fail& f) {
         return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
     }
     const int k = std::min(n, (int)KC_COUNT);
     for (int i = 0; i < k; ++i) {

@@ -143,6 +143,12 @@ struct gks_mesh {
 
 namespace gks {
 
+// thrown by a launcher whose kernel launch reported an error
+struct LaunchError {
+    hipError_t err;
+    const char* kernel;
+};
+
 // kernel classes for profiling
 enum Kc {
     KC_RHS = 0, KC_SPMV, KC_SPMV_RES, KC_ILU_FWD, KC_ILU_BWD, KC_DOTS, KC_AXPY_DOTS, KC_AXPY_NORM,

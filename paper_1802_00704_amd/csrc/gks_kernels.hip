@@ -703,10 +703,16 @@ inline double spmv_bytes(int n, int esz, bool resid) { return n * (KW * 25.0 * e
 inline double ilu_fwd_bytes(int rows, int esz) { return rows * (LW * 25.0 * esz + LW * 4.0 + 3 * VB); }
 inline double ilu_bwd_bytes(int rows, int esz) { return rows * (LW * 25.0 * esz + LW * 4.0 + 25.0 * esz + 3 * VB); }
 
+static inline void check_launch(int kc) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) throw LaunchError{e, kc_names[kc]};
+}
+
 #define PROFB(kc, bytes, ...)        \
     do {                             \
         prof_begin(m, kc, bytes);    \
         __VA_ARGS__;                 \
+        check_launch(kc);            \
         prof_end(m, kc);             \
     } while (0)
 #define PROF(kc, ...) PROFB(kc, 0.0, __VA_ARGS__)
@@ -858,11 +864,13 @@ void launch_cfl(gks_mesh* m, const double* W, double* dt_out) {
 
 void launch_set_scalar(gks_mesh* m, double* p, double v) {
     hipLaunchKernelGGL(k_set, dim3(1), dim3(1), 0, m->stream, p, v);
+    check_launch(KC_MISC);
 }
 
 void launch_zero(gks_mesh* m, double* p, int64_t count) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(count)), dim3(TPB), 0, m->stream, count, p);
+    check_launch(KC_MISC);
 }
 
 __global__ void k_zero_i32(int count, int32_t* p) {
@@ -871,11 +879,13 @@ __global__ void k_zero_i32(int count, int32_t* p) {
 
 void launch_zero_i32(gks_mesh* m, int32_t* p, int count) {
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, m->stream, count, p);
+    check_launch(KC_MISC);
 }
 
 void launch_copy(gks_mesh* m, double* dst, const double* src, int64_t count) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_copy, dim3(nblocks(count)), dim3(TPB), 0, m->stream, count, dst, src);
+    check_launch(KC_MISC);
 }
 
 }  // namespace gks
