@@ -190,7 +190,7 @@ def main():
         "dtype": "f64+f32" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "form": head,
-                   "solver": "multicolour BILU(0); FP64 FGMRES(30) with 4 FP32 inner sweeps" if head == "mixed"
+                   "solver": "multicolour BILU(0); FP64 FGMRES(30) with 5 FP32 BILU(0)-Richardson inner sweeps" if head == "mixed"
                    else "multicolour BILU(0); FP64 GMRES(30)",
                    "cells": m.nt},
         "roofline": roofline(r["profile"], r["elapsed_s"]),

@@ -99,7 +99,7 @@ typedef struct {
     int32_t precision;       /* GKS_FP64 or GKS_MIXED                            */
     int32_t ordering;        /* GKS_ORDER_MULTICOLOR or GKS_ORDER_RCM            */
     int32_t inner_iters;     /* GKS_MIXED: FP32 preconditioned sweeps per outer
-                                iteration (4)                                   */
+                                iteration (5)                                   */
     int32_t exact_time;      /* 0: time coefficients c_1..c_8 of Eq.
                                 Nomenclature2 as printed; 1: exact integrals     */
     int32_t nonphys_fallback;/* 0: non-physical Gauss-point state -> GKS_ENONPHYS;

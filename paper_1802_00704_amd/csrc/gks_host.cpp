@@ -477,16 +477,27 @@ struct HostSystem {
     std::vector<int> perm;                        // solver order -> cell
     std::vector<int32_t> lev_ptr;
     int n_levels = 0, n_colors = 0, rcm_bw = 0, nfb = 0;
-    std::vector<double> Kval, a0, Lval, Uval, Dv;
-    std::vector<int32_t> Kcol, rnb, Lcol, Ucol;
+    std::vector<double> Kval, a0c, Lval, Uval, Dv;
+    std::vector<int32_t> Kcol, nbc, iperm, Lcol, Ucol;
     std::vector<int32_t> own, nbr, cface, bck;
     std::vector<double> fgeo, gpd, cgeo, bcs;
 };
 
-std::vector<float> to32(const std::vector<double>& v) {
-    std::vector<float> o(v.size());
-    for (size_t i = 0; i < v.size(); ++i) o[i] = (float)v[i];
-    return o;
+// Entry-major [slots*25][n] -> vector-packed device layout (gks_internal.h).
+template <typename T>
+std::vector<T> pack_blocks(const std::vector<double>& src, int slots, int n, int np) {
+    constexpr int V = 16 / sizeof(T);
+    std::vector<T> dst((size_t)slots * 25 * np, T(0));
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < n; ++i)
+        for (int s = 0; s < slots; ++s) {
+            const size_t base = (size_t)s * 25 * np;
+            for (int e = 0; e < 25; ++e) {
+                const size_t at = e < 24 ? base + ((size_t)(e / V) * np + i) * V + e % V : base + (size_t)24 * np + i;
+                dst[at] = (T)src[((size_t)s * 25 + e) * n + i];
+            }
+        }
+    return dst;
 }
 
 void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S) {
@@ -557,10 +568,16 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     Kval.assign((size_t)KW * 25 * n, 0.0);
     std::vector<int32_t>& Kcol = S.Kcol;
     Kcol.assign((size_t)KW * n, n);
-    std::vector<double>& a0 = S.a0;
-    a0.assign((size_t)3 * 5 * n, 0.0);
-    std::vector<int32_t>& rnb = S.rnb;
-    rnb.assign((size_t)3 * n, 0);
+    S.iperm.assign(iperm.begin(), iperm.end());
+    S.nbc.assign((size_t)3 * n, 0);
+    S.a0c.assign((size_t)3 * 5 * n, 0.0);
+    for (int o = 0; o < n; ++o)
+        for (int s2 = 0; s2 < 3; ++s2) {
+            const int j = hm.nb[o][s2];
+            S.nbc[(size_t)s2 * n + o] = j >= 0 ? j : o;
+            if (j >= 0)
+                for (int l = 0; l < 5; ++l) S.a0c[((size_t)s2 * 5 + l) * n + o] = as.a0[o][s2][l];
+        }
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         const int o = perm[i];
@@ -568,11 +585,9 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         for (int e = 0; e < 25; ++e) Kval[(size_t)e * n + i] = as.diag[o][e];
         for (int s = 0; s < 3; ++s) {
             const int j = hm.nb[o][s];
-            rnb[(size_t)s * n + i] = j >= 0 ? j : o;
             if (j < 0) continue;
             Kcol[(size_t)(s + 1) * n + i] = iperm[j];
             for (int e = 0; e < 25; ++e) Kval[((size_t)(s + 1) * 25 + e) * n + i] = as.off[o][s][e];
-            for (int l = 0; l < 5; ++l) a0[((size_t)s * 5 + l) * n + i] = as.a0[o][s][l];
         }
     }
 
@@ -748,22 +763,23 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     d.cface = dev_upload(m, S.cface);
     d.bc_kind = dev_upload(m, S.bck);
     d.bc_state = dev_upload(m, S.bcs);
-    std::vector<int32_t> permv(S.perm.begin(), S.perm.end());
-    d.perm = dev_upload(m, permv);
-    d.rnb = dev_upload(m, S.rnb);
-    d.a0 = dev_upload(m, S.a0);
-    d.Kval = dev_upload(m, S.Kval);
+    d.iperm = dev_upload(m, S.iperm);
+    d.nbc = dev_upload(m, S.nbc);
+    d.a0c = dev_upload(m, S.a0c);
+    d.np = (n + 3) / 4 * 4;
+    const int np = d.np;
+    d.Kval = dev_upload(m, pack_blocks<double>(S.Kval, KW, n, np));
     d.Kcol = dev_upload(m, S.Kcol);
-    d.Lval = dev_upload(m, S.Lval);
+    d.Lval = dev_upload(m, pack_blocks<double>(S.Lval, LW, n, np));
     d.Lcol = dev_upload(m, S.Lcol);
-    d.Uval = dev_upload(m, S.Uval);
+    d.Uval = dev_upload(m, pack_blocks<double>(S.Uval, LW, n, np));
     d.Ucol = dev_upload(m, S.Ucol);
-    d.Dinv = dev_upload(m, S.Dv);
+    d.Dinv = dev_upload(m, pack_blocks<double>(S.Dv, 1, n, np));
     if (prm.precision == GKS_MIXED) {
-        d.Kval32 = dev_upload(m, to32(S.Kval));
-        d.Lval32 = dev_upload(m, to32(S.Lval));
-        d.Uval32 = dev_upload(m, to32(S.Uval));
-        d.Dinv32 = dev_upload(m, to32(S.Dv));
+        d.Kval32 = dev_upload(m, pack_blocks<float>(S.Kval, KW, n, np));
+        d.Lval32 = dev_upload(m, pack_blocks<float>(S.Lval, LW, n, np));
+        d.Uval32 = dev_upload(m, pack_blocks<float>(S.Uval, LW, n, np));
+        d.Dinv32 = dev_upload(m, pack_blocks<float>(S.Dv, 1, n, np));
     }
 
     // ---- work space
@@ -773,7 +789,11 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     w.X = dev_alloc<double>(m, vec);
     w.R = dev_alloc<double>(m, vec);
     w.V = dev_alloc<double>(m, vec * (mres + 1));
-    if (prm.precision == GKS_MIXED) w.Z = dev_alloc<double>(m, vec * mres);
+    if (prm.precision == GKS_MIXED) {
+        w.Z = dev_alloc<float>(m, vec * mres);
+        w.yf = dev_alloc<float>(m, vec);
+        w.df = dev_alloc<float>(m, vec);
+    }
     w.w = dev_alloc<double>(m, vec);
     w.t1 = dev_alloc<double>(m, vec);
     w.t2 = dev_alloc<double>(m, vec);
@@ -840,7 +860,7 @@ int solve_gmres(gks_mesh* m, gks_solve_info* info) {
         while (k < mres && total < m->prm.max_iter) {
             double* vk = w.V + (int64_t)k * vs;
             double* vk1 = w.V + (int64_t)(k + 1) * vs;
-            launch_ilu(m, vk, &ks->scale[k][0], w.t1, w.t2, false);
+            launch_ilu(m, vk, &ks->scale[k][0], w.t1, w.t2);
             launch_spmv64(m, w.t2, nullptr, w.w);
             launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0]);
             launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w);
@@ -857,7 +877,7 @@ int solve_gmres(gks_mesh* m, gks_solve_info* info) {
         }
         launch_ctl(m, 3);
         launch_combine(m, w.V, vs, k, &ks->y[0][0], &ks->scale[0][0], w.t1);
-        launch_ilu(m, w.t1, nullptr, w.t2, w.t3, false);
+        launch_ilu(m, w.t1, nullptr, w.t2, w.t3);
         launch_acc(m, w.X, w.t3);
     }
     if (info) {
@@ -904,15 +924,10 @@ int solve_fgmres_mixed(gks_mesh* m, gks_solve_info* info) {
         while (k < mres && total < m->prm.max_iter) {
             double* vk = w.V + (int64_t)k * vs;
             double* vk1 = w.V + (int64_t)(k + 1) * vs;
-            double* zk = w.Z + (int64_t)k * vs;
+            float* zk = w.Z + (int64_t)k * vs;
             const double* sk = &ks->scale[k][0];
-            launch_ilu(m, vk, sk, w.t1, zk, true);
-            for (int j = 1; j < q; ++j) {
-                launch_resid32(m, zk, vk, sk, w.t3);
-                launch_ilu(m, w.t3, nullptr, w.t1, w.t2, true);
-                launch_acc(m, zk, w.t2);
-            }
-            launch_spmv64(m, zk, nullptr, w.w);
+            for (int j = 0; j < q; ++j) launch_mx_sweep(m, j == 0, vk, sk, w.yf, w.df, zk);
+            launch_spmv64_f32x(m, zk, w.w);
             launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0]);
             launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w);
             launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0]);
@@ -927,7 +942,7 @@ int solve_fgmres_mixed(gks_mesh* m, gks_solve_info* info) {
             if (all_conv(w.st_host)) break;
         }
         launch_ctl(m, 3);
-        launch_combine(m, w.Z, vs, k, &ks->y[0][0], w.ones, w.t1);
+        launch_combine_f32(m, w.Z, vs, k, &ks->y[0][0], w.ones, w.t1);
         launch_acc(m, w.X, w.t1);
     }
     if (info) {
@@ -993,7 +1008,7 @@ void gks_params_default(gks_params* p) {
     p->max_iter = 500;
     p->precision = GKS_FP64;
     p->ordering = GKS_ORDER_MULTICOLOR;
-    p->inner_iters = 4;
+    p->inner_iters = 5;
     p->exact_time = 0;
     p->nonphys_fallback = 0;
     p->all_quadratic = 0;

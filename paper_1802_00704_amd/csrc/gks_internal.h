@@ -9,9 +9,13 @@
 // 4 x 5 block is 160 contiguous bytes.  Every vector has n + 1 cells; cell n
 // is a zero dummy that padded matrix slots point at.
 //
-// Block-ELL matrices store 5 x 5 blocks entry-major: val[(slot * 25 + e) * n
-// + i], entry e = 5 r + c (row r, column c), so a wave reading one entry of
-// consecutive rows reads contiguous memory.
+// Block-ELL matrices are uploaded "vector-packed": for slot s of row i the
+// entries e < 24 of the 5 x 5 block (e = 5 r + c) lie at
+// s*25*np + ((e / V) * np + i) * V + e % V (V = 4 floats or 2 doubles, 16
+// bytes) and entry 24 at s*25*np + 24*np + i, np = n rounded up to 4, so each
+// thread reads a block with 16-byte loads and a wave reads contiguous runs.
+// (Host-side arrays, e.g. those of gks_host_inspect, are entry-major
+// val[(slot * 25 + e) * n + i].)
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -83,9 +87,10 @@ struct DevMesh {
     int n_bc = 0;
     // solver (solver order)
     int n = 0;
-    int32_t* perm = nullptr;      // [n] new -> old
-    int32_t* rnb = nullptr;       // [3][n] old index of neighbour (self if none)
-    double* a0 = nullptr;         // [3][5][n] CLS row-0 coefficients per neighbour slot
+    int np = 0;                   // row stride of the vector-packed matrices (n rounded up to 4)
+    int32_t* iperm = nullptr;     // [nt] cell -> solver row
+    int32_t* nbc = nullptr;       // [3][nt] face neighbours in cell order (self if none)
+    double* a0c = nullptr;        // [3][5][nt] CLS row-0 coefficients per neighbour slot (cell order)
     double* Kval = nullptr;       // [KW][25][n]
     int32_t* Kcol = nullptr;      // [KW][n] (n = dummy)
     float* Kval32 = nullptr;
@@ -104,7 +109,9 @@ struct Work {
     double* X = nullptr;          // [n+1][CB] current solution (warm start)
     double* R = nullptr;          // [n+1][CB] right-hand side
     double* V = nullptr;          // [(m+1)][n+1][CB] Krylov basis
-    double* Z = nullptr;          // [m][n+1][CB] flexible GMRES: preconditioned basis
+    float* Z = nullptr;           // [m][n+1][CB] flexible GMRES: preconditioned basis (FP32)
+    float* yf = nullptr;          // [n+1][CB] mixed inner sweeps: forward result
+    float* df = nullptr;          // [n+1][CB] mixed inner sweeps: correction
     double* w = nullptr;          // [n+1][CB]
     double* t1 = nullptr;         // [n+1][CB]
     double* t2 = nullptr;         // [n+1][CB]
@@ -160,16 +167,18 @@ extern const char* kc_names[NPROF];
 // launchers (gks_kernels.hip); all enqueue on m->stream
 void launch_rhs(gks_mesh* m, const double* W);
 void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y);
-void launch_spmv32(gks_mesh* m, const double* x, const double* xscale, double* y);
+void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y);
 void launch_resid(gks_mesh* m, const double* x, const double* b, double* y);
-void launch_resid32(gks_mesh* m, const double* x, const double* b, const double* bscale, double* y);
-void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out, bool fp32);
+void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out);
+void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out);
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
                  const double* w, double* out);
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out);
+void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, const double* y, const double* scale,
+                        double* out);
 void launch_acc(gks_mesh* m, double* X, const double* z);
 void launch_ctl(gks_mesh* m, int mode);
 void launch_mask_cols(gks_mesh* m, double* X);

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
+#include <cstdlib>
 
 #include "gks_flux_device.h"
 #include "gks_internal.h"
@@ -25,14 +26,58 @@ constexpr int RED_CHUNK = 8;      // vectors per block of the dot kernel
 
 static inline int nblocks(int64_t n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
 
+// The hardware hands consecutive workgroups of a grid to the 8 XCDs in turn,
+// and each XCD has its own L2.  Row kernels gather neighbour blocks, so they
+// renumber workgroups such that every XCD works on one contiguous range of
+// rows and its neighbours stay in that XCD's L2.
+constexpr int NXCD = 8;
+__device__ __forceinline__ int xcd_block() {
+    const int G = gridDim.x, b = blockIdx.x;
+    const int q = G / NXCD, r = G % NXCD;
+    const int x = b % NXCD, k = b / NXCD;
+    return x * q + min(x, r) + k;
+}
+__device__ __forceinline__ int xcd_row() { return xcd_block() * blockDim.x + threadIdx.x; }
+
+
+// ------------------------------------------------------------------ block loads
+// Matrix storage ("vector-packed"): for slot s of row i, entries e < 24 of the
+// 5 x 5 block (e = 5 r + c) lie at  s*25*np + ((e / V) * np + i) * V + e % V
+// and entry 24 at  s*25*np + 24*np + i,  with V = 16 bytes / sizeof(T) and the
+// row stride np a multiple of 4.  A thread loads a block with 24 / V 16-byte
+// loads plus one scalar, and a wave reads contiguous 1 KiB runs.
+template <typename T> struct Vec16;
+template <> struct Vec16<float> {
+    using type = float4;
+    static constexpr int N = 4;
+    static __device__ __forceinline__ void put(float* o, const float4& v) { o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w; }
+};
+template <> struct Vec16<double> {
+    using type = double2;
+    static constexpr int N = 2;
+    static __device__ __forceinline__ void put(double* o, const double2& v) { o[0] = v.x; o[1] = v.y; }
+};
+
+template <typename T>
+__device__ __forceinline__ void load_block(const T* __restrict__ val, int64_t np, int s, int i, T (&blk)[25]) {
+    using VT = typename Vec16<T>::type;
+    constexpr int V = Vec16<T>::N;
+    const T* base = val + (int64_t)s * 25 * np;
+    const VT* vb = reinterpret_cast<const VT*>(base);
+#pragma unroll
+    for (int g = 0; g < 24 / V; ++g) Vec16<T>::put(blk + g * V, vb[(int64_t)g * np + i]);
+    blk[24] = base[24 * np + i];
+}
+
 // ------------------------------------------------------------------ RHS
-// R_i = sum_j a0_ij (W_j - W_i) for the four variables (Eq. A:B:b, b = C^T b)
-__global__ void __launch_bounds__(TPB) k_rhs(int n, const int32_t* __restrict__ perm,
-                                             const int32_t* __restrict__ rnb, const double* __restrict__ a0,
-                                             const double* __restrict__ W, int nt, double* __restrict__ R) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int oi = perm[i];
+// R_i = sum_j a0_ij (W_j - W_i) for the four variables (Eq. A:B:b, b = C^T b).
+// One thread per cell in the caller's order (W reads stay local); the
+// 160-byte block goes to the cell's solver row.
+__global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__ iperm,
+                                             const int32_t* __restrict__ nbc, const double* __restrict__ a0c,
+                                             const double* __restrict__ W, double* __restrict__ R) {
+    const int oi = xcd_row();
+    if (oi >= nt) return;
     double wi[NC];
 #pragma unroll
     for (int c = 0; c < NC; ++c) wi[c] = W[(int64_t)c * nt + oi];
@@ -43,10 +88,10 @@ __global__ void __launch_bounds__(TPB) k_rhs(int n, const int32_t* __restrict__ 
         for (int l = 0; l < NB; ++l) acc[c][l] = 0.0;
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
-        const int j = rnb[(int64_t)s * n + i];
+        const int j = nbc[(int64_t)s * nt + oi];
         double a[NB];
 #pragma unroll
-        for (int l = 0; l < NB; ++l) a[l] = a0[((int64_t)s * NB + l) * n + i];
+        for (int l = 0; l < NB; ++l) a[l] = a0c[((int64_t)s * NB + l) * nt + oi];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double d = W[(int64_t)c * nt + j] - wi[c];
@@ -54,7 +99,7 @@ __global__ void __launch_bounds__(TPB) k_rhs(int n, const int32_t* __restrict__ 
             for (int l = 0; l < NB; ++l) acc[c][l] += a[l] * d;
         }
     }
-    double* out = R + (int64_t)i * CB;
+    double* out = R + (int64_t)iperm[oi] * CB;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -64,11 +109,12 @@ __global__ void __launch_bounds__(TPB) k_rhs(int n, const int32_t* __restrict__ 
 // ------------------------------------------------------------------ SpMV
 // y = K (s .* x)   or   y = b - K x   (RESID), block-ELL, thread per row.
 // In RESID mode xscale (when not null) scales b instead: y = s .* b - K x.
-template <typename T, bool RESID>
-__global__ void __launch_bounds__(TPB) k_spmv(int n, const T* __restrict__ val, const int32_t* __restrict__ col,
-                                              const double* __restrict__ x, const double* __restrict__ xscale,
+// MT: matrix element type; XT: element type of the input vector x.
+template <typename T, typename XT, bool RESID>
+__global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col,
+                                              const XT* __restrict__ x, const double* __restrict__ xscale,
                                               const double* __restrict__ b, double* __restrict__ y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = xcd_row();
     if (i >= n) return;
     double acc[NC][NB];
 #pragma unroll
@@ -78,13 +124,12 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, const T* __restrict__ val, 
 #pragma unroll
     for (int s = 0; s < KW; ++s) {
         const int j = col[(int64_t)s * n + i];
-        const double* xj = x + (int64_t)j * CB;
+        const XT* xj = x + (int64_t)j * CB;
         double xv[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) xv[q] = xj[q];
+        for (int q = 0; q < CB; ++q) xv[q] = (double)xj[q];
         T blk[25];
-#pragma unroll
-        for (int e = 0; e < 25; ++e) blk[e] = val[((int64_t)s * 25 + e) * n + i];
+        load_block(val, np, s, i, blk);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -117,10 +162,10 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, const T* __restrict__ val, 
 // backward z_i = Dinv_i (y_i - sum_{j>i} U_ij z_j)
 // over the rows [r0, r1) of one dependency level.
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int r0, int r1, const T* __restrict__ Lv,
+__global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int np, int r0, int r1, const T* __restrict__ Lv,
                                                  const int32_t* __restrict__ Lc, const double* __restrict__ v,
                                                  const double* __restrict__ vscale, double* __restrict__ y) {
-    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = r0 + xcd_row();
     if (i >= r1) return;
     double acc[CB];
     const double* vi = v + (int64_t)i * CB;
@@ -138,8 +183,7 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int r0, int r1, const T*
 #pragma unroll
         for (int q = 0; q < CB; ++q) yv[q] = yk[q];
         T blk[25];
-#pragma unroll
-        for (int e = 0; e < 25; ++e) blk[e] = Lv[((int64_t)s * 25 + e) * n + i];
+        load_block(Lv, np, s, i, blk);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -153,10 +197,10 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int r0, int r1, const T*
 }
 
 template <typename T>
-__global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int r0, int r1, const T* __restrict__ Uv,
+__global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int np, int r0, int r1, const T* __restrict__ Uv,
                                                  const int32_t* __restrict__ Uc, const T* __restrict__ Dinv,
                                                  const double* __restrict__ y, double* __restrict__ z) {
-    const int i = r0 + blockIdx.x * blockDim.x + threadIdx.x;
+    const int i = r0 + xcd_row();
     if (i >= r1) return;
     double acc[CB];
     const double* yi = y + (int64_t)i * CB;
@@ -170,8 +214,7 @@ __global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int r0, int r1, const T*
 #pragma unroll
         for (int q = 0; q < CB; ++q) zv[q] = zj[q];
         T blk[25];
-#pragma unroll
-        for (int e = 0; e < 25; ++e) blk[e] = Uv[((int64_t)s * 25 + e) * n + i];
+        load_block(Uv, np, s, i, blk);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -180,8 +223,7 @@ __global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int r0, int r1, const T*
                 for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (double)blk[r * NB + q] * zv[c * NB + q];
     }
     T d[25];
-#pragma unroll
-    for (int e = 0; e < 25; ++e) d[e] = Dinv[(int64_t)e * n + i];
+    load_block(Dinv, np, 0, i, d);
     double* zi = z + (int64_t)i * CB;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -192,6 +234,124 @@ __global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int r0, int r1, const T*
             for (int q = 0; q < NB; ++q) s += (double)d[r * NB + q] * acc[c * NB + q];
             zi[c * NB + r] = s;
         }
+}
+
+// ------------------------------------------------------------------ mixed-precision inner sweeps
+// One BILU(0)-preconditioned Richardson sweep z <- z + M^-1 (s .* v - K z)
+// with the FP32 matrix and factors, FP32 vectors (20 floats per cell):
+//   forward  (rows of one level)  y_i = r_i - sum_{k<i} L_ik y_k,
+//            r_i = s .* v_i - sum_s K_is z_s   (FIRST: z = 0, r_i = s .* v_i)
+//   backward (rows of one level)  d_i = Dinv_i (y_i - sum_{j>i} U_ij d_j),
+//            z_i += d_i                        (FIRST: z_i = d_i, d is z)
+// z is not modified during the forward levels, so the residual needs no
+// separate pass.
+template <bool FIRST, typename ACC>
+__global__ void __launch_bounds__(TPB) k_mx_fwd(int n, int np, int r0, int r1, const float* __restrict__ Kv,
+                                                const int32_t* __restrict__ Kc, const float* __restrict__ Lv,
+                                                const int32_t* __restrict__ Lc, const double* __restrict__ v,
+                                                const double* __restrict__ vscale, const float* __restrict__ z,
+                                                float* __restrict__ y) {
+    const int i = r0 + xcd_row();
+    if (i >= r1) return;
+    ACC acc[CB];
+    const double* vi = v + (int64_t)i * CB;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        const ACC sc = (ACC)vscale[c];
+#pragma unroll
+        for (int r = 0; r < NB; ++r) acc[c * NB + r] = sc * (ACC)vi[c * NB + r];
+    }
+    if (!FIRST) {
+#pragma unroll
+        for (int s = 0; s < KW; ++s) {
+            const int j = Kc[(int64_t)s * n + i];
+            const float* zj = z + (int64_t)j * CB;
+            float zv[CB];
+#pragma unroll
+            for (int q = 0; q < CB; ++q) zv[q] = zj[q];
+            float blk[25];
+            load_block(Kv, np, s, i, blk);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NB; ++r)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)zv[c * NB + q];
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        const int k = Lc[(int64_t)s * n + i];
+        const float* yk = y + (int64_t)k * CB;
+        float yv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) yv[q] = yk[q];
+        float blk[25];
+        load_block(Lv, np, s, i, blk);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)yv[c * NB + q];
+    }
+    float* yi = y + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) yi[q] = (float)acc[q];
+}
+
+template <bool FIRST, typename ACC>
+__global__ void __launch_bounds__(TPB) k_mx_bwd(int n, int np, int r0, int r1, const float* __restrict__ Uv,
+                                                const int32_t* __restrict__ Uc, const float* __restrict__ Dinv,
+                                                const float* __restrict__ y, float* __restrict__ d,
+                                                float* __restrict__ z) {
+    const int i = r0 + xcd_row();
+    if (i >= r1) return;
+    float* dd = FIRST ? z : d;
+    ACC acc[CB];
+    const float* yi = y + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = (ACC)yi[q];
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        const int j = Uc[(int64_t)s * n + i];
+        const float* dj = dd + (int64_t)j * CB;
+        float dv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) dv[q] = dj[q];
+        float blk[25];
+        load_block(Uv, np, s, i, blk);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)dv[c * NB + q];
+    }
+    float dg[25];
+    load_block(Dinv, np, 0, i, dg);
+    float di[CB];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            ACC t = 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) t += (ACC)dg[r * NB + q] * acc[c * NB + q];
+            di[c * NB + r] = (float)t;
+        }
+    float* zi = z + (int64_t)i * CB;
+    if (FIRST) {
+#pragma unroll
+        for (int q = 0; q < CB; ++q) zi[q] = di[q];
+    } else {
+        float* dout = d + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            dout[q] = di[q];
+            zi[q] = zi[q] + di[q];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ reductions
@@ -245,51 +405,64 @@ __global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ 
     }
 }
 
-// w <- w - sum_j coef_j[c] V_j   (coef_j = h[j][c] * scale[j][c]); out may alias w
+// Vector kernels over the Krylov basis map one 16-byte group of a cell's 20
+// values to a thread (10 threads per cell for FP64, 5 for FP32), so each load
+// instruction of a wave reads 1 KiB of contiguous memory and several basis
+// vectors are in flight per thread.  Value q of a cell belongs to column q / 5.
+template <typename VT>
+struct Grp {
+    static constexpr int E = 16 / sizeof(VT);   // values per thread
+    static constexpr int T = CB / E;            // threads per cell
+};
+
+// out = w - sum_j h_j[c] scale_j[c] V_j   (out may alias w)
 __global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ V, int64_t vstride, int nvec,
                                               const double* __restrict__ h, const double* __restrict__ scale,
                                               const double* w, double* out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / 10;
+    const int p = (int)(t - i * 10);
     if (i >= n) return;
-    double acc[CB];
-    const double* wi = w + (int64_t)i * CB;
-#pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = wi[q];
+    const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
+    const int64_t off = i * CB + 2 * p;
+    const double2 w2 = *reinterpret_cast<const double2*>(w + off);
+    double a0 = w2.x, a1 = w2.y;
+#pragma unroll 4
     for (int j = 0; j < nvec; ++j) {
-        const double* vi = V + (int64_t)j * vstride + (int64_t)i * CB;
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double cf = h[j * NC + c] * scale[j * NC + c];
-#pragma unroll
-            for (int l = 0; l < NB; ++l) acc[c * NB + l] -= cf * vi[c * NB + l];
-        }
+        const double2 v = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
+        a0 -= h[j * NC + c0] * scale[j * NC + c0] * v.x;
+        a1 -= h[j * NC + c1] * scale[j * NC + c1] * v.y;
     }
-    double* oi = out + (int64_t)i * CB;
-#pragma unroll
-    for (int q = 0; q < CB; ++q) oi[q] = acc[q];
+    *reinterpret_cast<double2*>(out + off) = make_double2(a0, a1);
 }
 
 // out = sum_j y_j[c] scale_j[c] V_j
-__global__ void __launch_bounds__(TPB) k_combine(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+template <typename VT>
+__global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V, int64_t vstride, int nvec,
                                                  const double* __restrict__ y, const double* __restrict__ scale,
                                                  double* __restrict__ out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    constexpr int E = Grp<VT>::E, TC = Grp<VT>::T;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = t / TC;
+    const int p = (int)(t - i * TC);
     if (i >= n) return;
-    double acc[CB];
+    int col[E];
 #pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int e = 0; e < E; ++e) col[e] = (E * p + e) / NB;
+    const int64_t off = i * CB + E * p;
+    double acc[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) acc[e] = 0.0;
+#pragma unroll 4
     for (int j = 0; j < nvec; ++j) {
-        const double* vi = V + (int64_t)j * vstride + (int64_t)i * CB;
+        VT v[E];
+        *reinterpret_cast<typename Vec16<VT>::type*>(v) =
+            *reinterpret_cast<const typename Vec16<VT>::type*>(V + (int64_t)j * vstride + off);
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double cf = y[j * NC + c] * scale[j * NC + c];
-#pragma unroll
-            for (int l = 0; l < NB; ++l) acc[c * NB + l] += cf * vi[c * NB + l];
-        }
+        for (int e = 0; e < E; ++e) acc[e] += y[j * NC + col[e]] * scale[j * NC + col[e]] * (double)v[e];
     }
-    double* oi = out + (int64_t)i * CB;
 #pragma unroll
-    for (int q = 0; q < CB; ++q) oi[q] = acc[q];
+    for (int e = 0; e < E; ++e) out[off + e] = acc[e];
 }
 
 // X += z
@@ -383,12 +556,13 @@ __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restr
 }
 
 // ------------------------------------------------------------------ layout conversion
-__global__ void __launch_bounds__(TPB) k_copyout(int n, int nt, const int32_t* __restrict__ perm,
+// X in the caller's layout [4][5][nt] from the solver vector: one thread per
+// cell in the caller's order (coalesced writes, one 160-byte read).
+__global__ void __launch_bounds__(TPB) k_copyout(int nt, const int32_t* __restrict__ iperm,
                                                  const double* __restrict__ Xs, double* __restrict__ Xc) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int oi = perm[i];
-    const double* xi = Xs + (int64_t)i * CB;
+    const int oi = xcd_row();
+    if (oi >= nt) return;
+    const double* xi = Xs + (int64_t)iperm[oi] * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) Xc[(int64_t)q * nt + oi] = xi[q];
 }
@@ -717,37 +891,73 @@ static inline void check_launch(int kc) {
     } while (0)
 #define PROF(kc, ...) PROFB(kc, 0.0, __VA_ARGS__)
 
+
+
 void launch_rhs(gks_mesh* m, const double* W) {
-    const int n = m->d.n;
-    PROFB(KC_RHS, n * (3 * (4.0 + 40.0) + 4.0 + 4 * 8.0 * 4 + VB), hipLaunchKernelGGL(k_rhs, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.perm, m->d.rnb,
-                                    m->d.a0, W, m->d.nt, m->w.R));
+    const int nt = m->d.nt;
+    PROFB(KC_RHS, nt * (3 * (4.0 + 40.0) + 4.0 + 4 * 8.0 * 4 + VB), hipLaunchKernelGGL(k_rhs, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.iperm, m->d.nbc,
+                                    m->d.a0c, W, m->w.R));
 }
 
 void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y) {
     const int n = m->d.n;
-    PROFB(KC_SPMV, spmv_bytes(n, 8, false), hipLaunchKernelGGL((k_spmv<double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
-                                     m->d.Kval, m->d.Kcol, x, xscale, nullptr, y));
+    PROFB(KC_SPMV, spmv_bytes(n, 8, false), hipLaunchKernelGGL((k_spmv<double, double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
+                                         m->d.Kval, m->d.Kcol, x, xscale, nullptr, y));
 }
 
-void launch_spmv32(gks_mesh* m, const double* x, const double* xscale, double* y) {
+void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y) {
     const int n = m->d.n;
-    PROFB(KC_SPMV32, spmv_bytes(n, 4, false), hipLaunchKernelGGL((k_spmv<float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
-                                       m->d.Kval32, m->d.Kcol, x, xscale, nullptr, y));
+    PROFB(KC_SPMV, n * (KW * 25.0 * 8 + KW * 4.0 + VB / 2 + VB), hipLaunchKernelGGL((k_spmv<double, float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
+                                         m->d.Kval, m->d.Kcol, x, nullptr, nullptr, y));
 }
 
 void launch_resid(gks_mesh* m, const double* x, const double* b, double* y) {
     const int n = m->d.n;
-    PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
+    PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
                                          m->d.Kval, m->d.Kcol, x, nullptr, b, y));
 }
 
-void launch_resid32(gks_mesh* m, const double* x, const double* b, const double* bscale, double* y) {
-    const int n = m->d.n;
-    PROFB(KC_SPMV32, spmv_bytes(n, 4, true), hipLaunchKernelGGL((k_spmv<float, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n,
-                                       m->d.Kval32, m->d.Kcol, x, bscale, b, y));
+// One inner sweep of the mixed form over all levels (see k_mx_fwd/k_mx_bwd).
+
+template <typename ACC>
+static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z);
+
+void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z) {
+    mx_sweep<double>(m, first, v, vscale, y, d, z);
 }
 
-void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out, bool fp32) {
+template <typename ACC>
+static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z) {
+    const int n = m->d.n;
+    const auto& lp = m->d.lev_ptr;
+    const int nl = (int)lp.size() - 1;
+    const double VF = VB / 2;
+    for (int l = 0; l < nl; ++l) {
+        const int r0 = lp[l], r1 = lp[l + 1];
+        if (r1 <= r0) continue;
+        const int rows = r1 - r0;
+        if (first)
+            PROFB(KC_ILU_FWD32, rows * (LW * 100.0 + LW * 4.0 + VB + 2 * VF), hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
+                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y));
+        else
+            PROFB(KC_ILU_FWD32, rows * ((KW + LW) * 100.0 + (KW + LW) * 4.0 + VB + 3 * VF), hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
+                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y));
+    }
+    for (int l = nl - 1; l >= 0; --l) {
+        const int r0 = lp[l], r1 = lp[l + 1];
+        if (r1 <= r0) continue;
+        const int rows = r1 - r0;
+        if (first)
+            PROFB(KC_ILU_BWD32, rows * (LW * 100.0 + 100.0 + LW * 4.0 + 3 * VF), hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
+                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z));
+        else
+            PROFB(KC_ILU_BWD32, rows * (LW * 100.0 + 100.0 + LW * 4.0 + 5 * VF), hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
+                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z));
+    }
+}
+
+void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out) {
+    const bool fp32 = false;
     const int n = m->d.n;
     const auto& lp = m->d.lev_ptr;
     const int nl = (int)lp.size() - 1;
@@ -756,20 +966,20 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
         if (r1 <= r0) continue;
         if (fp32)
             PROFB(KC_ILU_FWD32, ilu_fwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_fwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                  n, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp));
+                                                  n, m->d.np, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp));
         else
             PROFB(KC_ILU_FWD, ilu_fwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_fwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                n, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp));
+                                                n, m->d.np, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         if (fp32)
             PROFB(KC_ILU_BWD32, ilu_bwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_bwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                  n, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out));
+                                                  n, m->d.np, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out));
         else
             PROFB(KC_ILU_BWD, ilu_bwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_bwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                n, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out));
+                                                n, m->d.np, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out));
     }
 }
 
@@ -790,14 +1000,21 @@ void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, i
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
                  const double* w, double* out) {
     const int n = m->d.n;
-    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)n * 10)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
                                           h, scale, w, out));
 }
 
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out) {
     const int n = m->d.n;
-    PROFB(KC_COMBINE, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_combine, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+    PROFB(KC_COMBINE, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_combine<double>, dim3(nblocks((int64_t)n * Grp<double>::T)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+                                        y, scale, out));
+}
+
+void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, const double* y, const double* scale,
+                        double* out) {
+    const int n = m->d.n;
+    PROFB(KC_COMBINE, (double)n * (nvec * VB / 2 + VB), hipLaunchKernelGGL(k_combine<float>, dim3(nblocks((int64_t)n * Grp<float>::T)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
                                         y, scale, out));
 }
 
@@ -816,9 +1033,9 @@ void launch_mask_cols(gks_mesh* m, double* X) {
 }
 
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell) {
-    const int n = m->d.n;
-    PROFB(KC_COPYOUT, (double)n * (4.0 + 2 * VB), hipLaunchKernelGGL(k_copyout, dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.nt,
-                                        m->d.perm, Xs, Xcell));
+    const int nt = m->d.nt;
+    PROFB(KC_COPYOUT, (double)nt * (4.0 + 2 * VB), hipLaunchKernelGGL(k_copyout, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt,
+                                        m->d.iperm, Xs, Xcell));
 }
 
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F) {
