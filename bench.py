@@ -10,10 +10,13 @@ the mixed form (FP64 flexible GMRES with FP32 inner BILU(0)/SpMV sweeps) and
 in the plain FP64 form.  The headline value is the mixed form's
 cell-steps/s; the FP64 form is reported beside it.
 
-Prints ONE JSON line.  The roofline entry is for the kernel class with the
-largest share of the timed region, measured with HIP events on the
-library's stream during the timed steps; the CPU baseline is the oracle on a
-bounded sample of the same workload family.
+Prints ONE JSON line.  The value is timed over the K steps without
+instrumentation.  The roofline entry is for the kernel class with the
+largest share of kernel time, whose launch durations are measured with HIP
+event pairs on the library's stream over K further steps of the same run;
+its traffic comes from the committed counter summary when the kernel sources
+still match it.  The CPU baseline is the oracle on a bounded sample of the
+same workload family.
 """
 from __future__ import annotations
 
@@ -102,8 +105,6 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool):
     for _ in range(warmup):
         gm.step(W)
     torch.cuda.synchronize()
-    if profile:
-        gm.profile(True)
     lat = []
     iters = []
     t_start = time.perf_counter()
@@ -114,8 +115,19 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool):
         iters.append(max(info["iters"]))
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
-    prof = gm.profile_get() if profile else {}
-    gm.profile(False)
+    # Kernel durations: the same number of steps again with a HIP event pair
+    # around every launch on the library's stream (events add host latency
+    # between launches, so these steps are not part of the timed value).
+    prof, prof_elapsed = {}, 0.0
+    if profile:
+        gm.profile(True)
+        t_p = time.perf_counter()
+        for _ in range(steps):
+            gm.step(W)
+        torch.cuda.synchronize()
+        prof_elapsed = time.perf_counter() - t_p
+        prof = gm.profile_get()
+        gm.profile(False)
     stats = gm.stats()
     gm.close()
     lat_ms = np.array(lat) * 1e3
@@ -129,7 +141,24 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool):
         "stats": stats,
         "profile": prof,
         "elapsed_s": elapsed,
+        "profiled_elapsed_s": prof_elapsed,
     }
+
+
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gks_solver_hbm_traffic_shock_vortex_1m.txt")
+
+
+def measured_traffic(kernel_class: str):
+    """HBM bytes per launch of a kernel class from the committed counter
+    summary, or None when the kernels changed since the counters were taken."""
+    try:
+        from paper_1802_00704_amd.profiling import kernel_sources_sha256, read_summary
+        sha, table = read_summary(TRAFFIC_SUMMARY)
+    except (OSError, ImportError):
+        return None
+    if sha != kernel_sources_sha256():
+        return None
+    return table.get(kernel_class)
 
 
 def roofline(prof: dict, elapsed_s: float):
@@ -142,7 +171,7 @@ def roofline(prof: dict, elapsed_s: float):
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
     shares = {k: round(v["ms"] / tot, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]) if v["ms"] > 0}
     return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name),
             "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 2),
             "bytes_per_launch": d["bytes"] / max(1, d["launches"]),
             "time_share": shares, "kernel_time_fraction_of_steps": round(tot * 1e-3 / elapsed_s, 4)}
@@ -193,9 +222,9 @@ def main():
                    "solver": "multicolour BILU(0); FP64 FGMRES(30) with 5 FP32 BILU(0)-Richardson inner sweeps" if head == "mixed"
                    else "multicolour BILU(0); FP64 GMRES(30)",
                    "cells": m.nt},
-        "roofline": roofline(r["profile"], r["elapsed_s"]),
+        "roofline": roofline(r["profile"], r["profiled_elapsed_s"]),
         "cpu_baseline": cpu,
-        "forms": {f: {k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s")}
+        "forms": {f: {k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")}
                   for f in forms},
         "latency_ms": {"step_p50": r["step_ms_p50"], "step_p99": r["step_ms_p99"]},
         "device": torch.cuda.get_device_name(0),

@@ -1,0 +1,121 @@
+"""Turn rocprofv3 counter traces of libgks into per-kernel-class HBM traffic.
+
+Usage (after two counter runs of the same command, FETCH_SIZE then
+WRITE_SIZE, each converted with ``rocpd2csv -i <db> -d <dir>``):
+
+    python -m paper_1802_00704_amd.profiling <fetch_csv_dir> <write_csv_dir>
+
+prints, per kernel class of the library's event profiler, the mean HBM
+bytes per launch.  Counter values (KiB per dispatch) are scaled by what
+the same counter reads for the library's plain copy kernel ``k_copy``, whose
+bytes are known exactly (8 bytes read and 8 written per element of its
+grid).  The output also carries a SHA-256 of the kernel sources, so a reader
+can tell whether the figures still describe the current kernels.
+"""
+from __future__ import annotations
+
+import collections
+import csv
+import glob
+import hashlib
+import os
+import re
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCES = ("csrc/gks_kernels.hip", "csrc/gks_flux_device.h", "csrc/gks_internal.h")
+
+# rocprof kernel symbol (without arguments) -> event-profiler class name
+CLASS_OF = [
+    (r"k_mx_fwd", "ilu_fwd32"), (r"k_mx_bwd", "ilu_bwd32"),
+    (r"k_ilu_fwd", "ilu_fwd"), (r"k_ilu_bwd", "ilu_bwd"),
+    (r"k_spmv<double, double, true>", "spmv_resid"), (r"k_spmv", "spmv"),
+    (r"k_dots", "dots"), (r"k_axpy", "axpy_dots"), (r"k_combine", "combine"), (r"k_acc", "axpy"),
+    (r"k_sum_partials", "finalize"), (r"k_gmres_ctl", "misc"), (r"k_mask_cols", "misc"),
+    (r"k_copyout", "copyout"), (r"k_rhs", "rhs"), (r"k_flux", "flux"), (r"k_update", "update"),
+    (r"k_cfl", "cfl"), (r"k_copy", "copy"),
+]
+
+
+def kernel_sources_sha256() -> str:
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(HERE, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def kernel_class(name: str) -> str | None:
+    base = re.sub(r"\(.*", "", name).replace("void ", "").replace("gks::", "").strip()
+    for pat, cls in CLASS_OF:
+        if base.startswith(pat):
+            return cls
+    return None
+
+
+def _load(path_dir: str, counter: str):
+    files = glob.glob(os.path.join(path_dir, "*counter_collection*.csv"))
+    if not files:
+        raise FileNotFoundError("no counter_collection csv in %s" % path_dir)
+    rows = []
+    for r in csv.DictReader(open(files[0])):
+        if r["Counter_Name"] == counter:
+            rows.append((r["Kernel_Name"], int(r["Grid_Size"]), float(r["Counter_Value"])))
+    return rows
+
+
+def traffic(fetch_dir: str, write_dir: str) -> dict:
+    f = _load(fetch_dir, "FETCH_SIZE")
+    w = _load(write_dir, "WRITE_SIZE")
+
+    def calib(rows):
+        cp = [(g, v) for n, g, v in rows if kernel_class(n) == "copy"]
+        if not cp:
+            raise ValueError("the copy kernel is missing from the trace")
+        return sum(8.0 * g for g, _ in cp) / sum(1024.0 * v for _, v in cp)
+
+    cf, cw = calib(f), calib(w)
+    out = collections.OrderedDict()
+    for rows, key, c in ((f, "fetch", cf), (w, "write", cw)):
+        acc = collections.defaultdict(list)
+        for n, _, v in rows:
+            cls = kernel_class(n)
+            if cls:
+                acc[cls].append(1024.0 * v * c)
+        for cls, vals in acc.items():
+            out.setdefault(cls, {})[key] = sum(vals) / len(vals)
+            out[cls]["launches"] = len(vals)
+    return {"calibration": {"fetch": cf, "write": cw}, "classes": out}
+
+
+def main(argv):
+    if len(argv) != 3:
+        print(__doc__)
+        return 2
+    t = traffic(argv[1], argv[2])
+    print("kernel_sources_sha256 %s" % kernel_sources_sha256())
+    print("calibration fetch %.6f write %.6f" % (t["calibration"]["fetch"], t["calibration"]["write"]))
+    print("%-12s %8s %16s %16s %16s" % ("class", "launches", "fetch_B/launch", "write_B/launch", "traffic_B/launch"))
+    for cls, d in t["classes"].items():
+        fe, wr = d.get("fetch", 0.0), d.get("write", 0.0)
+        print("%-12s %8d %16.0f %16.0f %16.0f" % (cls, d["launches"], fe, wr, fe + wr))
+    return 0
+
+
+def read_summary(path: str) -> tuple[str, dict]:
+    """(sha256, {class: traffic bytes per launch}) from a committed summary."""
+    sha, table = "", {}
+    for line in open(path):
+        parts = line.split()
+        if len(parts) == 2 and parts[0] == "kernel_sources_sha256":
+            sha = parts[1]
+        elif len(parts) == 5 and not line.startswith("#") and parts[0] != "class":
+            try:
+                table[parts[0]] = float(parts[4])
+            except ValueError:
+                pass
+    return sha, table
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv))
