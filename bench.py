@@ -177,6 +177,24 @@ def roofline(prof: dict, elapsed_s: float):
             "time_share": shares, "kernel_time_fraction_of_steps": round(tot * 1e-3 / elapsed_s, 4)}
 
 
+def serving_leg(n_requests: int, slots: int) -> dict:
+    """The first n_requests of the seeded serving stream (Poisson arrivals at
+    40/s; advection or shock-vortex, 2e3-2e5 triangles log-uniform, 50-500
+    steps, FP64 or mixed), served with continuous batching."""
+    import gks_inputs as gi
+    import paper_1802_00704_amd as g
+    from paper_1802_00704_amd.serving import Request, Server
+    reqs = []
+    for sp in gi.serving_specs(n_requests):
+        m, W0 = gi.serving_case(sp)
+        prm = {"precision": g.GKS_MIXED if sp["mixed"] else g.GKS_FP64, "nonphys_fallback": 1}
+        reqs.append(Request(rid=sp["rid"], mesh=m, W0=W0, steps=sp["steps"], params=prm, arrival=sp["arrival"]))
+    stats = Server(slots=slots).run(reqs, realtime=True)
+    stats["stream"] = ("first %d of 2000 seeded requests, Poisson 40/s, 2e3-2e5 triangles, 50-500 steps, "
+                       "50/50 FP64/mixed" % n_requests)
+    return stats
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -186,6 +204,9 @@ def main():
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--serving-requests", type=int, default=60,
+                    help="requests of the serving stream to run after the throughput legs (0: skip)")
+    ap.add_argument("--serving-slots", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X only; multi-GPU runs are not part of this build "
@@ -204,6 +225,11 @@ def main():
               flush=True)
     head = forms[0]
     r = res[head]
+    serving = serving_leg(args.serving_requests, args.serving_slots) if args.serving_requests > 0 else None
+    if serving:
+        print("# serving: %.4g cell-steps/s, step p50/p99 %.2f/%.2f ms, solve p50/p99 %.2f/%.2f ms" %
+              (serving["throughput_cell_steps_per_s"], serving["step_ms_p50"], serving["step_ms_p99"],
+               serving["solve_ms_p50"], serving["solve_ms_p99"]), file=sys.stderr, flush=True)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload)
     out = {
         "metric": METRIC,
@@ -226,7 +252,12 @@ def main():
         "cpu_baseline": cpu,
         "forms": {f: {k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")}
                   for f in forms},
-        "latency_ms": {"step_p50": r["step_ms_p50"], "step_p99": r["step_ms_p99"]},
+        "latency_ms": {"step_p50": r["step_ms_p50"], "step_p99": r["step_ms_p99"],
+                       "serving_step_p50": serving["step_ms_p50"] if serving else None,
+                       "serving_step_p99": serving["step_ms_p99"] if serving else None,
+                       "serving_solve_p50": serving["solve_ms_p50"] if serving else None,
+                       "serving_solve_p99": serving["solve_ms_p99"] if serving else None},
+        "serving": serving,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out))

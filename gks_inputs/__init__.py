@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Mesh", "jss_mesh", "cell_average", "density_advection_ic",
     "density_advection_exact", "shock_vortex_ic", "cavity_ic",
-    "prim_to_cons", "random_coefficients", "BC_NONE", "BC_SLIP",
+    "prim_to_cons", "random_coefficients", "serving_specs", "serving_case", "BC_NONE", "BC_SLIP",
     "BC_NOSLIP", "BC_INFLOW", "BC_OUTFLOW",
 ]
 
@@ -269,9 +269,18 @@ def shock_vortex_ic(mesh: Mesh, gamma: float = 1.4, mach: float = 1.1,
         p = rho * T
         return prim_to_cons(rho, left[1] + du, left[2] + dv, p, gamma)
 
-    Wl = cell_average(mesh, fn)
+    v = mesh.unwrapped_vertices()
+    cx = v[..., 0].mean(axis=1)
+    cy = v[..., 1].mean(axis=1)
+    Wl = prim_to_cons(np.full(mesh.nt, left[0]), left[1], left[2], left[3], gamma)
+    # the perturbation is below 1e-17 beyond r = 14 rc: average only near the vortex
+    near = np.hypot(cx - center[0], cy - center[1]) < 14.0 * rc + 2.0 * np.sqrt(
+        np.max(np.abs(v[..., 0] - cx[:, None]) + np.abs(v[..., 1] - cy[:, None]), axis=1) ** 2)
+    if np.any(near):
+        sub = Mesh(xy=mesh.xy, tri=mesh.tri[near], edge_tag=mesh.edge_tag[near], periodic=mesh.periodic,
+                   L=mesh.L, origin=mesh.origin, bc_table=mesh.bc_table)
+        Wl[:, near] = cell_average(sub, fn)
     Wr = prim_to_cons(np.full(mesh.nt, right[0]), right[1], right[2], right[3], gamma)
-    cx = mesh.unwrapped_vertices()[..., 0].mean(axis=1)
     return np.where((cx < x_shock)[None], Wl, Wr)
 
 
@@ -279,6 +288,38 @@ def cavity_ic(mesh: Mesh, gamma: float = 1.4, mach: float = 0.15) -> np.ndarray:
     """Fluid at rest: rho = 1, p = 1 / (gamma Ma^2) so a unit lid speed has Mach Ma."""
     p = 1.0 / (gamma * mach * mach)
     return prim_to_cons(np.ones(mesh.nt), 0.0, 0.0, p, gamma)
+
+
+def serving_specs(n_requests: int = 2000, rate: float = 40.0, seed: int = 5, nt_range=(2e3, 2e5),
+                  steps_range=(50, 500)) -> list:
+    """Seeded request stream: Poisson arrivals at `rate` per second; each
+    request is density advection or shock-vortex (50/50) on a JSS mesh whose
+    triangle count is log-uniform in nt_range, runs a uniform integer number
+    of steps in steps_range, in the FP64 or mixed form (50/50)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    gaps = rng.exponential(1.0 / rate, n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    kinds = rng.integers(0, 2, n_requests)
+    nts = np.exp(rng.uniform(np.log(nt_range[0]), np.log(nt_range[1]), n_requests))
+    steps = rng.integers(steps_range[0], steps_range[1] + 1, n_requests)
+    mixed = rng.integers(0, 2, n_requests)
+    seeds = rng.integers(1, 2 ** 31 - 1, n_requests)
+    return [{"rid": i, "kind": "advection" if kinds[i] == 0 else "shock_vortex", "nt": float(nts[i]),
+             "steps": int(steps[i]), "mixed": bool(mixed[i]), "seed": int(seeds[i]), "arrival": float(arrivals[i])}
+            for i in range(n_requests)]
+
+
+def serving_case(spec: dict):
+    """(mesh, W0) of one request of serving_specs."""
+    if spec["kind"] == "advection":
+        n = max(3, int(round(np.sqrt(spec["nt"] / 2.0))))
+        m = jss_mesh(n, n, spec["seed"])
+        return m, density_advection_ic(m)
+    ny = max(2, int(round(np.sqrt(spec["nt"] / 4.0))))
+    left, _ = shock_vortex_states()
+    walls = ((BC_INFLOW, left), (BC_OUTFLOW, None), (BC_SLIP, None), (BC_SLIP, None))
+    m = jss_mesh(2 * ny, ny, spec["seed"], Lx=2.0, Ly=1.0, periodic=False, walls=walls)
+    return m, shock_vortex_ic(m)
 
 
 def random_coefficients(nt: int, seed: int, scale: float = 0.05) -> np.ndarray:

@@ -113,6 +113,8 @@ typedef struct {
     int32_t restarts[4];     /* restart cycles                                   */
     double  rel_resid[4];    /* final true relative residual ||R - K X|| / ||R|| */
     int32_t nonphys;         /* non-physical Gauss-point states met in the flux  */
+    double  solve_ms;        /* host wall time of the reconstruction solve       */
+    double  call_ms;         /* host wall time of the whole call                 */
 } gks_solve_info;
 
 /* Mesh statistics. */

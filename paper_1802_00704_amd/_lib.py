@@ -53,11 +53,12 @@ class Params(C.Structure):
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32 * 4), ("restarts", C.c_int32 * 4), ("rel_resid", C.c_double * 4),
-                ("nonphys", C.c_int32)]
+                ("nonphys", C.c_int32), ("solve_ms", C.c_double), ("call_ms", C.c_double)]
 
     def as_dict(self):
         return {"iters": list(self.iters), "restarts": list(self.restarts),
-                "rel_resid": list(self.rel_resid), "nonphys": int(self.nonphys)}
+                "rel_resid": list(self.rel_resid), "nonphys": int(self.nonphys),
+                "solve_ms": float(self.solve_ms), "call_ms": float(self.call_ms)}
 
 
 class Stats(C.Structure):

@@ -956,10 +956,18 @@ int solve_fgmres_mixed(gks_mesh* m, gks_solve_info* info) {
     return status;
 }
 
+double ms_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+}
+
+// RHS + solve; the solve's wall time (it synchronises on every convergence
+// check, so host time measures the device work) goes to info->solve_ms.
 int run_solve(gks_mesh* m, const double* W, gks_solve_info* info) {
+    const auto t0 = std::chrono::steady_clock::now();
     launch_rhs(m, W);
-    if (m->prm.precision == GKS_MIXED) return solve_fgmres_mixed(m, info);
-    return solve_gmres(m, info);
+    const int st = m->prm.precision == GKS_MIXED ? solve_fgmres_mixed(m, info) : solve_gmres(m, info);
+    if (info) info->solve_ms = ms_since(t0);
+    return st;
 }
 
 void prof_collect(gks_mesh* m) {
@@ -1064,6 +1072,7 @@ int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_
 
 int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info* info) {
     if (!m) return GKS_EINVAL;
+    const auto t_call = std::chrono::steady_clock::now();
     if (!W || !X || (const void*)W == (const void*)X) {
         m->err = "null or aliased W / X";
         return GKS_EINVAL;
@@ -1073,7 +1082,10 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
         launch_copyout(m, m->w.X, X);
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
-        if (info) info->nonphys = 0;
+        if (info) {
+            info->nonphys = 0;
+            info->call_ms = ms_since(t_call);
+        }
         if (st != GKS_OK) m->err = "GMRES did not converge within max_iter";
         return st;
     } catch (const Fail& f) {
@@ -1111,6 +1123,7 @@ int gks_flux(gks_mesh* m, const double* W, const double* X, double dt, double* F
 
 int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info* info) {
     if (!m) return GKS_EINVAL;
+    const auto t_call = std::chrono::steady_clock::now();
     if (!W) {
         m->err = "null W";
         return GKS_EINVAL;
@@ -1146,6 +1159,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         launch_copy(m, W, w.Wn, (int64_t)4 * m->d.nt);
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
+        if (info) info->call_ms = ms_since(t_call);
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
