@@ -26,8 +26,9 @@
  *     (sum over the two Gauss points of (S/2) times the time-integrated flux
  *     per unit length, Eqs. fluxgauss and fvm3), positive from owner to
  *     neighbour.
- *   - All device work is ordered on the HIP stream given at creation (NULL =
- *     the default stream).  Device pointers must belong to the device that
+ *   - All device work is ordered on the HIP stream given at creation; for
+ *     NULL the handle creates a stream of its own (which synchronises with
+ *     the legacy default stream).  Device pointers must belong to the device that
  *     was current at creation.  Calls on one handle are not thread-safe;
  *     distinct handles are independent.
  *   - Every call returns GKS_OK (0) or a negative error code and never
@@ -105,6 +106,16 @@ typedef struct {
     int32_t nonphys_fallback;/* 0: non-physical Gauss-point state -> GKS_ENONPHYS;
                                 1: that side falls back to its cell average     */
     int32_t all_quadratic;   /* testing: quadratic reconstruction in every cell  */
+    int32_t graphs;          /* 1: gks_step replays two captured HIP graphs
+                                (solve with the first GMRES cycle unrolled to
+                                a step budget; flux and update), continuing on
+                                the host when the cycle needs more steps; 0:
+                                eager launches.  Results are identical.  Graphs
+                                are not used while gks_profile_enable is on.  */
+    int32_t graph_budget;    /* Arnoldi steps unrolled in the solve graph: 0 =
+                                adaptive (follows the first-cycle length of
+                                recent steps, re-capturing when it changes);
+                                k > 0 = exactly min(k, restart, max_iter)       */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -124,10 +135,14 @@ typedef struct {
     int32_t n_colors;        /* colours (multicolour order) or 0                 */
     int32_t rcm_bandwidth;   /* max |i - j| over cell neighbours in RCM order    */
     int64_t device_bytes;    /* device memory held by the handle                 */
+    int64_t graph_steps;     /* gks_step calls run through the captured graphs   */
+    int32_t capture_failures;/* graph captures that failed (the step then ran
+                                with eager launches; 3 turn graphs off)         */
 } gks_mesh_stats;
 
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
- * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour. */
+ * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
+ * graph replay on. */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

@@ -48,7 +48,8 @@ class Params(C.Structure):
     _fields_ = [("gamma", C.c_double), ("mu", C.c_double), ("tau_eps", C.c_double), ("cls_w", C.c_double),
                 ("cfl", C.c_double), ("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("ordering", C.c_int32), ("inner_iters", C.c_int32),
-                ("exact_time", C.c_int32), ("nonphys_fallback", C.c_int32), ("all_quadratic", C.c_int32)]
+                ("exact_time", C.c_int32), ("nonphys_fallback", C.c_int32), ("all_quadratic", C.c_int32),
+                ("graphs", C.c_int32), ("graph_budget", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -63,7 +64,8 @@ class SolveInfo(C.Structure):
 
 class Stats(C.Structure):
     _fields_ = [("nt", C.c_int32), ("nf", C.c_int32), ("nf_boundary", C.c_int32), ("n_levels", C.c_int32),
-                ("n_colors", C.c_int32), ("rcm_bandwidth", C.c_int32), ("device_bytes", C.c_int64)]
+                ("n_colors", C.c_int32), ("rcm_bandwidth", C.c_int32), ("device_bytes", C.c_int64),
+                ("graph_steps", C.c_int64), ("capture_failures", C.c_int32)]
 
 
 class HostSystem(C.Structure):

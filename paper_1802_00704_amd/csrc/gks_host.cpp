@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <type_traits>
+#include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
@@ -447,15 +448,25 @@ std::vector<int> rcm_order(const HostMesh& hm) {
 }
 
 // ------------------------------------------------------------------ device helpers
+// Handles may live on several host threads (one per stream).  Allocation,
+// release and stream capture are serialised process-wide, and no library
+// call synchronises the whole device or uses the legacy stream, so one
+// handle's set-up or tear-down cannot disturb another handle's capture.
+std::mutex g_dev_mu;
+
 template <typename T>
 T* dev_upload(gks_mesh* m, const std::vector<T>& h) {
     T* p = nullptr;
     const size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
     hipError_t e = hipMalloc((void**)&p, bytes);
     if (e != hipSuccess) throw Fail{GKS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     m->allocs.push_back(p);
     m->dev_bytes += (int64_t)bytes;
-    if (!h.empty()) HIPCHK(hipMemcpy(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!h.empty()) {
+        HIPCHK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+    }
     return p;
 }
 
@@ -463,11 +474,12 @@ template <typename T>
 T* dev_alloc(gks_mesh* m, size_t count) {
     T* p = nullptr;
     const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
     hipError_t e = hipMalloc((void**)&p, bytes);
     if (e != hipSuccess) throw Fail{GKS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     m->allocs.push_back(p);
     m->dev_bytes += (int64_t)bytes;
-    HIPCHK(hipMemset(p, 0, bytes));
+    HIPCHK(hipMemsetAsync(p, 0, bytes, m->stream));   // set-up only, never captured
     return p;
 }
 
@@ -808,14 +820,18 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     w.Xcell = dev_alloc<double>(m, (size_t)20 * nt);
     w.F = dev_alloc<double>(m, (size_t)4 * nf);
     w.Wn = dev_alloc<double>(m, (size_t)4 * nt);
+    w.Wint = dev_alloc<double>(m, (size_t)4 * nt);
     w.dt_dev = dev_alloc<double>(m, 1);
     w.dtpart = dev_alloc<double>(m, 1024);
     w.counters = (int32_t*)dev_alloc<double>(m, 2);
-    HIPCHK(hipHostMalloc((void**)&w.st_host, sizeof(Status), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&w.counters_host, 4 * sizeof(int32_t), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&w.scal_host, 4 * sizeof(double), hipHostMallocDefault));
-    HIPCHK(hipMemcpy(&w.ks->tol, &prm.tol, sizeof(double), hipMemcpyHostToDevice));
-    HIPCHK(hipDeviceSynchronize());
+    {
+        std::lock_guard<std::mutex> lk(g_dev_mu);
+        HIPCHK(hipHostMalloc((void**)&w.st_host, sizeof(Status), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&w.counters_host, 4 * sizeof(int32_t), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&w.scal_host, 4 * sizeof(double), hipHostMallocDefault));
+    }
+    HIPCHK(hipMemcpyAsync(&w.ks->tol, &prm.tol, sizeof(double), hipMemcpyHostToDevice, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
 }
 
 // ------------------------------------------------------------------ GMRES driver (FP64)
@@ -830,130 +846,224 @@ bool all_conv(const Status* s) {
     return true;
 }
 
-// Right-preconditioned restarted GMRES on the four columns in lockstep.
-// Returns GKS_OK or GKS_ENOCONV; fills info.
-int solve_gmres(gks_mesh* m, gks_solve_info* info) {
-    Work& w = m->w;
-    KrylovState* ks = w.ks;
-    const int n = m->d.n;
-    const int64_t vs = (int64_t)(n + 1) * CB;
-    const int mres = m->prm.restart;
-    int iters[NC] = {0, 0, 0, 0};
-    int cycles = 0, total = 0;
+// Restarted GMRES on the four columns in lockstep, right-preconditioned
+// (FP64: BILU(0) in FP64) or flexible (mixed: the preconditioner is q =
+// inner_iters sweeps of BILU(0)-preconditioned Richardson iteration on the
+// FP32 copies of K and of the factors, z = M^-1 v; z += M^-1 (v - K z)).
+// Arnoldi with classical Gram-Schmidt applied twice, Givens rotations and
+// all convergence bookkeeping stay on the device (k_gmres_ctl); the host
+// reads the status once per step.  The same launch sequence is issued
+// eagerly or captured into a graph; in a graph the kernels are gated on the
+// device flags st.run (Arnoldi steps) and st.fin (end of cycle), so the
+// arithmetic is the same either way.
 
-    launch_dots_reduce(m, KC_DOTS, w.R, 0, 1, w.R, nullptr, ks->sq);
+// norms of the right-hand side, zero columns of X masked
+void solve_begin(gks_mesh* m) {
+    Work& w = m->w;
+    launch_dots_reduce(m, KC_DOTS, w.R, 0, 1, w.R, nullptr, w.ks->sq);
     launch_ctl(m, 0);
     launch_mask_cols(m, w.X);
+}
+
+// r = R - K X, its norms, v_0 = r / |r|   (gate: st.fin in graphs)
+void cycle_start(gks_mesh* m, const int32_t* gate) {
+    Work& w = m->w;
+    launch_resid(m, w.X, w.R, w.V, gate);
+    launch_dots_reduce(m, KC_DOTS, w.V, 0, 1, w.V, nullptr, w.ks->sq, gate);
+    launch_ctl(m, 1, gate != nullptr);
+}
+
+// Arnoldi step k: w = K M^-1 v_k, two Gram-Schmidt passes, |w|, Givens
+void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
+    Work& w = m->w;
+    KrylovState* ks = w.ks;
+    const int64_t vs = (int64_t)(m->d.n + 1) * CB;
+    double* vk = w.V + (int64_t)k * vs;
+    double* vk1 = w.V + (int64_t)(k + 1) * vs;
+    const double* sk = &ks->scale[k][0];
+    if (m->prm.precision == GKS_MIXED) {
+        float* zk = w.Z + (int64_t)k * vs;
+        for (int j = 0; j < m->prm.inner_iters; ++j) launch_mx_sweep(m, j == 0, vk, sk, w.yf, w.df, zk, gate);
+        launch_spmv64_f32x(m, zk, w.w, gate);
+    } else {
+        launch_ilu(m, vk, sk, w.t1, w.t2, gate);
+        launch_spmv64(m, w.t2, nullptr, w.w, gate);
+    }
+    launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0], gate);
+    launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, gate);
+    launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0], gate);
+    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, gate);
+    launch_dots_reduce(m, KC_DOTS, vk1, 0, 1, vk1, nullptr, ks->sq, gate);
+    launch_ctl(m, 2);
+}
+
+// End of a cycle of nvec steps: y from the triangular system, then
+// X += M^-1 (V y) (FP64) or X += Z y (mixed).  In graphs the device count
+// st.k bounds nvec and st.fin gates the work.
+void end_cycle(gks_mesh* m, int nvec, bool graph) {
+    Work& w = m->w;
+    KrylovState* ks = w.ks;
+    const int64_t vs = (int64_t)(m->d.n + 1) * CB;
+    const int32_t* gate = graph ? &ks->st.fin : nullptr;
+    const int32_t* nvec_dev = graph ? &ks->st.k : nullptr;
+    launch_ctl(m, 3, graph);
+    if (m->prm.precision == GKS_MIXED) {
+        launch_combine_f32(m, w.Z, vs, nvec, &ks->y[0][0], w.ones, w.t1, nvec_dev, gate);
+        launch_acc(m, w.X, w.t1, gate);
+    } else {
+        launch_combine(m, w.V, vs, nvec, &ks->y[0][0], &ks->scale[0][0], w.t1, nvec_dev, gate);
+        launch_ilu(m, w.t1, nullptr, w.t2, w.t3, gate);
+        launch_acc(m, w.X, w.t3, gate);
+    }
+}
+
+void fill_info(gks_mesh* m, gks_solve_info* info) {
+    if (!info) return;
+    const Status* st = m->w.st_host;
+    for (int c = 0; c < NC; ++c) {
+        info->iters[c] = st->its[c];
+        info->restarts[c] = st->cycles;
+        info->rel_resid[c] = st->bnorm[c] > 0.0 ? st->beta[c] / st->bnorm[c] : 0.0;
+    }
+}
+
+enum { RESUME_NONE = 0, RESUME_CYCLE_START = 1, RESUME_IN_CYCLE = 2 };
+
+// Host-driven cycles from the state the device holds.  RESUME_NONE: the
+// solve starts (R is in place); RESUME_CYCLE_START: the status of a cycle
+// start has been read; RESUME_IN_CYCLE: k0 steps of the current cycle are
+// done.  Returns GKS_OK or GKS_ENOCONV; fills info.
+int solve_loop(gks_mesh* m, gks_solve_info* info, int resume, int k0) {
+    const Status* st = m->w.st_host;
+    const int mres = m->prm.restart;
+    if (resume == RESUME_NONE) solve_begin(m);
     int status = GKS_ENOCONV;
-    for (;;) {
-        launch_resid(m, w.X, w.R, w.V);
-        launch_dots_reduce(m, KC_DOTS, w.V, 0, 1, w.V, nullptr, ks->sq);
-        launch_ctl(m, 1);
-        read_status(m);
-        if (all_conv(w.st_host)) {
-            status = GKS_OK;
-            break;
-        }
-        if (total >= m->prm.max_iter) break;
-        ++cycles;
+    for (;; resume = RESUME_NONE) {
         int k = 0;
-        while (k < mres && total < m->prm.max_iter) {
-            double* vk = w.V + (int64_t)k * vs;
-            double* vk1 = w.V + (int64_t)(k + 1) * vs;
-            launch_ilu(m, vk, &ks->scale[k][0], w.t1, w.t2);
-            launch_spmv64(m, w.t2, nullptr, w.w);
-            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0]);
-            launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w);
-            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0]);
-            launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1);
-            launch_dots_reduce(m, KC_DOTS, vk1, 0, 1, vk1, nullptr, ks->sq);
-            launch_ctl(m, 2);
+        if (resume == RESUME_IN_CYCLE) {
+            k = k0;
+        } else {
+            if (resume == RESUME_NONE) {
+                cycle_start(m, nullptr);
+                read_status(m);
+            }
+            if (all_conv(st)) {
+                status = GKS_OK;
+                break;
+            }
+            if (st->total >= m->prm.max_iter) break;
+        }
+        while (k < mres && st->total < m->prm.max_iter) {
+            arnoldi_step(m, k, nullptr);
             ++k;
-            ++total;
             read_status(m);
-            for (int c = 0; c < NC; ++c)
-                if (!w.st_host->conv[c]) iters[c] = total;
-            if (all_conv(w.st_host)) break;
+            if (all_conv(st)) break;
         }
-        launch_ctl(m, 3);
-        launch_combine(m, w.V, vs, k, &ks->y[0][0], &ks->scale[0][0], w.t1);
-        launch_ilu(m, w.t1, nullptr, w.t2, w.t3);
-        launch_acc(m, w.X, w.t3);
+        end_cycle(m, k, false);
     }
-    if (info) {
-        for (int c = 0; c < NC; ++c) {
-            info->iters[c] = iters[c];
-            info->restarts[c] = cycles;
-            const double bn = w.st_host->bnorm[c];
-            info->rel_resid[c] = bn > 0.0 ? w.st_host->beta[c] / bn : 0.0;
-        }
-    }
+    fill_info(m, info);
     return status;
 }
 
-// Mixed precision: flexible GMRES in FP64 (Arnoldi with CGS2, Givens, true
-// residual with the FP64 matrix) preconditioned by q = inner_iters sweeps of
-// BILU(0)-preconditioned Richardson iteration on the FP32 copies of K and of
-// the factors:  z = M^-1 v;  z += M^-1 (v - K z)  (q - 1 times).
-int solve_fgmres_mixed(gks_mesh* m, gks_solve_info* info) {
-    Work& w = m->w;
-    KrylovState* ks = w.ks;
-    const int n = m->d.n;
-    const int64_t vs = (int64_t)(n + 1) * CB;
-    const int mres = m->prm.restart;
-    const int q = m->prm.inner_iters;
-    int iters[NC] = {0, 0, 0, 0};
-    int cycles = 0, total = 0;
+// ------------------------------------------------------------------ captured step graphs
+// Graph A: RHS, solve set-up, the first cycle unrolled to `budget` gated
+// Arnoldi steps, the gated end of cycle and the next cycle start.  Graph B:
+// copy-out of X, fluxes and update.  Both read the handle's own buffers only
+// (W is copied into Wint first), so they stay valid for any caller W.
+void issue_solve_graph(gks_mesh* m, int budget) {
+    KrylovState* ks = m->w.ks;
+    launch_rhs(m, m->w.Wint);
+    solve_begin(m);
+    cycle_start(m, nullptr);
+    for (int k = 0; k < budget; ++k) arnoldi_step(m, k, &ks->st.run);
+    end_cycle(m, budget, true);
+    cycle_start(m, &ks->st.fin);
+}
 
-    launch_dots_reduce(m, KC_DOTS, w.R, 0, 1, w.R, nullptr, ks->sq);
-    launch_ctl(m, 0);
-    launch_mask_cols(m, w.X);
-    int status = GKS_ENOCONV;
-    for (;;) {
-        launch_resid(m, w.X, w.R, w.V);
-        launch_dots_reduce(m, KC_DOTS, w.V, 0, 1, w.V, nullptr, ks->sq);
-        launch_ctl(m, 1);
-        read_status(m);
-        if (all_conv(w.st_host)) {
-            status = GKS_OK;
-            break;
-        }
-        if (total >= m->prm.max_iter) break;
-        ++cycles;
-        int k = 0;
-        while (k < mres && total < m->prm.max_iter) {
-            double* vk = w.V + (int64_t)k * vs;
-            double* vk1 = w.V + (int64_t)(k + 1) * vs;
-            float* zk = w.Z + (int64_t)k * vs;
-            const double* sk = &ks->scale[k][0];
-            for (int j = 0; j < q; ++j) launch_mx_sweep(m, j == 0, vk, sk, w.yf, w.df, zk);
-            launch_spmv64_f32x(m, zk, w.w);
-            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0]);
-            launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w);
-            launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0]);
-            launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1);
-            launch_dots_reduce(m, KC_DOTS, vk1, 0, 1, vk1, nullptr, ks->sq);
-            launch_ctl(m, 2);
-            ++k;
-            ++total;
-            read_status(m);
-            for (int c = 0; c < NC; ++c)
-                if (!w.st_host->conv[c]) iters[c] = total;
-            if (all_conv(w.st_host)) break;
-        }
-        launch_ctl(m, 3);
-        launch_combine_f32(m, w.Z, vs, k, &ks->y[0][0], w.ones, w.t1);
-        launch_acc(m, w.X, w.t1);
+void issue_update_graph(gks_mesh* m) {
+    Work& w = m->w;
+    launch_copyout(m, w.X, w.Xcell);
+    launch_zero_i32(m, w.counters, 4);
+    launch_flux(m, w.Wint, w.Xcell, w.dt_dev, w.F);
+    launch_update(m, w.Wint, w.F, w.Wn);
+}
+
+// A capture that did not produce an executable graph (nothing of it ran).
+struct CaptureFailed {
+    std::string msg;
+};
+
+template <typename F>
+hipGraphExec_t capture(gks_mesh* m, F&& issue) {
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    hipError_t e = hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) throw CaptureFailed{std::string("hipStreamBeginCapture: ") + hipGetErrorString(e)};
+    m->capturing = true;
+    std::string why;
+    try {
+        issue();
+    } catch (const LaunchError& le) {
+        why = std::string("launch of ") + le.kernel + ": " + hipGetErrorString(le.err);
+    } catch (const Fail& f) {
+        why = f.msg;
     }
-    if (info) {
-        for (int c = 0; c < NC; ++c) {
-            info->iters[c] = iters[c];
-            info->restarts[c] = cycles;
-            const double bn = w.st_host->bnorm[c];
-            info->rel_resid[c] = bn > 0.0 ? w.st_host->beta[c] / bn : 0.0;
-        }
+    m->capturing = false;
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(m->stream, &g);
+    if (why.empty() && e != hipSuccess) why = std::string("hipStreamEndCapture: ") + hipGetErrorString(e);
+    hipGraphExec_t ex = nullptr;
+    if (why.empty()) {
+        e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) why = std::string("hipGraphInstantiate: ") + hipGetErrorString(e);
     }
-    return status;
+    if (g) (void)hipGraphDestroy(g);
+    if (!why.empty()) {
+        (void)hipGetLastError();
+        throw CaptureFailed{why};
+    }
+    return ex;
+}
+
+// Both step graphs, (re)captured as needed before either is launched.
+void ensure_graphs(gks_mesh* m) {
+    const int cap = std::min(m->prm.restart, m->prm.max_iter);
+    if (m->prm.graph_budget > 0) m->budget = std::min(cap, m->prm.graph_budget);
+    if (m->budget <= 0) m->budget = cap;
+    if (!m->gB) m->gB = capture(m, [&] { issue_update_graph(m); });
+    if (!m->gA || m->gA_budget != m->budget) {
+        if (m->gA) (void)hipGraphExecDestroy(m->gA);
+        m->gA = nullptr;
+        m->gA = capture(m, [&] { issue_solve_graph(m, m->budget); });
+        m->gA_budget = m->budget;
+    }
+}
+
+// The solve of a step through graph A, continued on the host (same cycle,
+// same arithmetic) when the first cycle needs more steps than the graph
+// holds.  The budget follows the first-cycle length of recent steps: it
+// grows at once when exceeded and shrinks when 4 or more steps were unused.
+int solve_graph(gks_mesh* m, gks_solve_info* info) {
+    const int cap = std::min(m->prm.restart, m->prm.max_iter);
+    HIPCHK(hipGraphLaunch(m->gA, m->stream));
+    read_status(m);
+    const Status* st = m->w.st_host;
+    int r;
+    if (all_conv(st)) {
+        fill_info(m, info);
+        r = GKS_OK;
+    } else if (st->run && st->k > 0) {
+        r = solve_loop(m, info, RESUME_IN_CYCLE, st->k);
+    } else {
+        r = solve_loop(m, info, RESUME_CYCLE_START, 0);
+    }
+    const int need = std::min(cap, std::max(1, (int)m->w.st_host->total));
+    if (m->prm.graph_budget > 0)
+        ;
+    else if (need > m->budget)
+        m->budget = std::min(cap, need + 2);
+    else if (need + 4 <= m->budget)
+        m->budget = std::min(cap, need + 2);
+    return r;
 }
 
 double ms_since(std::chrono::steady_clock::time_point t0) {
@@ -965,7 +1075,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 int run_solve(gks_mesh* m, const double* W, gks_solve_info* info) {
     const auto t0 = std::chrono::steady_clock::now();
     launch_rhs(m, W);
-    const int st = m->prm.precision == GKS_MIXED ? solve_fgmres_mixed(m, info) : solve_gmres(m, info);
+    const int st = solve_loop(m, info, RESUME_NONE, 0);
     if (info) info->solve_ms = ms_since(t0);
     return st;
 }
@@ -989,7 +1099,8 @@ bool params_ok(const gks_params& p) {
     return p.gamma > 1.0 && p.cfl > 0.0 && p.tol > 0.0 && p.restart >= 1 && p.restart <= MAXM &&
            p.max_iter >= 1 && p.mu >= 0.0 && p.tau_eps >= 0.0 && p.cls_w > 0.0 &&
            (p.precision == GKS_FP64 || p.precision == GKS_MIXED) &&
-           (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1;
+           (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
+           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0;
 }
 
 int fail(gks_mesh* m, const Fail& f) {
@@ -1020,6 +1131,8 @@ void gks_params_default(gks_params* p) {
     p->exact_time = 0;
     p->nonphys_fallback = 0;
     p->all_quadratic = 0;
+    p->graphs = 1;
+    p->graph_budget = 0;
 }
 
 int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_stream, gks_mesh** out) {
@@ -1055,6 +1168,11 @@ int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_
     m->stream = (hipStream_t)hip_stream;
     try {
         HIPCHK(hipGetDevice(&m->device));
+        if (!m->stream) {
+            std::lock_guard<std::mutex> lk(g_dev_mu);
+            HIPCHK(hipStreamCreate(&m->stream));
+            m->own_stream = true;
+        }
         setup(m, desc);
     } catch (const Fail& f) {
         g_create_err = f.msg;
@@ -1130,21 +1248,51 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
     }
     try {
         Work& w = m->w;
-        if (dt > 0.0)
-            launch_set_scalar(m, w.dt_dev, dt);
-        else
-            launch_cfl(m, W, w.dt_dev);
-        launch_zero_i32(m, w.counters, 4);
-        const int st = run_solve(m, W, info);
-        if (st != GKS_OK) {
-            HIPCHK(hipStreamSynchronize(m->stream));
-            prof_collect(m);
-            m->err = "GMRES did not converge within max_iter";
-            return st;
+        bool graphs = m->prm.graphs && !m->prof.on && m->capture_failures < 3;
+        if (graphs) {
+            try {
+                ensure_graphs(m);
+            } catch (const CaptureFailed& cf) {
+                // eager launches for this step (same kernels, same result)
+                ++m->capture_failures;
+                m->capture_err = cf.msg;
+                graphs = false;
+            }
         }
-        launch_copyout(m, w.X, w.Xcell);
-        launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
-        launch_update(m, W, w.F, w.Wn);
+        if (graphs) {
+            // graph path: the step works on the handle's copy of W
+            ++m->graph_steps;
+            launch_copy(m, w.Wint, W, (int64_t)4 * m->d.nt);
+            if (dt > 0.0)
+                launch_set_scalar(m, w.dt_dev, dt);
+            else
+                launch_cfl(m, w.Wint, w.dt_dev);
+            const auto t0 = std::chrono::steady_clock::now();
+            const int st = solve_graph(m, info);
+            if (info) info->solve_ms = ms_since(t0);
+            if (st != GKS_OK) {
+                HIPCHK(hipStreamSynchronize(m->stream));
+                m->err = "GMRES did not converge within max_iter";
+                return st;
+            }
+            HIPCHK(hipGraphLaunch(m->gB, m->stream));
+        } else {
+            if (dt > 0.0)
+                launch_set_scalar(m, w.dt_dev, dt);
+            else
+                launch_cfl(m, W, w.dt_dev);
+            launch_zero_i32(m, w.counters, 4);
+            const int st = run_solve(m, W, info);
+            if (st != GKS_OK) {
+                HIPCHK(hipStreamSynchronize(m->stream));
+                prof_collect(m);
+                m->err = "GMRES did not converge within max_iter";
+                return st;
+            }
+            launch_copyout(m, w.X, w.Xcell);
+            launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
+            launch_update(m, W, w.F, w.Wn);
+        }
         HIPCHK(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));
         HIPCHK(hipMemcpyAsync(w.scal_host, w.dt_dev, sizeof(double), hipMemcpyDeviceToHost, m->stream));
         HIPCHK(hipStreamSynchronize(m->stream));
@@ -1185,6 +1333,8 @@ int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st) {
     st->n_colors = m->n_colors;
     st->rcm_bandwidth = m->rcm_bw;
     st->device_bytes = m->dev_bytes;
+    st->graph_steps = m->graph_steps;
+    st->capture_failures = m->capture_failures;
     return GKS_OK;
 }
 
@@ -1303,13 +1453,17 @@ const char* gks_last_error(const gks_mesh* m) {
 
 void gks_destroy(gks_mesh* m) {
     if (!m) return;
-    (void)hipDeviceSynchronize();
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    std::lock_guard<std::mutex> lk(g_dev_mu);
     for (auto& p : m->prof.pending) {
         (void)hipEventDestroy(p.second.first);
         (void)hipEventDestroy(p.second.second);
     }
     for (auto e : m->prof.pool) (void)hipEventDestroy(e);
+    if (m->gA) (void)hipGraphExecDestroy(m->gA);
+    if (m->gB) (void)hipGraphExecDestroy(m->gB);
     for (void* p : m->allocs) (void)hipFree(p);
+    if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
     if (m->w.st_host) (void)hipHostFree(m->w.st_host);
     if (m->w.counters_host) (void)hipHostFree(m->w.counters_host);
     if (m->w.scal_host) (void)hipHostFree(m->w.scal_host);

@@ -53,8 +53,13 @@ struct Status {
     double beta[NC];              // ||r_c|| at the start of the cycle (true residual)
     double bnorm[NC];             // ||R_c||
     int32_t k;                    // Arnoldi steps done in this cycle
+    int32_t run;                  // 1 while the cycle continues (gates the iteration kernels)
+    int32_t fin;                  // 1 once the cycle has ended (gates the end-of-cycle kernels)
+    int32_t total;                // Arnoldi steps over all cycles of this solve
+    int32_t cycles;               // cycles begun
     int32_t conv[NC];             // 1 once the estimate meets tol
     int32_t active[NC];           // 0 for a zero right-hand side
+    int32_t its[NC];              // steps column c took part in before it converged
 };
 
 struct KrylovState {
@@ -124,6 +129,7 @@ struct Work {
     double* Xcell = nullptr;      // [4][5][nt] X in cell order (gks_step)
     double* F = nullptr;          // [4][nf]
     double* Wn = nullptr;         // [4][nt]
+    double* Wint = nullptr;       // [4][nt] the step's copy of W (graph path)
     double* dt_dev = nullptr;     // [1]
     double* dtpart = nullptr;     // block minima of the CFL rule
     int32_t* counters = nullptr;  // [4] nonphysical count, ...
@@ -145,6 +151,16 @@ struct gks_mesh {
     int64_t dev_bytes = 0;
     std::vector<void*> allocs;
     bool have_x = false;
+    bool capturing = false;       // a stream capture is in progress (no profiling events)
+    bool own_stream = false;      // the handle created m->stream itself
+    // captured step graphs (see gks_step): A = solve with a fixed iteration
+    // budget, B = copy-out, flux, update; rebuilt when the budget changes
+    hipGraphExec_t gA = nullptr, gB = nullptr;
+    int gA_budget = 0;            // Arnoldi steps captured in gA
+    int budget = 0;               // steps wanted in gA for the next step
+    int64_t graph_steps = 0;      // steps run through the graphs
+    int capture_failures = 0;     // captures that failed (3 turn graphs off)
+    std::string capture_err;      // the last capture failure
     std::string err;
 };
 
@@ -166,21 +182,29 @@ extern const char* kc_names[NPROF];
 
 // launchers (gks_kernels.hip); all enqueue on m->stream
 void launch_rhs(gks_mesh* m, const double* W);
-void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y);
-void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y);
-void launch_resid(gks_mesh* m, const double* x, const double* b, double* y);
-void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out);
-void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z);
+// gate: device flag; when non-null and zero the kernels return at once (used to
+// unroll a fixed iteration budget into a captured graph).
+void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y, const int32_t* gate = nullptr);
+void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* gate = nullptr);
+void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate = nullptr);
+void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out,
+                const int32_t* gate = nullptr);
+void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
+                     const int32_t* gate = nullptr);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
-                        const double* scale, double* out);
+                        const double* scale, double* out, const int32_t* gate = nullptr);
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                 const double* w, double* out);
+                 const double* w, double* out, const int32_t* gate = nullptr);
+// nvec_dev: when non-null the number of vectors is min(nvec, *nvec_dev)
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
-                    double* out);
+                    double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);
 void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, const double* y, const double* scale,
-                        double* out);
-void launch_acc(gks_mesh* m, double* X, const double* z);
-void launch_ctl(gks_mesh* m, int mode);
+                        double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);
+void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate = nullptr);
+// mode 0: norms of the right-hand side; 1: start of a cycle (true residual);
+// 2: Arnoldi step (skipped once st.run is 0); 3: triangular solve for y.
+// gated: skip unless st.fin is 1 (end-of-cycle work in a captured graph).
+void launch_ctl(gks_mesh* m, int mode, bool gated = false);
 void launch_mask_cols(gks_mesh* m, double* X);
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell);
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);

@@ -113,7 +113,9 @@ __global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__
 template <typename T, typename XT, bool RESID>
 __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col,
                                               const XT* __restrict__ x, const double* __restrict__ xscale,
-                                              const double* __restrict__ b, double* __restrict__ y) {
+                                              const double* __restrict__ b, double* __restrict__ y,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int i = xcd_row();
     if (i >= n) return;
     double acc[NC][NB];
@@ -164,7 +166,9 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int np, int r0, int r1, const T* __restrict__ Lv,
                                                  const int32_t* __restrict__ Lc, const double* __restrict__ v,
-                                                 const double* __restrict__ vscale, double* __restrict__ y) {
+                                                 const double* __restrict__ vscale, double* __restrict__ y,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int i = r0 + xcd_row();
     if (i >= r1) return;
     double acc[CB];
@@ -199,7 +203,9 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int np, int r0, int r1, 
 template <typename T>
 __global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int np, int r0, int r1, const T* __restrict__ Uv,
                                                  const int32_t* __restrict__ Uc, const T* __restrict__ Dinv,
-                                                 const double* __restrict__ y, double* __restrict__ z) {
+                                                 const double* __restrict__ y, double* __restrict__ z,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int i = r0 + xcd_row();
     if (i >= r1) return;
     double acc[CB];
@@ -250,7 +256,9 @@ __global__ void __launch_bounds__(TPB) k_mx_fwd(int n, int np, int r0, int r1, c
                                                 const int32_t* __restrict__ Kc, const float* __restrict__ Lv,
                                                 const int32_t* __restrict__ Lc, const double* __restrict__ v,
                                                 const double* __restrict__ vscale, const float* __restrict__ z,
-                                                float* __restrict__ y) {
+                                                float* __restrict__ y,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int i = r0 + xcd_row();
     if (i >= r1) return;
     ACC acc[CB];
@@ -304,7 +312,9 @@ template <bool FIRST, typename ACC>
 __global__ void __launch_bounds__(TPB) k_mx_bwd(int n, int np, int r0, int r1, const float* __restrict__ Uv,
                                                 const int32_t* __restrict__ Uc, const float* __restrict__ Dinv,
                                                 const float* __restrict__ y, float* __restrict__ d,
-                                                float* __restrict__ z) {
+                                                float* __restrict__ z,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int i = r0 + xcd_row();
     if (i >= r1) return;
     float* dd = FIRST ? z : d;
@@ -359,7 +369,9 @@ __global__ void __launch_bounds__(TPB) k_mx_bwd(int n, int np, int r0, int r1, c
 // (blockIdx.y selects the chunk).  Each block writes its partial sums to
 // partial[(j * NC + c) * nblk + blockIdx.x].
 __global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
-                                              const double* __restrict__ w, double* __restrict__ partial) {
+                                              const double* __restrict__ w, double* __restrict__ partial,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     __shared__ double sh[RED_CHUNK * NC][TPB / 64];
     const int j0 = blockIdx.y * RED_CHUNK;
     const int nj = min(RED_CHUNK, nvec - j0);
@@ -418,7 +430,9 @@ struct Grp {
 // out = w - sum_j h_j[c] scale_j[c] V_j   (out may alias w)
 __global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ V, int64_t vstride, int nvec,
                                               const double* __restrict__ h, const double* __restrict__ scale,
-                                              const double* w, double* out) {
+                                              const double* w, double* out,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / 10;
     const int p = (int)(t - i * 10);
@@ -440,7 +454,10 @@ __global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ 
 template <typename VT>
 __global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V, int64_t vstride, int nvec,
                                                  const double* __restrict__ y, const double* __restrict__ scale,
-                                                 double* __restrict__ out) {
+                                                 double* __restrict__ out, const int32_t* __restrict__ nvec_dev,
+                                                 const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
+    if (nvec_dev) nvec = min(nvec, *nvec_dev);
     constexpr int E = Grp<VT>::E, TC = Grp<VT>::T;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t i = t / TC;
@@ -466,7 +483,9 @@ __global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V
 }
 
 // X += z
-__global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X, const double* __restrict__ z) {
+__global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X, const double* __restrict__ z,
+                                             const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < len) X[i] += z[i];
 }
@@ -474,7 +493,9 @@ __global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X
 // Sum partials of nval values in a fixed order: one wave per value.
 // mode 0: out[v] = sum;  mode 1: out[v] = sum * scale[v]
 __global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const double* __restrict__ partial,
-                                                      const double* __restrict__ scale, double* __restrict__ out) {
+                                                      const double* __restrict__ scale, double* __restrict__ out,
+    const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
     const int v = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (v >= nval) return;
@@ -491,9 +512,12 @@ __global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const 
 // mode 2 (ARNOLDI): column k of H from h1 + h2 and ||w||^2, Givens rotation,
 //                   residual estimate, k += 1
 // mode 3 (SOLVE):   y = R^{-1} g over the first k columns
-__global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restrict__ ks) {
+__global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restrict__ ks, int mres, int gated) {
+    if (mode == 2 && ks->st.run == 0) return;   // the cycle has ended
+    if (gated && ks->st.fin == 0) return;        // end-of-cycle work while the cycle still runs
     const int c = threadIdx.x;
     const int k = ks->st.k;
+    const int conv_in = c < NC ? ks->st.conv[c] : 1;
     __syncthreads();
     if (c < NC) {
         Status& st = ks->st;
@@ -501,6 +525,7 @@ __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restr
             const double b = sqrt(ks->sq[c]);
             st.bnorm[c] = b;
             st.active[c] = b > 0.0;
+            st.its[c] = 0;
         } else if (mode == 1) {
             const double b = sqrt(ks->sq[c]);
             st.beta[c] = b;
@@ -539,6 +564,7 @@ __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restr
             const double e = bn > 0.0 ? fabs(ks->g[k + 1][c]) / bn : 0.0;
             st.est[c] = e;
             st.conv[c] = (!st.active[c]) || e <= ks->tol;
+            if (!conv_in) st.its[c] = st.total + 1;
         } else if (mode == 3) {
             for (int j = k - 1; j >= 0; --j) {
                 double s = ks->g[j][c];
@@ -550,8 +576,24 @@ __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restr
     }
     __syncthreads();
     if (c == 0) {
-        if (mode == 1) ks->st.k = 0;
-        if (mode == 2) ks->st.k = k + 1;
+        int all = 1;
+        for (int q = 0; q < NC; ++q) all &= ks->st.conv[q];
+        if (mode == 0) {
+            ks->st.total = 0;
+            ks->st.cycles = 0;
+        }
+        if (mode == 1) {
+            ks->st.k = 0;
+            ks->st.run = !all;
+            ks->st.fin = 0;
+            ks->st.cycles += !all;
+        }
+        if (mode == 2) {
+            ks->st.k = k + 1;
+            ks->st.total += 1;
+            ks->st.run = !all && (k + 1 < mres);
+            ks->st.fin = !ks->st.run;
+        }
     }
 }
 
@@ -846,7 +888,7 @@ __global__ void k_cfl_final(int nblk, const double* __restrict__ partial, double
 // ================================================================== launchers
 
 void prof_begin(gks_mesh* m, int kc, double bytes, double flops) {
-    if (!m->prof.on) return;
+    if (!m->prof.on || m->capturing) return;
     m->prof.bytes[kc] += bytes;
     m->prof.flops[kc] += flops;
     hipEvent_t a, b;
@@ -865,7 +907,7 @@ void prof_begin(gks_mesh* m, int kc, double bytes, double flops) {
 
 void prof_end(gks_mesh* m, int kc) {
     (void)kc;
-    if (!m->prof.on || m->prof.pending.empty()) return;
+    if (!m->prof.on || m->capturing || m->prof.pending.empty()) return;
     (void)hipEventRecord(m->prof.pending.back().second.second, m->stream);
 }
 
@@ -899,35 +941,38 @@ void launch_rhs(gks_mesh* m, const double* W) {
                                     m->d.a0c, W, m->w.R));
 }
 
-void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y) {
+void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_SPMV, spmv_bytes(n, 8, false), hipLaunchKernelGGL((k_spmv<double, double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, xscale, nullptr, y));
+                                         m->d.Kval, m->d.Kcol, x, xscale, nullptr, y, gate));
 }
 
-void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y) {
+void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_SPMV, n * (KW * 25.0 * 8 + KW * 4.0 + VB / 2 + VB), hipLaunchKernelGGL((k_spmv<double, float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, nullptr, nullptr, y));
+                                         m->d.Kval, m->d.Kcol, x, nullptr, nullptr, y, gate));
 }
 
-void launch_resid(gks_mesh* m, const double* x, const double* b, double* y) {
+void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, nullptr, b, y));
+                                         m->d.Kval, m->d.Kcol, x, nullptr, b, y, gate));
 }
 
 // One inner sweep of the mixed form over all levels (see k_mx_fwd/k_mx_bwd).
 
 template <typename ACC>
-static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z);
+static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
+                     const int32_t* gate);
 
-void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z) {
-    mx_sweep<double>(m, first, v, vscale, y, d, z);
+void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
+                     const int32_t* gate) {
+    mx_sweep<double>(m, first, v, vscale, y, d, z, gate);
 }
 
 template <typename ACC>
-static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z) {
+static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
+                     const int32_t* gate) {
     const int n = m->d.n;
     const auto& lp = m->d.lev_ptr;
     const int nl = (int)lp.size() - 1;
@@ -938,10 +983,10 @@ static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vsc
         const int rows = r1 - r0;
         if (first)
             PROFB(KC_ILU_FWD32, rows * (LW * 100.0 + LW * 4.0 + VB + 2 * VF), hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y));
+                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y, gate));
         else
             PROFB(KC_ILU_FWD32, rows * ((KW + LW) * 100.0 + (KW + LW) * 4.0 + VB + 3 * VF), hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y));
+                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y, gate));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
@@ -949,14 +994,14 @@ static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vsc
         const int rows = r1 - r0;
         if (first)
             PROFB(KC_ILU_BWD32, rows * (LW * 100.0 + 100.0 + LW * 4.0 + 3 * VF), hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z));
+                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z, gate));
         else
             PROFB(KC_ILU_BWD32, rows * (LW * 100.0 + 100.0 + LW * 4.0 + 5 * VF), hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z));
+                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z, gate));
     }
 }
 
-void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out) {
+void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out, const int32_t* gate) {
     const bool fp32 = false;
     const int n = m->d.n;
     const auto& lp = m->d.lev_ptr;
@@ -966,65 +1011,66 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
         if (r1 <= r0) continue;
         if (fp32)
             PROFB(KC_ILU_FWD32, ilu_fwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_fwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                  n, m->d.np, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp));
+                                                  n, m->d.np, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp, gate));
         else
             PROFB(KC_ILU_FWD, ilu_fwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_fwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                n, m->d.np, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp));
+                                                n, m->d.np, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp, gate));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         if (fp32)
             PROFB(KC_ILU_BWD32, ilu_bwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_bwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                  n, m->d.np, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out));
+                                                  n, m->d.np, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out, gate));
         else
             PROFB(KC_ILU_BWD, ilu_bwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_bwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                n, m->d.np, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out));
+                                                n, m->d.np, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out, gate));
     }
 }
 
 // partial sums of V_j . w for j < nvec into m->w.partial, then reduce
 // (times scale_j when scale != NULL) into out[j * NC + c].
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
-                        const double* scale, double* out) {
+                        const double* scale, double* out, const int32_t* gate) {
     const int n = m->d.n;
     const int nb = m->w.nblk_red;
     const int nch = (nvec + RED_CHUNK - 1) / RED_CHUNK;
     PROFB(kc, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_dots, dim3(nb, nch), dim3(TPB), 0, m->stream, n, V, vstride, nvec, w,
-                                m->w.partial));
+                                m->w.partial, gate));
     const int nval = nvec * NC;
     PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3((nval + 3) / 4), dim3(TPB), 0, m->stream, nval, nb,
-                                      m->w.partial, scale, out));
+                                      m->w.partial, scale, out, gate));
 }
 
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                 const double* w, double* out) {
+                 const double* w, double* out, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)n * 10)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
-                                          h, scale, w, out));
+                                          h, scale, w, out, gate));
 }
 
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
-                    double* out) {
+                    double* out, const int32_t* nvec_dev, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_COMBINE, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_combine<double>, dim3(nblocks((int64_t)n * Grp<double>::T)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
-                                        y, scale, out));
+                                        y, scale, out, nvec_dev, gate));
 }
 
 void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, const double* y, const double* scale,
-                        double* out) {
+                        double* out, const int32_t* nvec_dev, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_COMBINE, (double)n * (nvec * VB / 2 + VB), hipLaunchKernelGGL(k_combine<float>, dim3(nblocks((int64_t)n * Grp<float>::T)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
-                                        y, scale, out));
+                                        y, scale, out, nvec_dev, gate));
 }
 
-void launch_acc(gks_mesh* m, double* X, const double* z) {
+void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate) {
     const int64_t len = (int64_t)m->d.n * CB;
-    PROFB(KC_AXPY, (double)len * 24.0, hipLaunchKernelGGL(k_acc, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, X, z));
+    PROFB(KC_AXPY, (double)len * 24.0, hipLaunchKernelGGL(k_acc, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, X, z, gate));
 }
 
-void launch_ctl(gks_mesh* m, int mode) {
-    PROF(KC_MISC, hipLaunchKernelGGL(k_gmres_ctl, dim3(1), dim3(64), 0, m->stream, mode, m->w.ks));
+void launch_ctl(gks_mesh* m, int mode, bool gated) {
+    PROF(KC_MISC, hipLaunchKernelGGL(k_gmres_ctl, dim3(1), dim3(64), 0, m->stream, mode, m->w.ks, m->prm.restart,
+                                     gated ? 1 : 0));
 }
 
 void launch_mask_cols(gks_mesh* m, double* X) {

@@ -47,6 +47,8 @@ class Request:
     solve_ms: list = field(default_factory=list)
     W: np.ndarray | None = None
     error: str | None = None
+    graph_steps: int = 0         # steps replayed through captured graphs
+    capture_failures: int = 0    # captures that fell back to eager launches
 
     @property
     def nt(self) -> int:
@@ -184,6 +186,8 @@ def gpu_runner(req: Request, stream):
                 req.step_ms.append(info["call_ms"])
                 req.solve_ms.append(info["solve_ms"])
             req.W = W.cpu().numpy()
+            st = gm.stats()
+            req.graph_steps, req.capture_failures = st["graph_steps"], st["capture_failures"]
         finally:
             gm.close()
 
@@ -209,6 +213,7 @@ def summarize(reqs, makespan: float, server: Server | None = None) -> dict:
         "solve_ms_p50": _pct(solves, 50), "solve_ms_p99": _pct(solves, 99),
         "request_ms_p50": _pct(e2e, 50), "request_ms_p99": _pct(e2e, 99),
         "queue_wait_ms_p50": _pct(wait, 50), "queue_wait_ms_p99": _pct(wait, 99),
+        "graph_steps": sum(r.graph_steps for r in ok), "capture_failures": sum(r.capture_failures for r in reqs),
     }
     if server is not None:
         out.update({"slots": server.slots, "hbm_budget": server.budget, "peak_admitted_bytes": server.peak_bytes,

@@ -31,6 +31,9 @@ def test_alone_equals_mix():
     stats = Server(slots=6, hbm_budget=1 << 36).run(mix, realtime=True)
     assert stats["completed"] == len(mix)
     assert stats["peak_concurrent"] >= 2
+    # every step of the concurrent mix replayed its captured graphs
+    assert stats["capture_failures"] == 0
+    assert stats["graph_steps"] == sum(r.steps for r in mix)
     for a, b in zip(alone, mix):
         assert a.error is None and b.error is None, (a.error, b.error)
         assert np.array_equal(a.W, b.W), a.rid
