@@ -94,11 +94,11 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
             "sample": "%s, %d steps in %.1f s" % (sample, steps, el)}
 
 
-def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool):
+def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, graphs: int = 1):
     import torch
     import paper_1802_00704_amd as g
     t0 = time.perf_counter()
-    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1)
+    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1, graphs=graphs)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     W = torch.tensor(W0, dtype=torch.float64, device="cuda")
@@ -204,6 +204,9 @@ def main():
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
+                    help="1: steps replay captured HIP graphs; 0: eager launches (counter runs use 0 so that "
+                         "every traced launch does work)")
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="requests of the serving stream to run after the throughput legs (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
@@ -219,7 +222,7 @@ def main():
     res = {}
     for f in forms:
         prec = g.GKS_MIXED if f == "mixed" else g.GKS_FP64
-        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile)
+        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile, args.graphs)
         print("# %s: %.4g cell-steps/s, %.3f ms/step, %.1f Krylov iterations/step" %
               (f, res[f]["value"], res[f]["ms_per_step"], res[f]["krylov_iters_per_step"]), file=sys.stderr,
               flush=True)

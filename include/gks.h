@@ -199,6 +199,17 @@ int gks_profile_enable(gks_mesh* m, int enable);
 int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms,
                     double* total_bytes);
 
+/* Apply the solve's preconditioner to four columns: Z = P(V), where P is
+ * the BILU(0) factorisation of section 3.2 (form GKS_FP64: one forward and
+ * one backward block substitution in FP64), or the inner iteration of the
+ * mixed form (form GKS_MIXED, handle created with precision GKS_MIXED:
+ * inner_iters Richardson sweeps z += M^-1 (v - K z) from z = 0 with the FP32
+ * matrix and factors).  V and Z are device arrays [4][5][nt] in the caller's
+ * cell order (the layout of X), not aliased.  Uses the handle's work space;
+ * for inspection and tests of the factor storage.
+ * Errors: GKS_EINVAL, GKS_EHIP. */
+int gks_apply_precond(gks_mesh* m, const double* V, double* Z, int form);
+
 /* Host-only view of the per-mesh state that gks_mesh_create builds (no
  * device is touched), for inspection and tests: faces, cell measures, the
  * renumbering, the normal-equation matrix of Eq. spdConserved:5 and its

@@ -19,7 +19,7 @@ GKS_FP64, GKS_MIXED = 0, 1
 GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM = 0, 1
 
 EXPORTS = ("gks_params_default", "gks_mesh_create", "gks_cls_reconstruct", "gks_flux", "gks_step",
-           "gks_faces", "gks_mesh_get_stats", "gks_profile_enable", "gks_profile_get",
+           "gks_faces", "gks_mesh_get_stats", "gks_profile_enable", "gks_profile_get", "gks_apply_precond",
            "gks_host_inspect", "gks_host_free", "gks_last_error", "gks_destroy")
 
 
@@ -100,6 +100,8 @@ def lib():
         L.gks_step.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
         L.gks_step.restype = C.c_int
         L.gks_faces.argtypes = [vp, vp, vp]
+        L.gks_apply_precond.argtypes = [vp, vp, vp, C.c_int]
+        L.gks_apply_precond.restype = C.c_int
         L.gks_faces.restype = C.c_int
         L.gks_mesh_get_stats.argtypes = [vp, C.POINTER(Stats)]
         L.gks_mesh_get_stats.restype = C.c_int
@@ -263,6 +265,16 @@ class GksMesh:
         code = lib().gks_step(self._h, _dev(W, (4, self.nt), "W"), float(dt), C.byref(used), C.byref(info))
         _check(code, self._h)
         return used.value, info.as_dict()
+
+    def apply_precond(self, V, form: int = 0, Z=None):
+        """Z = P(V) with the solver's preconditioner (gks_apply_precond)."""
+        import torch
+        if Z is None:
+            Z = torch.empty((4, 5, self.nt), dtype=torch.float64, device=V.device)
+        code = lib().gks_apply_precond(self._h, _dev(V, (4, 5, self.nt), "V"), _dev(Z, (4, 5, self.nt), "Z"),
+                                       int(form))
+        _check(code, self._h)
+        return Z
 
     def profile(self, enable: bool):
         _check(lib().gks_profile_enable(self._h, int(enable)), self._h)

@@ -512,6 +512,75 @@ std::vector<T> pack_blocks(const std::vector<double>& src, int slots, int n, int
     return dst;
 }
 
+// Slice tables of a factor stored as ELL [slots][n] with its real entries in
+// the leading slots (padding = column n): slices of 64 rows inside each level,
+// each as wide as its widest row.
+struct SliceLayout {
+    std::vector<int32_t> sbase;        // [levels + 1] first slice of each level
+    std::vector<int32_t> off, w;       // [slices] first chunk, slots
+    std::vector<double> lev_blocks;    // [levels] stored blocks (chunks * 64, rows that exist)
+    int32_t chunks = 0;
+};
+
+SliceLayout slice_layout(const std::vector<int32_t>& col, int slots, int n, const std::vector<int32_t>& lev_ptr) {
+    SliceLayout L;
+    const int nl = (int)lev_ptr.size() - 1;
+    L.sbase.assign(nl + 1, 0);
+    L.lev_blocks.assign(nl, 0.0);
+    for (int l = 0; l < nl; ++l) {
+        L.sbase[l] = (int32_t)L.w.size();
+        const int r1 = lev_ptr[l + 1];
+        for (int r = lev_ptr[l]; r < r1; r += 64) {
+            int w = 0;
+            for (int i = r; i < std::min(r + 64, r1); ++i) {
+                int c = 0;
+                while (c < slots && col[(size_t)c * n + i] != n) ++c;
+                w = std::max(w, c);
+            }
+            L.off.push_back(L.chunks);
+            L.w.push_back(w);
+            L.chunks += w;
+            L.lev_blocks[l] += (double)w * (std::min(r + 64, r1) - r);
+        }
+    }
+    L.sbase[nl] = (int32_t)L.w.size();
+    return L;
+}
+
+// Blocks of an ELL factor in the sliced layout (element type T) and, when
+// col_out is given, the column indices per chunk.
+template <typename T>
+std::vector<T> pack_sliced(const std::vector<double>& val, const std::vector<int32_t>& col, int n,
+                           const std::vector<int32_t>& lev_ptr, const SliceLayout& L, std::vector<int32_t>* col_out) {
+    constexpr int V = 16 / sizeof(T);
+    const size_t nch = std::max<int32_t>(1, L.chunks);
+    std::vector<T> dst(nch * 25 * 64, T(0));
+    if (col_out) col_out->assign(nch * 64, n);
+    const int nl = (int)lev_ptr.size() - 1;
+    for (int l = 0; l < nl; ++l) {
+        const int r0 = lev_ptr[l], r1 = lev_ptr[l + 1];
+        const int ns = L.sbase[l + 1] - L.sbase[l];
+#pragma omp parallel for schedule(static)
+        for (int k = 0; k < ns; ++k) {
+            const int sl = L.sbase[l] + k;
+            for (int s = 0; s < L.w[sl]; ++s) {
+                const size_t ch = (size_t)L.off[sl] + s;
+                for (int ln = 0; ln < 64; ++ln) {
+                    const int i = r0 + 64 * k + ln;
+                    if (i >= r1) break;
+                    if (col_out) (*col_out)[ch * 64 + ln] = col[(size_t)s * n + i];
+                    for (int e = 0; e < 25; ++e) {
+                        const size_t at = e < 24 ? ch * 25 * 64 + ((size_t)(e / V) * 64 + ln) * V + e % V
+                                                 : ch * 25 * 64 + 24 * 64 + ln;
+                        dst[at] = (T)val[((size_t)s * 25 + e) * n + i];
+                    }
+                }
+            }
+        }
+    }
+    return dst;
+}
+
 void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S) {
     PhaseTimer pt;
     HostMesh& hm = S.hm;
@@ -563,9 +632,21 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         key = col;
         S.n_colors = nkeys;
     }
+    // Rows of one level are independent; inside a level they are sorted by
+    // their number of neighbours in earlier levels (most first), RCM order
+    // breaking ties, so that 64-row slices of the factors have uniform
+    // widths (see the sliced factor storage of the sweep kernels).
+    std::vector<int> nlow(nt, 0);
+    for (int i = 0; i < nt; ++i)
+        for (int s = 0; s < 3; ++s) {
+            const int j = hm.nb[i][s];
+            if (j >= 0 && key[j] < key[i]) ++nlow[i];
+        }
     std::vector<int>& perm = S.perm;
     perm = rcm;  // new -> old
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
+        return key[a] != key[b] ? key[a] < key[b] : nlow[a] > nlow[b];
+    });
     std::vector<int> iperm(nt);
     for (int p = 0; p < nt; ++p) iperm[perm[p]] = p;
     S.lev_ptr.assign(nkeys + 1, 0);
@@ -782,15 +863,35 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     const int np = d.np;
     d.Kval = dev_upload(m, pack_blocks<double>(S.Kval, KW, n, np));
     d.Kcol = dev_upload(m, S.Kcol);
-    d.Lval = dev_upload(m, pack_blocks<double>(S.Lval, LW, n, np));
-    d.Lcol = dev_upload(m, S.Lcol);
-    d.Uval = dev_upload(m, pack_blocks<double>(S.Uval, LW, n, np));
-    d.Ucol = dev_upload(m, S.Ucol);
+    {
+        const SliceLayout Ls = slice_layout(S.Lcol, LW, n, S.lev_ptr);
+        const SliceLayout Us = slice_layout(S.Ucol, LW, n, S.lev_ptr);
+        std::vector<int32_t> lcol, ucol;
+        d.Lval = dev_upload(m, pack_sliced<double>(S.Lval, S.Lcol, n, S.lev_ptr, Ls, &lcol));
+        d.Uval = dev_upload(m, pack_sliced<double>(S.Uval, S.Ucol, n, S.lev_ptr, Us, &ucol));
+        d.Li.col = dev_upload(m, lcol);
+        d.Li.off = dev_upload(m, Ls.off);
+        d.Li.w = dev_upload(m, Ls.w);
+        d.Ui.col = dev_upload(m, ucol);
+        d.Ui.off = dev_upload(m, Us.off);
+        d.Ui.w = dev_upload(m, Us.w);
+        d.Lsbase = Ls.sbase;
+        d.Usbase = Us.sbase;
+        d.lev_Lb = Ls.lev_blocks;
+        d.lev_Ub = Us.lev_blocks;
+        const int nl = (int)S.lev_ptr.size() - 1;
+        d.lev_Kb.assign(nl, 0.0);
+        for (int l = 0; l < nl; ++l)
+            for (int i = S.lev_ptr[l]; i < S.lev_ptr[l + 1]; ++i)
+                for (int s2 = 0; s2 < KW; ++s2) d.lev_Kb[l] += S.Kcol[(size_t)s2 * n + i] != n ? 1.0 : 0.0;
+        if (prm.precision == GKS_MIXED) {
+            d.Lval32 = dev_upload(m, pack_sliced<float>(S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr));
+            d.Uval32 = dev_upload(m, pack_sliced<float>(S.Uval, S.Ucol, n, S.lev_ptr, Us, nullptr));
+        }
+    }
     d.Dinv = dev_upload(m, pack_blocks<double>(S.Dv, 1, n, np));
     if (prm.precision == GKS_MIXED) {
         d.Kval32 = dev_upload(m, pack_blocks<float>(S.Kval, KW, n, np));
-        d.Lval32 = dev_upload(m, pack_blocks<float>(S.Lval, LW, n, np));
-        d.Uval32 = dev_upload(m, pack_blocks<float>(S.Uval, LW, n, np));
         d.Dinv32 = dev_upload(m, pack_blocks<float>(S.Dv, 1, n, np));
     }
 
@@ -805,6 +906,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
         w.Z = dev_alloc<float>(m, vec * mres);
         w.yf = dev_alloc<float>(m, vec);
         w.df = dev_alloc<float>(m, vec);
+        w.bf = dev_alloc<float>(m, vec);
     }
     w.w = dev_alloc<double>(m, vec);
     w.t1 = dev_alloc<double>(m, vec);
@@ -1206,6 +1308,36 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
         }
         if (st != GKS_OK) m->err = "GMRES did not converge within max_iter";
         return st;
+    } catch (const Fail& f) {
+        return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
+    }
+}
+
+int gks_apply_precond(gks_mesh* m, const double* V, double* Z, int form) {
+    if (!m) return GKS_EINVAL;
+    if (!V || !Z || (const void*)V == (const void*)Z) {
+        m->err = "null or aliased V / Z";
+        return GKS_EINVAL;
+    }
+    if (form != GKS_FP64 && !(form == GKS_MIXED && m->prm.precision == GKS_MIXED)) {
+        m->err = "form must be GKS_FP64, or GKS_MIXED on a handle created with precision GKS_MIXED";
+        return GKS_EINVAL;
+    }
+    try {
+        Work& w = m->w;
+        launch_copyin(m, V, w.t1);
+        if (form == GKS_FP64) {
+            launch_ilu(m, w.t1, nullptr, w.t2, w.t3);
+            launch_copyout(m, w.t3, Z);
+        } else {
+            for (int j = 0; j < m->prm.inner_iters; ++j) launch_mx_sweep(m, j == 0, w.t1, w.ones, w.yf, w.df, w.Z);
+            launch_copyout_f32(m, w.Z, Z);
+        }
+        HIPCHK(hipStreamSynchronize(m->stream));
+        prof_collect(m);
+        return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
     } catch (const LaunchError& e) {

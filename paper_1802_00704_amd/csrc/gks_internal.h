@@ -75,6 +75,15 @@ struct KrylovState {
     double sq[NC];                // squared norms handed to the control kernel
 };
 
+// Sliced storage of the BILU(0) factors (see the sweep kernels): per slice
+// of 64 rows its first chunk and its number of slots; per chunk (one slot of
+// one slice) 64 column indices.
+struct SlicedIdx {
+    const int32_t* col = nullptr;  // [chunk][64]
+    const int32_t* off = nullptr;  // [slice] first chunk
+    const int32_t* w = nullptr;    // [slice] slots
+};
+
 struct DevMesh {
     int nt = 0, nf = 0, nfb = 0;
     // faces (face order)
@@ -99,15 +108,16 @@ struct DevMesh {
     double* Kval = nullptr;       // [KW][25][n]
     int32_t* Kcol = nullptr;      // [KW][n] (n = dummy)
     float* Kval32 = nullptr;
-    double* Lval = nullptr;       // [LW][25][n] strict lower factor blocks
-    int32_t* Lcol = nullptr;
-    double* Uval = nullptr;       // [LW][25][n] strict upper factor blocks
-    int32_t* Ucol = nullptr;
-    double* Dinv = nullptr;       // [25][n] inverted pivot blocks
+    double* Lval = nullptr;       // sliced [chunk][25 * 64] strict lower factor blocks
+    double* Uval = nullptr;       // sliced [chunk][25 * 64] strict upper factor blocks
+    SlicedIdx Li{}, Ui{};         // their column indices and slice tables
+    double* Dinv = nullptr;       // [25][np] inverted pivot blocks
     float* Lval32 = nullptr;
     float* Uval32 = nullptr;
     float* Dinv32 = nullptr;
     std::vector<int32_t> lev_ptr; // host: rows of level l are [lev_ptr[l], lev_ptr[l+1])
+    std::vector<int32_t> Lsbase, Usbase;  // host: first slice of each level
+    std::vector<double> lev_Kb, lev_Lb, lev_Ub;  // host: stored K, L, U blocks per level
 };
 
 struct Work {
@@ -117,6 +127,7 @@ struct Work {
     float* Z = nullptr;           // [m][n+1][CB] flexible GMRES: preconditioned basis (FP32)
     float* yf = nullptr;          // [n+1][CB] mixed inner sweeps: forward result
     float* df = nullptr;          // [n+1][CB] mixed inner sweeps: correction
+    float* bf = nullptr;          // [n+1][CB] mixed inner sweeps: FP32 right-hand side
     double* w = nullptr;          // [n+1][CB]
     double* t1 = nullptr;         // [n+1][CB]
     double* t2 = nullptr;         // [n+1][CB]
@@ -207,6 +218,8 @@ void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate = n
 void launch_ctl(gks_mesh* m, int mode, bool gated = false);
 void launch_mask_cols(gks_mesh* m, double* X);
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell);
+void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell);
+void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);
 void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out);

@@ -160,16 +160,68 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict
 }
 
 // ------------------------------------------------------------------ BILU(0) sweeps
+// Factor storage ("sliced"): the rows of one dependency level are cut into
+// slices of 64 consecutive rows, one wavefront each.  Slice k holds w[k]
+// slots; slot s of the slice is a chunk of 64 blocks in the vector-packed
+// layout with row stride 64, plus 64 column indices.  The host sorts the
+// rows of a level by their number of lower (upper) neighbours, so a slice's
+// width is nearly every row's exact count and padding is rare; padded slots
+// point at the zero dummy row with zero blocks.  A wave reads its slice's
+// width and first chunk once (scalar), so the slot loop is uniform.
+struct SliceRef {
+    int64_t ch0;   // first chunk of the slice
+    int w;         // slots in the slice
+    int lane;      // row within the slice
+};
+
+__device__ __forceinline__ SliceRef slice_ref(const SlicedIdx& S, int sbase, int rl) {
+    const int sl = sbase + (rl >> 6);
+    SliceRef r;
+    r.ch0 = __builtin_amdgcn_readfirstlane(S.off[sl]);
+    r.w = __builtin_amdgcn_readfirstlane(S.w[sl]);
+    r.lane = rl & 63;
+    return r;
+}
+
+// acc_c -= B x_c for the four columns, B a 5 x 5 block
+template <typename T, typename XT, typename ACC>
+__device__ __forceinline__ void block_sub(ACC (&acc)[CB], const T (&blk)[25], const XT (&x)[CB]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)x[c * NB + q];
+}
+
+// acc -= sum over the slice's slots of F_is x_{col(s)}
+template <typename T, typename XT, typename ACC>
+__device__ __forceinline__ void slice_sub(ACC (&acc)[CB], const T* __restrict__ val, const int32_t* __restrict__ col,
+                                          const SliceRef& sr, const XT* __restrict__ x) {
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        if (s >= sr.w) break;
+        const int64_t ch = sr.ch0 + s;
+        const int j = col[ch * 64 + sr.lane];
+        const XT* xj = x + (int64_t)j * CB;
+        XT xv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) xv[q] = xj[q];
+        T blk[25];
+        load_block(val + ch * 25 * 64, 64, 0, sr.lane, blk);
+        block_sub(acc, blk, xv);
+    }
+}
+
 // forward  y_i = s .* v_i - sum_{k<i} L_ik y_k            (unit lower factor)
 // backward z_i = Dinv_i (y_i - sum_{j>i} U_ij z_j)
 // over the rows [r0, r1) of one dependency level.
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int np, int r0, int r1, const T* __restrict__ Lv,
-                                                 const int32_t* __restrict__ Lc, const double* __restrict__ v,
-                                                 const double* __restrict__ vscale, double* __restrict__ y,
-    const int32_t* __restrict__ gate) {
+__global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, SlicedIdx Li, const double* __restrict__ Lv,
+                                                 const double* __restrict__ v, const double* __restrict__ vscale,
+                                                 double* __restrict__ y, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    const int i = r0 + xcd_row();
+    const int rl = xcd_row();
+    const int i = r0 + rl;
     if (i >= r1) return;
     double acc[CB];
     const double* vi = v + (int64_t)i * CB;
@@ -179,97 +231,77 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int n, int np, int r0, int r1, 
 #pragma unroll
         for (int r = 0; r < NB; ++r) acc[c * NB + r] = sc * vi[c * NB + r];
     }
-#pragma unroll
-    for (int s = 0; s < LW; ++s) {
-        const int k = Lc[(int64_t)s * n + i];
-        const double* yk = y + (int64_t)k * CB;
-        double yv[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) yv[q] = yk[q];
-        T blk[25];
-        load_block(Lv, np, s, i, blk);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (double)blk[r * NB + q] * yv[c * NB + q];
-    }
+    slice_sub(acc, Lv, Li.col, slice_ref(Li, sbase, rl), y);
     double* yi = y + (int64_t)i * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) yi[q] = acc[q];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_ilu_bwd(int n, int np, int r0, int r1, const T* __restrict__ Uv,
-                                                 const int32_t* __restrict__ Uc, const T* __restrict__ Dinv,
+__global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
+                                                 const double* __restrict__ Uv, const double* __restrict__ Dinv,
                                                  const double* __restrict__ y, double* __restrict__ z,
-    const int32_t* __restrict__ gate) {
+                                                 const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    const int i = r0 + xcd_row();
+    const int rl = xcd_row();
+    const int i = r0 + rl;
     if (i >= r1) return;
     double acc[CB];
     const double* yi = y + (int64_t)i * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) acc[q] = yi[q];
-#pragma unroll
-    for (int s = 0; s < LW; ++s) {
-        const int j = Uc[(int64_t)s * n + i];
-        const double* zj = z + (int64_t)j * CB;
-        double zv[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) zv[q] = zj[q];
-        T blk[25];
-        load_block(Uv, np, s, i, blk);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (double)blk[r * NB + q] * zv[c * NB + q];
-    }
-    T d[25];
+    slice_sub(acc, Uv, Ui.col, slice_ref(Ui, sbase, rl), z);
+    double d[25];
     load_block(Dinv, np, 0, i, d);
     double* zi = z + (int64_t)i * CB;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
 #pragma unroll
         for (int r = 0; r < NB; ++r) {
-            double s = 0.0;
+            double t = 0.0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q) s += (double)d[r * NB + q] * acc[c * NB + q];
-            zi[c * NB + r] = s;
+            for (int q = 0; q < NB; ++q) t += d[r * NB + q] * acc[c * NB + q];
+            zi[c * NB + r] = t;
         }
 }
 
 // ------------------------------------------------------------------ mixed-precision inner sweeps
-// One BILU(0)-preconditioned Richardson sweep z <- z + M^-1 (s .* v - K z)
-// with the FP32 matrix and factors, FP32 vectors (20 floats per cell):
+// One BILU(0)-preconditioned Richardson sweep z <- z + M^-1 (b - K z) with
+// the FP32 matrix and factors and FP32 vectors (20 floats per cell), where
+// b = FP32(s .* v) is formed once, by the first sweep:
 //   forward  (rows of one level)  y_i = r_i - sum_{k<i} L_ik y_k,
-//            r_i = s .* v_i - sum_s K_is z_s   (FIRST: z = 0, r_i = s .* v_i)
+//            r_i = b_i - sum_s K_is z_s      (FIRST: z = 0, r_i = b_i)
 //   backward (rows of one level)  d_i = Dinv_i (y_i - sum_{j>i} U_ij d_j),
 //            z_i += d_i                        (FIRST: z_i = d_i, d is z)
 // z is not modified during the forward levels, so the residual needs no
-// separate pass.
+// separate pass.  Sums are accumulated in ACC.
 template <bool FIRST, typename ACC>
-__global__ void __launch_bounds__(TPB) k_mx_fwd(int n, int np, int r0, int r1, const float* __restrict__ Kv,
-                                                const int32_t* __restrict__ Kc, const float* __restrict__ Lv,
-                                                const int32_t* __restrict__ Lc, const double* __restrict__ v,
-                                                const double* __restrict__ vscale, const float* __restrict__ z,
-                                                float* __restrict__ y,
-    const int32_t* __restrict__ gate) {
+__global__ void __launch_bounds__(TPB) k_mx_fwd(int n, int np, int r0, int r1, int sbase, const float* __restrict__ Kv,
+                                                const int32_t* __restrict__ Kc, SlicedIdx Li,
+                                                const float* __restrict__ Lv, const double* __restrict__ v,
+                                                const double* __restrict__ vscale, float* __restrict__ b,
+                                                const float* __restrict__ z, float* __restrict__ y,
+                                                const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    const int i = r0 + xcd_row();
+    const int rl = xcd_row();
+    const int i = r0 + rl;
     if (i >= r1) return;
     ACC acc[CB];
-    const double* vi = v + (int64_t)i * CB;
+    float* bi = b + (int64_t)i * CB;
+    if (FIRST) {
+        const double* vi = v + (int64_t)i * CB;
 #pragma unroll
-    for (int c = 0; c < NC; ++c) {
-        const ACC sc = (ACC)vscale[c];
+        for (int c = 0; c < NC; ++c) {
+            const double sc = vscale[c];
 #pragma unroll
-        for (int r = 0; r < NB; ++r) acc[c * NB + r] = sc * (ACC)vi[c * NB + r];
-    }
-    if (!FIRST) {
+            for (int r = 0; r < NB; ++r) {
+                const float t = (float)(sc * vi[c * NB + r]);
+                bi[c * NB + r] = t;
+                acc[c * NB + r] = (ACC)t;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < CB; ++q) acc[q] = (ACC)bi[q];
 #pragma unroll
         for (int s = 0; s < KW; ++s) {
             const int j = Kc[(int64_t)s * n + i];
@@ -279,65 +311,30 @@ __global__ void __launch_bounds__(TPB) k_mx_fwd(int n, int np, int r0, int r1, c
             for (int q = 0; q < CB; ++q) zv[q] = zj[q];
             float blk[25];
             load_block(Kv, np, s, i, blk);
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int r = 0; r < NB; ++r)
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)zv[c * NB + q];
+            block_sub(acc, blk, zv);
         }
     }
-#pragma unroll
-    for (int s = 0; s < LW; ++s) {
-        const int k = Lc[(int64_t)s * n + i];
-        const float* yk = y + (int64_t)k * CB;
-        float yv[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) yv[q] = yk[q];
-        float blk[25];
-        load_block(Lv, np, s, i, blk);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)yv[c * NB + q];
-    }
+    slice_sub(acc, Lv, Li.col, slice_ref(Li, sbase, rl), y);
     float* yi = y + (int64_t)i * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) yi[q] = (float)acc[q];
 }
 
 template <bool FIRST, typename ACC>
-__global__ void __launch_bounds__(TPB) k_mx_bwd(int n, int np, int r0, int r1, const float* __restrict__ Uv,
-                                                const int32_t* __restrict__ Uc, const float* __restrict__ Dinv,
+__global__ void __launch_bounds__(TPB) k_mx_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
+                                                const float* __restrict__ Uv, const float* __restrict__ Dinv,
                                                 const float* __restrict__ y, float* __restrict__ d,
-                                                float* __restrict__ z,
-    const int32_t* __restrict__ gate) {
+                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    const int i = r0 + xcd_row();
+    const int rl = xcd_row();
+    const int i = r0 + rl;
     if (i >= r1) return;
     float* dd = FIRST ? z : d;
     ACC acc[CB];
     const float* yi = y + (int64_t)i * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) acc[q] = (ACC)yi[q];
-#pragma unroll
-    for (int s = 0; s < LW; ++s) {
-        const int j = Uc[(int64_t)s * n + i];
-        const float* dj = dd + (int64_t)j * CB;
-        float dv[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) dv[q] = dj[q];
-        float blk[25];
-        load_block(Uv, np, s, i, blk);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int q = 0; q < NB; ++q) acc[c * NB + r] -= (ACC)blk[r * NB + q] * (ACC)dv[c * NB + q];
-    }
+    slice_sub(acc, Uv, Ui.col, slice_ref(Ui, sbase, rl), dd);
     float dg[25];
     load_block(Dinv, np, 0, i, dg);
     float di[CB];
@@ -600,13 +597,24 @@ __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restr
 // ------------------------------------------------------------------ layout conversion
 // X in the caller's layout [4][5][nt] from the solver vector: one thread per
 // cell in the caller's order (coalesced writes, one 160-byte read).
+template <typename T>
 __global__ void __launch_bounds__(TPB) k_copyout(int nt, const int32_t* __restrict__ iperm,
-                                                 const double* __restrict__ Xs, double* __restrict__ Xc) {
+                                                 const T* __restrict__ Xs, double* __restrict__ Xc) {
     const int oi = xcd_row();
     if (oi >= nt) return;
-    const double* xi = Xs + (int64_t)iperm[oi] * CB;
+    const T* xi = Xs + (int64_t)iperm[oi] * CB;
 #pragma unroll
-    for (int q = 0; q < CB; ++q) Xc[(int64_t)q * nt + oi] = xi[q];
+    for (int q = 0; q < CB; ++q) Xc[(int64_t)q * nt + oi] = (double)xi[q];
+}
+
+// solver vector from the caller's layout [4][5][nt] (inverse of k_copyout)
+__global__ void __launch_bounds__(TPB) k_copyin(int nt, const int32_t* __restrict__ iperm,
+                                                const double* __restrict__ Xc, double* __restrict__ Xs) {
+    const int oi = xcd_row();
+    if (oi >= nt) return;
+    double* xi = Xs + (int64_t)iperm[oi] * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) xi[q] = Xc[(int64_t)q * nt + oi];
 }
 
 __global__ void k_set(double* p, double v) { *p = v; }
@@ -916,8 +924,6 @@ void prof_end(gks_mesh* m, int kc) {
 // input vector block read once, each output block written once.
 constexpr double VB = CB * 8.0;
 inline double spmv_bytes(int n, int esz, bool resid) { return n * (KW * 25.0 * esz + KW * 4.0 + (resid ? 3 : 2) * VB); }
-inline double ilu_fwd_bytes(int rows, int esz) { return rows * (LW * 25.0 * esz + LW * 4.0 + 3 * VB); }
-inline double ilu_bwd_bytes(int rows, int esz) { return rows * (LW * 25.0 * esz + LW * 4.0 + 25.0 * esz + 3 * VB); }
 
 static inline void check_launch(int kc) {
     const hipError_t e = hipGetLastError();
@@ -960,71 +966,66 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
 }
 
 // One inner sweep of the mixed form over all levels (see k_mx_fwd/k_mx_bwd).
-
-template <typename ACC>
-static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
-                     const int32_t* gate);
-
+// Bytes: stored blocks (100 B FP32, 4 B index) of each level, plus per row
+// its own vectors (b in, y out; K z reads z once; backward y in, Dinv,
+// d out and z read-modify-write).
 void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
                      const int32_t* gate) {
-    mx_sweep<double>(m, first, v, vscale, y, d, z, gate);
-}
-
-template <typename ACC>
-static void mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
-                     const int32_t* gate) {
-    const int n = m->d.n;
-    const auto& lp = m->d.lev_ptr;
+    using ACC = double;
+    const DevMesh& D = m->d;
+    float* b = m->w.bf;
+    const auto& lp = D.lev_ptr;
     const int nl = (int)lp.size() - 1;
     const double VF = VB / 2;
     for (int l = 0; l < nl; ++l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         const int rows = r1 - r0;
+        const double lb = D.lev_Lb[l] * 104.0;
         if (first)
-            PROFB(KC_ILU_FWD32, rows * (LW * 100.0 + LW * 4.0 + VB + 2 * VF), hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y, gate));
+            PROFB(KC_ILU_FWD32, lb + rows * (VB + 2 * VF),
+                  hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np, r0,
+                                     r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
         else
-            PROFB(KC_ILU_FWD32, rows * ((KW + LW) * 100.0 + (KW + LW) * 4.0 + VB + 3 * VF), hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Kval32, m->d.Kcol, m->d.Lval32, m->d.Lcol, v, vscale, z, y, gate));
+            PROFB(KC_ILU_FWD32, lb + D.lev_Kb[l] * 104.0 + rows * 3 * VF,
+                  hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np, r0,
+                                     r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         const int rows = r1 - r0;
+        const double ub = D.lev_Ub[l] * 104.0;
         if (first)
-            PROFB(KC_ILU_BWD32, rows * (LW * 100.0 + 100.0 + LW * 4.0 + 3 * VF), hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z, gate));
+            PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 2 * VF),
+                  hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0, r1,
+                                     D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
         else
-            PROFB(KC_ILU_BWD32, rows * (LW * 100.0 + 100.0 + LW * 4.0 + 5 * VF), hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, n, m->d.np, r0, r1,
-                  m->d.Uval32, m->d.Ucol, m->d.Dinv32, y, d, z, gate));
+            PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 4 * VF),
+                  hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0, r1,
+                                     D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
     }
 }
 
+// FP64 BILU(0) solve out = M^-1 (s .* in), level by level.  Bytes: stored
+// blocks (200 B, 4 B index) plus per row in/out vectors (and Dinv).
 void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out, const int32_t* gate) {
-    const bool fp32 = false;
-    const int n = m->d.n;
-    const auto& lp = m->d.lev_ptr;
+    const DevMesh& D = m->d;
+    const auto& lp = D.lev_ptr;
     const int nl = (int)lp.size() - 1;
     for (int l = 0; l < nl; ++l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
-        if (fp32)
-            PROFB(KC_ILU_FWD32, ilu_fwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_fwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                  n, m->d.np, r0, r1, m->d.Lval32, m->d.Lcol, in, in_scale, tmp, gate));
-        else
-            PROFB(KC_ILU_FWD, ilu_fwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_fwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                n, m->d.np, r0, r1, m->d.Lval, m->d.Lcol, in, in_scale, tmp, gate));
+        PROFB(KC_ILU_FWD, D.lev_Lb[l] * 204.0 + (r1 - r0) * 2.0 * VB,
+              hipLaunchKernelGGL(k_ilu_fwd, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream, r0, r1, D.Lsbase[l], D.Li,
+                                 D.Lval, in, in_scale, tmp, gate));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
-        if (fp32)
-            PROFB(KC_ILU_BWD32, ilu_bwd_bytes(r1 - r0, 4), hipLaunchKernelGGL(k_ilu_bwd<float>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                  n, m->d.np, r0, r1, m->d.Uval32, m->d.Ucol, m->d.Dinv32, tmp, out, gate));
-        else
-            PROFB(KC_ILU_BWD, ilu_bwd_bytes(r1 - r0, 8), hipLaunchKernelGGL(k_ilu_bwd<double>, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream,
-                                                n, m->d.np, r0, r1, m->d.Uval, m->d.Ucol, m->d.Dinv, tmp, out, gate));
+        PROFB(KC_ILU_BWD, D.lev_Ub[l] * 204.0 + (r1 - r0) * (200.0 + 2.0 * VB),
+              hipLaunchKernelGGL(k_ilu_bwd, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream, D.np, r0, r1, D.Usbase[l],
+                                 D.Ui, D.Uval, D.Dinv, tmp, out, gate));
     }
 }
 
@@ -1080,8 +1081,18 @@ void launch_mask_cols(gks_mesh* m, double* X) {
 
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell) {
     const int nt = m->d.nt;
-    PROFB(KC_COPYOUT, (double)nt * (4.0 + 2 * VB), hipLaunchKernelGGL(k_copyout, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt,
+    PROFB(KC_COPYOUT, (double)nt * (4.0 + 2 * VB), hipLaunchKernelGGL(k_copyout<double>, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt,
                                         m->d.iperm, Xs, Xcell));
+}
+
+void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell) {
+    const int nt = m->d.nt;
+    PROF(KC_COPYOUT, hipLaunchKernelGGL(k_copyout<float>, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.iperm, Xs, Xcell));
+}
+
+void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs) {
+    const int nt = m->d.nt;
+    PROF(KC_MISC, hipLaunchKernelGGL(k_copyin, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.iperm, Xcell, Xs));
 }
 
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F) {
