@@ -908,6 +908,8 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
         w.df = dev_alloc<float>(m, vec);
         w.bf = dev_alloc<float>(m, vec);
     }
+    w.Xp = dev_alloc<float>(m, vec);
+    w.Xpp = dev_alloc<float>(m, vec);
     w.w = dev_alloc<double>(m, vec);
     w.t1 = dev_alloc<double>(m, vec);
     w.t2 = dev_alloc<double>(m, vec);
@@ -1299,6 +1301,7 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
     }
     try {
         const int st = run_solve(m, W, info);
+        m->hist = st == GKS_OK ? 1 : 0;   // X is a solution, but not of the step sequence
         launch_copyout(m, m->w.X, X);
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
@@ -1378,8 +1381,12 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         m->err = "null W";
         return GKS_EINVAL;
     }
+    const int hist = m->hist;
+    m->hist = 0;   // until this step has succeeded
     try {
         Work& w = m->w;
+        // initial guess of the solve: extrapolation of the last solutions
+        const int order = std::max(0, std::min(hist, 3) - 1);
         bool graphs = m->prm.graphs && !m->prof.on && m->capture_failures < 3;
         if (graphs) {
             try {
@@ -1395,6 +1402,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
             // graph path: the step works on the handle's copy of W
             ++m->graph_steps;
             launch_copy(m, w.Wint, W, (int64_t)4 * m->d.nt);
+            launch_extrap(m, order);
             if (dt > 0.0)
                 launch_set_scalar(m, w.dt_dev, dt);
             else
@@ -1414,6 +1422,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
             else
                 launch_cfl(m, W, w.dt_dev);
             launch_zero_i32(m, w.counters, 4);
+            launch_extrap(m, order);
             const int st = run_solve(m, W, info);
             if (st != GKS_OK) {
                 HIPCHK(hipStreamSynchronize(m->stream));
@@ -1440,6 +1449,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
         if (info) info->call_ms = ms_since(t_call);
+        m->hist = std::min(hist, 3) + 1;
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);

@@ -128,6 +128,8 @@ struct Work {
     float* yf = nullptr;          // [n+1][CB] mixed inner sweeps: forward result
     float* df = nullptr;          // [n+1][CB] mixed inner sweeps: correction
     float* bf = nullptr;          // [n+1][CB] mixed inner sweeps: FP32 right-hand side
+    float* Xp = nullptr;          // [n][CB] solution of the step before the last (FP32)
+    float* Xpp = nullptr;         // [n][CB] the one before that (FP32)
     double* w = nullptr;          // [n+1][CB]
     double* t1 = nullptr;         // [n+1][CB]
     double* t2 = nullptr;         // [n+1][CB]
@@ -169,6 +171,7 @@ struct gks_mesh {
     hipGraphExec_t gA = nullptr, gB = nullptr;
     int gA_budget = 0;            // Arnoldi steps captured in gA
     int budget = 0;               // steps wanted in gA for the next step
+    int hist = 0;                 // solutions held in X, Xp, Xpp (extrapolated guess)
     int64_t graph_steps = 0;      // steps run through the graphs
     int capture_failures = 0;     // captures that failed (3 turn graphs off)
     std::string capture_err;      // the last capture failure
@@ -187,7 +190,7 @@ struct LaunchError {
 enum Kc {
     KC_RHS = 0, KC_SPMV, KC_SPMV_RES, KC_ILU_FWD, KC_ILU_BWD, KC_DOTS, KC_AXPY_DOTS, KC_AXPY_NORM,
     KC_FINAL, KC_COMBINE, KC_AXPY, KC_COPYOUT, KC_FLUX, KC_UPDATE, KC_CFL, KC_MISC,
-    KC_SPMV32, KC_ILU_FWD32, KC_ILU_BWD32, KC_COUNT
+    KC_SPMV32, KC_ILU_FWD32, KC_ILU_BWD32, KC_EXTRAP, KC_COUNT
 };
 extern const char* kc_names[NPROF];
 
@@ -220,6 +223,9 @@ void launch_mask_cols(gks_mesh* m, double* X);
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell);
 void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell);
 void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
+// initial guess of a step's solve from the last solutions (order 0, 1, 2)
+// and shift of the history
+void launch_extrap(gks_mesh* m, int order);
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);
 void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out);

@@ -19,7 +19,7 @@ namespace gks {
 const char* kc_names[NPROF] = {"rhs",       "spmv",       "spmv_resid", "ilu_fwd",  "ilu_bwd",
                                "dots",      "axpy_dots",  "axpy_norm",  "finalize", "combine",
                                "axpy",      "copyout",    "flux",       "update",   "cfl",
-                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "", "", "", "", ""};
+                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "", "", "", ""};
 
 constexpr int TPB = 256;          // threads per block of the streaming kernels
 constexpr int RED_CHUNK = 8;      // vectors per block of the dot kernel
@@ -607,6 +607,25 @@ __global__ void __launch_bounds__(TPB) k_copyout(int nt, const int32_t* __restri
     for (int q = 0; q < CB; ++q) Xc[(int64_t)q * nt + oi] = (double)xi[q];
 }
 
+// Initial guess for the next step's solve by polynomial extrapolation in
+// time of the last solutions (uniform steps): order 0 X, order 1 2X - Xp,
+// order 2 3X - 3Xp + Xpp; the history shifts (Xpp <- Xp, Xp <- X).  The
+// history is kept in FP32: it only shapes the starting point, which the
+// solve then corrects to its tolerance.
+__global__ void __launch_bounds__(TPB) k_extrap(int64_t len, int order, double* __restrict__ X,
+                                                float* __restrict__ Xp, float* __restrict__ Xpp) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= len) return;
+    const double x = X[e];
+    const float p = Xp[e];
+    double g = x;
+    if (order == 1) g = 2.0 * x - (double)p;
+    if (order >= 2) g = 3.0 * (x - (double)p) + (double)Xpp[e];
+    X[e] = g;
+    Xpp[e] = p;
+    Xp[e] = (float)x;
+}
+
 // solver vector from the caller's layout [4][5][nt] (inverse of k_copyout)
 __global__ void __launch_bounds__(TPB) k_copyin(int nt, const int32_t* __restrict__ iperm,
                                                 const double* __restrict__ Xc, double* __restrict__ Xs) {
@@ -1088,6 +1107,12 @@ void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell) {
 void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell) {
     const int nt = m->d.nt;
     PROF(KC_COPYOUT, hipLaunchKernelGGL(k_copyout<float>, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.iperm, Xs, Xcell));
+}
+
+void launch_extrap(gks_mesh* m, int order) {
+    const int64_t len = (int64_t)m->d.n * CB;
+    PROFB(KC_EXTRAP, (double)len * 32.0, hipLaunchKernelGGL(k_extrap, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, order,
+                                                          m->w.X, m->w.Xp, m->w.Xpp));
 }
 
 void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs) {

@@ -33,7 +33,7 @@ CLASS_OF = [
     (r"k_dots", "dots"), (r"k_axpy", "axpy_dots"), (r"k_combine", "combine"), (r"k_acc", "axpy"),
     (r"k_sum_partials", "finalize"), (r"k_gmres_ctl", "misc"), (r"k_mask_cols", "misc"),
     (r"k_copyout", "copyout"), (r"k_rhs", "rhs"), (r"k_flux", "flux"), (r"k_update", "update"),
-    (r"k_cfl", "cfl"), (r"k_copy", "copy"),
+    (r"k_cfl", "cfl"), (r"k_copyout", "copyout"), (r"k_copyin", "misc"), (r"k_copy", "copy"), (r"k_extrap", "extrap"),
 ]
 
 

@@ -114,3 +114,29 @@ def test_apply_precond_rejects_bad_arguments():
     with pytest.raises(g.GksError):
         gm.apply_precond(V, g.GKS_FP64, Z=V)
     gm.close()
+
+
+@pytest.mark.parametrize("precision", [g.GKS_FP64, g.GKS_MIXED])
+def test_extrapolated_start_cuts_iterations(precision):
+    """gks_step starts each solve from the extrapolation in time of the last
+    solutions (order 0, 1, then 2 as history accumulates).  On smooth
+    advection that start is orders of magnitude closer, so later steps need
+    fewer iterations; a reconstruction call in between restarts the history
+    without changing the converged result beyond the tolerance."""
+    mesh = gi.jss_mesh(64, 64, 2)
+    W0 = gi.density_advection_ic(mesh)
+    gm = g.GksMesh(mesh, precision=precision, tol=1e-10)
+    W = torch.tensor(W0, device="cuda")
+    its = []
+    for _ in range(6):
+        _, info = gm.step(W)
+        its.append(max(info["iters"]))
+    print("iterations per step", its, flush=True)
+    assert max(its[3:]) < its[1]
+    # same W, fresh handle: the reconstruction agrees to the solver tolerance
+    X1, _ = gm.reconstruct(W)
+    X2, _ = g.GksMesh(mesh, precision=precision, tol=1e-10).reconstruct(W)
+    assert float((X1 - X2).abs().max() / X2.abs().max()) < 1e-8
+    _, info = gm.step(W)   # order 0 again after the reconstruction
+    assert max(info["iters"]) <= its[1]
+    gm.close()
