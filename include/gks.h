@@ -138,6 +138,10 @@ typedef struct {
     int64_t graph_steps;     /* gks_step calls run through the captured graphs   */
     int32_t capture_failures;/* graph captures that failed (the step then ran
                                 with eager launches; 3 turn graphs off)         */
+    int32_t split_form;      /* 1: the cell graph has no 3-cycles, so BILU(0)
+                                has no off-diagonal fill (U = K_U, L = K_L D^-1)
+                                and the mixed form's inner sweeps run in the
+                                split form without products by all of K        */
 } gks_mesh_stats;
 
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,

@@ -65,7 +65,7 @@ class SolveInfo(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("nt", C.c_int32), ("nf", C.c_int32), ("nf_boundary", C.c_int32), ("n_levels", C.c_int32),
                 ("n_colors", C.c_int32), ("rcm_bandwidth", C.c_int32), ("device_bytes", C.c_int64),
-                ("graph_steps", C.c_int64), ("capture_failures", C.c_int32)]
+                ("graph_steps", C.c_int64), ("capture_failures", C.c_int32), ("split_form", C.c_int32)]
 
 
 class HostSystem(C.Structure):

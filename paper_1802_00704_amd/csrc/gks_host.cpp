@@ -490,6 +490,11 @@ struct HostSystem {
     std::vector<int32_t> lev_ptr;
     int n_levels = 0, n_colors = 0, rcm_bw = 0, nfb = 0;
     std::vector<double> Kval, a0c, Lval, Uval, Dv;
+    // When the cell graph has no 3-cycles BILU(0) has no off-diagonal fill:
+    // U = K_U and L = K_L D^-1 exactly, and the mixed-form inner sweeps use
+    // the split form (K_L blocks in L's slots, E = D - K_D per row).
+    bool tri_free = false;
+    std::vector<double> KLval, Ev;
     std::vector<int32_t> Kcol, nbc, iperm, Lcol, Ucol;
     std::vector<int32_t> own, nbr, cface, bck;
     std::vector<double> fgeo, gpd, cgeo, bcs;
@@ -753,6 +758,8 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     Dv.assign((size_t)25 * n, 0.0);
     Lcol.assign((size_t)LW * n, n);
     Ucol.assign((size_t)LW * n, n);
+    S.KLval.assign((size_t)LW * 25 * n, 0.0);
+    S.Ev.assign((size_t)25 * n, 0.0);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         const int* ci = &rc[(size_t)KW * i];
@@ -763,14 +770,35 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
             if (c < i) {
                 Lcol[(size_t)nl * n + i] = c;
                 for (int e = 0; e < 25; ++e) Lval[((size_t)nl * 25 + e) * n + i] = vi[a][e];
+                for (int s2 = 0; s2 < KW; ++s2)
+                    if (Kcol[(size_t)s2 * n + i] == c)
+                        for (int e = 0; e < 25; ++e)
+                            S.KLval[((size_t)nl * 25 + e) * n + i] = Kval[((size_t)s2 * 25 + e) * n + i];
                 ++nl;
             } else if (c > i) {
                 Ucol[(size_t)nu * n + i] = c;
                 for (int e = 0; e < 25; ++e) Uval[((size_t)nu * 25 + e) * n + i] = vi[a][e];
                 ++nu;
+            } else {
+                // E = D - K_D: the pivot block after elimination minus the diagonal of K
+                for (int e = 0; e < 25; ++e) S.Ev[(size_t)e * n + i] = vi[a][e] - Kval[(size_t)e * n + i];
             }
         }
         for (int e = 0; e < 25; ++e) Dv[(size_t)e * n + i] = dinv[i][e];
+    }
+    {
+        // 3-cycles of the cell graph (three mutually adjacent cells)
+        bool tri = false;
+#pragma omp parallel for schedule(static) reduction(|| : tri)
+        for (int i = 0; i < nt; ++i)
+            for (int a = 0; a < 3; ++a)
+                for (int b = a + 1; b < 3; ++b) {
+                    const int j = hm.nb[i][a], k = hm.nb[i][b];
+                    if (j < 0 || k < 0 || j == k) continue;
+                    for (int c = 0; c < 3; ++c)
+                        if (hm.nb[j][c] == k) tri = true;
+                }
+        S.tri_free = !tri;
     }
     pt.mark("BILU(0)");
     // ---- face / cell arrays in device layout
@@ -885,13 +913,18 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
             for (int i = S.lev_ptr[l]; i < S.lev_ptr[l + 1]; ++i)
                 for (int s2 = 0; s2 < KW; ++s2) d.lev_Kb[l] += S.Kcol[(size_t)s2 * n + i] != n ? 1.0 : 0.0;
         if (prm.precision == GKS_MIXED) {
-            d.Lval32 = dev_upload(m, pack_sliced<float>(S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr));
+            d.split = S.tri_free;
+            // split form: K_L in L's slots; general form: L itself
+            d.Lval32 = dev_upload(m, pack_sliced<float>(d.split ? S.KLval : S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr));
             d.Uval32 = dev_upload(m, pack_sliced<float>(S.Uval, S.Ucol, n, S.lev_ptr, Us, nullptr));
         }
     }
     d.Dinv = dev_upload(m, pack_blocks<double>(S.Dv, 1, n, np));
     if (prm.precision == GKS_MIXED) {
-        d.Kval32 = dev_upload(m, pack_blocks<float>(S.Kval, KW, n, np));
+        if (d.split)
+            d.E32 = dev_upload(m, pack_blocks<float>(S.Ev, 1, n, np));
+        else
+            d.Kval32 = dev_upload(m, pack_blocks<float>(S.Kval, KW, n, np));
         d.Dinv32 = dev_upload(m, pack_blocks<float>(S.Dv, 1, n, np));
     }
 
@@ -987,7 +1020,7 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
     const double* sk = &ks->scale[k][0];
     if (m->prm.precision == GKS_MIXED) {
         float* zk = w.Z + (int64_t)k * vs;
-        for (int j = 0; j < m->prm.inner_iters; ++j) launch_mx_sweep(m, j == 0, vk, sk, w.yf, w.df, zk, gate);
+        launch_mx_precond(m, vk, sk, zk, gate);
         launch_spmv64_f32x(m, zk, w.w, gate);
     } else {
         launch_ilu(m, vk, sk, w.t1, w.t2, gate);
@@ -1335,7 +1368,7 @@ int gks_apply_precond(gks_mesh* m, const double* V, double* Z, int form) {
             launch_ilu(m, w.t1, nullptr, w.t2, w.t3);
             launch_copyout(m, w.t3, Z);
         } else {
-            for (int j = 0; j < m->prm.inner_iters; ++j) launch_mx_sweep(m, j == 0, w.t1, w.ones, w.yf, w.df, w.Z);
+            launch_mx_precond(m, w.t1, w.ones, w.Z);
             launch_copyout_f32(m, w.Z, Z);
         }
         HIPCHK(hipStreamSynchronize(m->stream));
@@ -1477,6 +1510,7 @@ int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st) {
     st->device_bytes = m->dev_bytes;
     st->graph_steps = m->graph_steps;
     st->capture_failures = m->capture_failures;
+    st->split_form = m->d.split ? 1 : 0;
     return GKS_OK;
 }
 

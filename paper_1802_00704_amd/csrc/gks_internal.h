@@ -112,9 +112,11 @@ struct DevMesh {
     double* Uval = nullptr;       // sliced [chunk][25 * 64] strict upper factor blocks
     SlicedIdx Li{}, Ui{};         // their column indices and slice tables
     double* Dinv = nullptr;       // [25][np] inverted pivot blocks
-    float* Lval32 = nullptr;
-    float* Uval32 = nullptr;
+    float* Lval32 = nullptr;      // sliced FP32: L, or K_L in the split form
+    float* Uval32 = nullptr;      // sliced FP32: U (= K_U in the split form)
     float* Dinv32 = nullptr;
+    float* E32 = nullptr;         // split form: [25][np] D - K_D
+    bool split = false;           // mixed inner sweeps in the split form (cell graph without 3-cycles)
     std::vector<int32_t> lev_ptr; // host: rows of level l are [lev_ptr[l], lev_ptr[l+1])
     std::vector<int32_t> Lsbase, Usbase;  // host: first slice of each level
     std::vector<double> lev_Kb, lev_Lb, lev_Ub;  // host: stored K, L, U blocks per level
@@ -203,8 +205,8 @@ void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* g
 void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate = nullptr);
 void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out,
                 const int32_t* gate = nullptr);
-void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
-                     const int32_t* gate = nullptr);
+// z = P(s .* v): the mixed form's inner iteration, inner_iters sweeps
+void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate = nullptr);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,

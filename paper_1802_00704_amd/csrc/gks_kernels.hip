@@ -361,6 +361,147 @@ __global__ void __launch_bounds__(TPB) k_mx_bwd(int np, int r0, int r1, int sbas
     }
 }
 
+// ------------------------------------------------------------------ split-form inner sweeps
+// When the cell graph has no 3-cycles, BILU(0) has no off-diagonal fill, so
+// M = (D + K_L) D^-1 (D + K_U) with D the pivot blocks and K_L, K_U the
+// strict block triangles of K.  The Richardson sweep z <- z + M^-1 (b - K z)
+// is then  (D + K_L) w = b + E z + K_L D^-1 K_U z,  (D + K_U) z' = D w,
+// E = D - K_D, and the previous backward solve gives D^-1 K_U z = w_prev - z
+// (Eisenstat's observation), so no product with all of K is needed:
+//   forward  w_i = Dinv_i (b_i + E_i z_i - sum_{k<i} K_ik t_k),
+//            t_i = w_i - w_prev_i + z_i           (first sweep: z = 0, t = w)
+//   backward z'_i = w_i - Dinv_i sum_{j>i} K_ij z'_j
+// The last level has no upper neighbours (z'_i = w_i, set by the forward
+// kernel); the backward kernel of level 0 can also run the next sweep's
+// forward for its rows, which have no lower neighbours (BF).
+template <typename ACC>
+__device__ __forceinline__ void block_mul(float (&out)[CB], const float (&blk)[25], const ACC (&x)[CB]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < NB; ++r) {
+            ACC t = 0;
+#pragma unroll
+            for (int q = 0; q < NB; ++q) t += (ACC)blk[r * NB + q] * x[c * NB + q];
+            out[c * NB + r] = (float)t;
+        }
+}
+
+template <bool FIRST, bool LAST, typename ACC>
+__global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, SlicedIdx Li,
+                                                const float* __restrict__ KLv, const float* __restrict__ E,
+                                                const float* __restrict__ Dinv, const double* __restrict__ v,
+                                                const double* __restrict__ vscale, float* __restrict__ b,
+                                                float* __restrict__ t, float* __restrict__ w,
+                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
+    const int rl = xcd_row();
+    const int i = r0 + rl;
+    if (i >= r1) return;
+    ACC acc[CB];
+    float* bi = b + (int64_t)i * CB;
+    float zi[CB];
+    if (FIRST) {
+        const double* vi = v + (int64_t)i * CB;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double sc = vscale[c];
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const float x = (float)(sc * vi[c * NB + r]);
+                bi[c * NB + r] = x;
+                acc[c * NB + r] = (ACC)x;
+            }
+        }
+    } else {
+        const float* zp = z + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            zi[q] = zp[q];
+            acc[q] = (ACC)bi[q];
+        }
+        float eb[25];
+        load_block(E, np, 0, i, eb);
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) acc[c * NB + r] += (ACC)eb[r * NB + q] * (ACC)zi[c * NB + q];
+    }
+    slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), FIRST ? w : t);
+    float db[25];
+    load_block(Dinv, np, 0, i, db);
+    float wi[CB];
+    block_mul(wi, db, acc);
+    float* wp = w + (int64_t)i * CB;
+    if (!FIRST && !LAST) {
+        float* tp = t + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) tp[q] = wi[q] - wp[q] + zi[q];
+    }
+#pragma unroll
+    for (int q = 0; q < CB; ++q) wp[q] = wi[q];
+    if (LAST) {
+        float* zp = z + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) zp[q] = wi[q];
+    }
+}
+
+template <bool BF, typename ACC>
+__global__ void __launch_bounds__(TPB) k_es_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
+                                                const float* __restrict__ KUv, const float* __restrict__ E,
+                                                const float* __restrict__ Dinv, const float* __restrict__ b,
+                                                float* __restrict__ t, float* __restrict__ w,
+                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
+    const int rl = xcd_row();
+    const int i = r0 + rl;
+    if (i >= r1) return;
+    ACC acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0;
+    slice_sub(acc, KUv, Ui.col, slice_ref(Ui, sbase, rl), z);   // acc = -sum K_ij z'_j
+    float db[25];
+    load_block(Dinv, np, 0, i, db);
+    float u[CB];
+    block_mul(u, db, acc);
+    float* wp = w + (int64_t)i * CB;
+    float wi[CB], zn[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) {
+        wi[q] = wp[q];
+        zn[q] = wi[q] + u[q];
+    }
+    float* zp = z + (int64_t)i * CB;
+#pragma unroll
+    for (int q = 0; q < CB; ++q) zp[q] = zn[q];
+    if (BF) {
+        // next sweep, forward, for a row without lower neighbours
+        const float* bi = b + (int64_t)i * CB;
+        float eb[25];
+        load_block(E, np, 0, i, eb);
+        ACC a2[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) a2[q] = (ACC)bi[q];
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int r = 0; r < NB; ++r)
+#pragma unroll
+                for (int q = 0; q < NB; ++q) a2[c * NB + r] += (ACC)eb[r * NB + q] * (ACC)zn[c * NB + q];
+        float w2[CB];
+        block_mul(w2, db, a2);
+        float* tp = t + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            tp[q] = w2[q] - wi[q] + zn[q];
+            wp[q] = w2[q];
+        }
+    }
+}
+
 // ------------------------------------------------------------------ reductions
 // Per-column dot products p_j = V_j . w for j in a chunk of RED_CHUNK vectors
 // (blockIdx.y selects the chunk).  Each block writes its partial sums to
@@ -984,46 +1125,113 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
                                          m->d.Kval, m->d.Kcol, x, nullptr, b, y, gate));
 }
 
-// One inner sweep of the mixed form over all levels (see k_mx_fwd/k_mx_bwd).
-// Bytes: stored blocks (100 B FP32, 4 B index) of each level, plus per row
-// its own vectors (b in, y out; K z reads z once; backward y in, Dinv,
-// d out and z read-modify-write).
-void launch_mx_sweep(gks_mesh* m, bool first, const double* v, const double* vscale, float* y, float* d, float* z,
-                     const int32_t* gate) {
+// The mixed form's inner iteration z = P(s .* v): inner_iters BILU(0)-
+// preconditioned Richardson sweeps in FP32, in the split form when the
+// handle has it (see k_es_fwd/k_es_bwd), else the general fused sweeps
+// (k_mx_fwd/k_mx_bwd).  Bytes: stored blocks (100 B FP32, 4 B index) of each
+// level plus per row its own vectors (80 B FP32, 160 B FP64 v).
+static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
     using ACC = double;
     const DevMesh& D = m->d;
     float* b = m->w.bf;
+    float* y = m->w.yf;
+    float* d = m->w.df;
     const auto& lp = D.lev_ptr;
     const int nl = (int)lp.size() - 1;
     const double VF = VB / 2;
-    for (int l = 0; l < nl; ++l) {
-        const int r0 = lp[l], r1 = lp[l + 1];
-        if (r1 <= r0) continue;
-        const int rows = r1 - r0;
-        const double lb = D.lev_Lb[l] * 104.0;
-        if (first)
-            PROFB(KC_ILU_FWD32, lb + rows * (VB + 2 * VF),
-                  hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np, r0,
-                                     r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
-        else
-            PROFB(KC_ILU_FWD32, lb + D.lev_Kb[l] * 104.0 + rows * 3 * VF,
-                  hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np, r0,
-                                     r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
+    for (int sw = 0; sw < m->prm.inner_iters; ++sw) {
+        const bool first = sw == 0;
+        for (int l = 0; l < nl; ++l) {
+            const int r0 = lp[l], r1 = lp[l + 1];
+            if (r1 <= r0) continue;
+            const int rows = r1 - r0;
+            const double lb = D.lev_Lb[l] * 104.0;
+            if (first)
+                PROFB(KC_ILU_FWD32, lb + rows * (VB + 2 * VF),
+                      hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np,
+                                         r0, r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
+            else
+                PROFB(KC_ILU_FWD32, lb + D.lev_Kb[l] * 104.0 + rows * 3 * VF,
+                      hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np,
+                                         r0, r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
+        }
+        for (int l = nl - 1; l >= 0; --l) {
+            const int r0 = lp[l], r1 = lp[l + 1];
+            if (r1 <= r0) continue;
+            const int rows = r1 - r0;
+            const double ub = D.lev_Ub[l] * 104.0;
+            if (first)
+                PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 2 * VF),
+                      hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0,
+                                         r1, D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
+            else
+                PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 4 * VF),
+                      hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0,
+                                         r1, D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
+        }
     }
-    for (int l = nl - 1; l >= 0; --l) {
+}
+
+static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+    using ACC = double;
+    const DevMesh& D = m->d;
+    float* b = m->w.bf;
+    float* w = m->w.yf;
+    float* t = m->w.df;
+    const auto& lp = D.lev_ptr;
+    const int nl = (int)lp.size() - 1;
+    const int q = m->prm.inner_iters;
+    const double VF = VB / 2;
+    auto fwd = [&](int l, bool first) {
         const int r0 = lp[l], r1 = lp[l + 1];
-        if (r1 <= r0) continue;
+        if (r1 <= r0) return;
         const int rows = r1 - r0;
-        const double ub = D.lev_Ub[l] * 104.0;
-        if (first)
-            PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 2 * VF),
-                  hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0, r1,
-                                     D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
+        const bool last = l == nl - 1;
+        // blocks: K_L, Dinv (+ E); vectors: b (v when first), w, t, z
+        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + 2 * VF : 100.0 + 3 * VF)) +
+                          rows * VF * ((last ? 1 : 0) + (!first && !last ? 2 : 0));
+        const dim3 g(nblocks(rows)), bl(TPB);
+        if (first && last)
+            PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<true, true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
+                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+        else if (first)
+            PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<true, false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
+                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+        else if (last)
+            PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<false, true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
+                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
         else
-            PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 4 * VF),
-                  hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0, r1,
-                                     D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
+            PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<false, false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
+                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+    };
+    auto bwd = [&](int l, bool bf) {
+        const int r0 = lp[l], r1 = lp[l + 1];
+        if (r1 <= r0) return;
+        const int rows = r1 - r0;
+        // blocks: K_U, Dinv (+ E); vectors: w, z (+ b, t, w)
+        const double by = D.lev_Ub[l] * 104.0 + rows * (100.0 + 2 * VF) + (bf ? rows * (100.0 + 3 * VF) : 0.0);
+        const dim3 g(nblocks(rows)), bl(TPB);
+        if (bf)
+            PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
+                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, D.Dinv32, b, t, w, z, gate));
+        else
+            PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
+                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, D.Dinv32, b, t, w, z, gate));
+    };
+    for (int sw = 0; sw < q; ++sw) {
+        const bool first = sw == 0;
+        // level 0's forward of a later sweep ran in the previous sweep's BF launch
+        for (int l = (first || nl < 2) ? 0 : 1; l < nl; ++l) fwd(l, first);
+        for (int l = nl - 2; l >= 1; --l) bwd(l, false);
+        if (nl >= 2) bwd(0, sw + 1 < q);
     }
+}
+
+void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+    if (m->d.split)
+        mx_sweeps_split(m, v, vscale, z, gate);
+    else
+        mx_sweeps_general(m, v, vscale, z, gate);
 }
 
 // FP64 BILU(0) solve out = M^-1 (s .* in), level by level.  Bytes: stored

@@ -13,6 +13,7 @@ import numpy as np
 import pytest
 
 import gks_inputs as gi
+from mesh_variants import split_some_triangles
 
 torch = pytest.importorskip("torch")
 import paper_1802_00704_amd as g  # noqa: E402
@@ -75,9 +76,15 @@ def relerr(a, b):
 
 
 @pytest.mark.parametrize("case,ordering", [("adv", g.GKS_ORDER_MULTICOLOR), ("sv", g.GKS_ORDER_MULTICOLOR),
-                                           ("adv", g.GKS_ORDER_RCM), ("sv", g.GKS_ORDER_RCM)])
+                                           ("adv", g.GKS_ORDER_RCM), ("sv", g.GKS_ORDER_RCM),
+                                           ("split", g.GKS_ORDER_MULTICOLOR), ("split", g.GKS_ORDER_RCM)])
 def test_preconditioner_matches_host_factors(case, ordering):
-    mesh = gi.jss_mesh(20, 20, 1) if case == "adv" else sv_mesh()
+    """JSS meshes have no 3-cycles in their cell graph, so the mixed inner
+    sweeps run in the split form; the "split" case inserts centroid
+    vertices, whose three cells are mutually adjacent, and so runs the
+    general fused sweeps.  Both must equal plain Richardson on the factors."""
+    mesh = {"adv": lambda: gi.jss_mesh(20, 20, 1), "sv": sv_mesh,
+            "split": lambda: split_some_triangles(sv_mesh())}[case]()
     print("preconditioner case", case, "ordering", ordering, flush=True)
     hs = g.host_inspect(mesh, ordering=ordering)
     F = Factors(hs)
@@ -86,6 +93,7 @@ def test_preconditioner_matches_host_factors(case, ordering):
     Vd = torch.tensor(V, device="cuda")
 
     gm = g.GksMesh(mesh, ordering=ordering, precision=g.GKS_MIXED)
+    assert gm.stats()["split_form"] == (0 if case == "split" else 1)
     z64 = gm.apply_precond(Vd, g.GKS_FP64).cpu().numpy()
     v = F.to_solver(V)
     ref = F.to_caller(F.msolve(v))

@@ -15,6 +15,7 @@ import pytest
 import scipy.sparse as sp
 
 import gks_inputs as gi
+from mesh_variants import split_some_triangles
 import paper_1802_00704_amd as g
 from paper_1802_00704_amd import _lib
 from oracle import cls
@@ -169,3 +170,23 @@ def test_invalid_meshes_are_rejected():
         g.host_inspect(nonmanifold)
     with pytest.raises(g.GksError):
         g.host_inspect(m, restart=0)
+
+
+def _factor_blocks(hs):
+    n = hs["nt"]
+    K = {(i, int(hs["kcol"][s, i])): hs["kval"][s, :, i] for s in range(4) for i in range(n) if hs["kcol"][s, i] != n}
+    U = {(i, int(hs["ucol"][s, i])): hs["uval"][s, :, i] for s in range(3) for i in range(n) if hs["ucol"][s, i] != n}
+    return K, U
+
+
+def test_bilu0_has_no_fill_on_triangle_free_cell_graphs():
+    """Without 3-cycles in the cell graph, the elimination never updates an
+    off-diagonal block: U equals the upper blocks of K bitwise (the premise of
+    the split form of the mixed inner sweeps).  With 3-cycles it does not."""
+    left, _ = gi.shock_vortex_states()
+    walls = ((gi.BC_INFLOW, left), (gi.BC_OUTFLOW, None), (gi.BC_SLIP, None), (gi.BC_SLIP, None))
+    mesh = gi.jss_mesh(12, 6, 3, Lx=2.0, Ly=1.0, periodic=False, walls=walls)
+    K, U = _factor_blocks(g.host_inspect(mesh))
+    assert all(np.array_equal(U[key], K[key]) for key in U)
+    K, U = _factor_blocks(g.host_inspect(split_some_triangles(mesh)))
+    assert not all(np.array_equal(U[key], K[key]) for key in U)
