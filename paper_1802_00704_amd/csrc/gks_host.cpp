@@ -637,10 +637,11 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         key = col;
         S.n_colors = nkeys;
     }
-    // Rows of one level are independent; inside a level they are sorted by
-    // their number of neighbours in earlier levels (most first), RCM order
-    // breaking ties, so that 64-row slices of the factors have uniform
-    // widths (see the sliced factor storage of the sweep kernels).
+    // Rows of one level are independent.  Inside each window of 4096 rows of
+    // a level (RCM order) they are sorted by their number of neighbours in
+    // earlier levels, most first, so that 64-row slices of the factors have
+    // uniform widths (see the sliced factor storage of the sweep kernels)
+    // while a window keeps the spatial locality of its neighbour gathers.
     std::vector<int> nlow(nt, 0);
     for (int i = 0; i < nt; ++i)
         for (int s = 0; s < 3; ++s) {
@@ -649,9 +650,17 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         }
     std::vector<int>& perm = S.perm;
     perm = rcm;  // new -> old
-    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) {
-        return key[a] != key[b] ? key[a] < key[b] : nlow[a] > nlow[b];
-    });
+    std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return key[a] < key[b]; });
+    {
+        constexpr int SORT_WINDOW = 4096;   // a multiple of the 64-row slice
+        std::vector<int> lp(nkeys + 1, 0);
+        for (int i = 0; i < nt; ++i) lp[key[i] + 1]++;
+        for (int l = 0; l < nkeys; ++l) lp[l + 1] += lp[l];
+        for (int l = 0; l < nkeys; ++l)
+            for (int w0 = lp[l]; w0 < lp[l + 1]; w0 += SORT_WINDOW)
+                std::stable_sort(perm.begin() + w0, perm.begin() + std::min(w0 + SORT_WINDOW, lp[l + 1]),
+                                 [&](int a, int b) { return nlow[a] > nlow[b]; });
+    }
     std::vector<int> iperm(nt);
     for (int p = 0; p < nt; ++p) iperm[perm[p]] = p;
     S.lev_ptr.assign(nkeys + 1, 0);
@@ -949,6 +958,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     w.t3 = dev_alloc<double>(m, vec);
     w.nblk_red = std::max(1, std::min(1024, (n + 255) / 256));
     w.partial = dev_alloc<double>(m, (size_t)w.nblk_red * (MAXM + 1) * NC);
+    w.npart = dev_alloc<double>(m, (size_t)NC * (((size_t)n * 10 + 255) / 256 + 1));
     {
         std::vector<double> ones((size_t)(MAXM + 1) * NC, 1.0);
         w.ones = dev_upload(m, ones);
@@ -994,19 +1004,17 @@ bool all_conv(const Status* s) {
 // device flags st.run (Arnoldi steps) and st.fin (end of cycle), so the
 // arithmetic is the same either way.
 
-// norms of the right-hand side, zero columns of X masked
+// norms of the right-hand side (ks->sq, written by the RHS launch), zero
+// columns of X masked
 void solve_begin(gks_mesh* m) {
-    Work& w = m->w;
-    launch_dots_reduce(m, KC_DOTS, w.R, 0, 1, w.R, nullptr, w.ks->sq);
     launch_ctl(m, 0);
-    launch_mask_cols(m, w.X);
+    launch_mask_cols(m, m->w.X);
 }
 
 // r = R - K X, its norms, v_0 = r / |r|   (gate: st.fin in graphs)
 void cycle_start(gks_mesh* m, const int32_t* gate) {
     Work& w = m->w;
-    launch_resid(m, w.X, w.R, w.V, gate);
-    launch_dots_reduce(m, KC_DOTS, w.V, 0, 1, w.V, nullptr, w.ks->sq, gate);
+    launch_resid(m, w.X, w.R, w.V, gate, w.ks->sq);
     launch_ctl(m, 1, gate != nullptr);
 }
 
@@ -1029,8 +1037,7 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
     launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0], gate);
     launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, gate);
     launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0], gate);
-    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, gate);
-    launch_dots_reduce(m, KC_DOTS, vk1, 0, 1, vk1, nullptr, ks->sq, gate);
+    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, gate, ks->sq);
     launch_ctl(m, 2);
 }
 
@@ -1109,7 +1116,7 @@ int solve_loop(gks_mesh* m, gks_solve_info* info, int resume, int k0) {
 // (W is copied into Wint first), so they stay valid for any caller W.
 void issue_solve_graph(gks_mesh* m, int budget) {
     KrylovState* ks = m->w.ks;
-    launch_rhs(m, m->w.Wint);
+    launch_rhs(m, m->w.Wint, ks->sq);
     solve_begin(m);
     cycle_start(m, nullptr);
     for (int k = 0; k < budget; ++k) arnoldi_step(m, k, &ks->st.run);
@@ -1211,7 +1218,7 @@ double ms_since(std::chrono::steady_clock::time_point t0) {
 // check, so host time measures the device work) goes to info->solve_ms.
 int run_solve(gks_mesh* m, const double* W, gks_solve_info* info) {
     const auto t0 = std::chrono::steady_clock::now();
-    launch_rhs(m, W);
+    launch_rhs(m, W, m->w.ks->sq);
     const int st = solve_loop(m, info, RESUME_NONE, 0);
     if (info) info->solve_ms = ms_since(t0);
     return st;

@@ -130,6 +130,7 @@ struct Work {
     float* yf = nullptr;          // [n+1][CB] mixed inner sweeps: forward result
     float* df = nullptr;          // [n+1][CB] mixed inner sweeps: correction
     float* bf = nullptr;          // [n+1][CB] mixed inner sweeps: FP32 right-hand side
+    double* npart = nullptr;      // per-block partial sums of the fused norms: [4][blocks of 10 n threads]
     float* Xp = nullptr;          // [n][CB] solution of the step before the last (FP32)
     float* Xpp = nullptr;         // [n][CB] the one before that (FP32)
     double* w = nullptr;          // [n+1][CB]
@@ -197,12 +198,15 @@ enum Kc {
 extern const char* kc_names[NPROF];
 
 // launchers (gks_kernels.hip); all enqueue on m->stream
-void launch_rhs(gks_mesh* m, const double* W);
+// sq_out (device, 4 doubles): when given, also the per-column sums of R^2
+void launch_rhs(gks_mesh* m, const double* W, double* sq_out = nullptr);
 // gate: device flag; when non-null and zero the kernels return at once (used to
 // unroll a fixed iteration budget into a captured graph).
 void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y, const int32_t* gate = nullptr);
 void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* gate = nullptr);
-void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate = nullptr);
+// sq_out: when given, also the per-column sums of y^2 (fused reduction)
+void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate = nullptr,
+                  double* sq_out = nullptr);
 void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out,
                 const int32_t* gate = nullptr);
 // z = P(s .* v): the mixed form's inner iteration, inner_iters sweeps
@@ -210,7 +214,7 @@ void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                 const double* w, double* out, const int32_t* gate = nullptr);
+                 const double* w, double* out, const int32_t* gate = nullptr, double* sq_out = nullptr);
 // nvec_dev: when non-null the number of vectors is min(nvec, *nvec_dev)
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);

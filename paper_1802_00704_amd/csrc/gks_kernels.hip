@@ -25,6 +25,8 @@ constexpr int TPB = 256;          // threads per block of the streaming kernels
 constexpr int RED_CHUNK = 8;      // vectors per block of the dot kernel
 
 static inline int nblocks(int64_t n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
+// grid of the Gram-Schmidt update (grid-stride beyond): 8 blocks per CU
+constexpr int AXPY_BLOCKS = 2048;
 
 // The hardware hands consecutive workgroups of a grid to the 8 XCDs in turn,
 // and each XCD has its own L2.  Row kernels gather neighbour blocks, so they
@@ -69,94 +71,136 @@ __device__ __forceinline__ void load_block(const T* __restrict__ val, int64_t np
     blk[24] = base[24 * np + i];
 }
 
+// Per-column sums of squares of the values a thread produced, reduced over
+// the block in a fixed order (wave butterfly, then the block's waves) to
+// partial[c * gridDim.x + blockIdx.x].  Every thread of the block must call
+// it (no early return before it); blockDim.x == TPB.
+__device__ __forceinline__ void block_sumsq4(const double (&s)[NC], double* __restrict__ partial) {
+    __shared__ double sh[NC][TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+        double v = s[c];
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (lane == 0) sh[c][wid] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < NC) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / 64; ++q) t += sh[threadIdx.x][q];
+        partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+    }
+}
+
 // ------------------------------------------------------------------ RHS
 // R_i = sum_j a0_ij (W_j - W_i) for the four variables (Eq. A:B:b, b = C^T b).
 // One thread per cell in the caller's order (W reads stay local); the
 // 160-byte block goes to the cell's solver row.
+// With partial != NULL the block also writes the per-column sums of R^2.
 __global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__ iperm,
                                              const int32_t* __restrict__ nbc, const double* __restrict__ a0c,
-                                             const double* __restrict__ W, double* __restrict__ R) {
+                                             const double* __restrict__ W, double* __restrict__ R,
+                                             double* __restrict__ partial) {
     const int oi = xcd_row();
-    if (oi >= nt) return;
-    double wi[NC];
+    double sq[NC] = {0.0, 0.0, 0.0, 0.0};
+    if (oi < nt) {
+        double wi[NC];
 #pragma unroll
-    for (int c = 0; c < NC; ++c) wi[c] = W[(int64_t)c * nt + oi];
-    double acc[NC][NB];
+        for (int c = 0; c < NC; ++c) wi[c] = W[(int64_t)c * nt + oi];
+        double acc[NC][NB];
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int l = 0; l < NB; ++l) acc[c][l] = 0.0;
+            for (int l = 0; l < NB; ++l) acc[c][l] = 0.0;
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const int j = nbc[(int64_t)s * nt + oi];
-        double a[NB];
+        for (int s = 0; s < 3; ++s) {
+            const int j = nbc[(int64_t)s * nt + oi];
+            double a[NB];
 #pragma unroll
-        for (int l = 0; l < NB; ++l) a[l] = a0c[((int64_t)s * NB + l) * nt + oi];
+            for (int l = 0; l < NB; ++l) a[l] = a0c[((int64_t)s * NB + l) * nt + oi];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double d = W[(int64_t)c * nt + j] - wi[c];
+            for (int c = 0; c < NC; ++c) {
+                const double d = W[(int64_t)c * nt + j] - wi[c];
 #pragma unroll
-            for (int l = 0; l < NB; ++l) acc[c][l] += a[l] * d;
+                for (int l = 0; l < NB; ++l) acc[c][l] += a[l] * d;
+            }
         }
+        double* out = R + (int64_t)iperm[oi] * CB;
+#pragma unroll
+        for (int c = 0; c < NC; ++c)
+#pragma unroll
+            for (int l = 0; l < NB; ++l) {
+                out[c * NB + l] = acc[c][l];
+                sq[c] += acc[c][l] * acc[c][l];
+            }
     }
-    double* out = R + (int64_t)iperm[oi] * CB;
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int l = 0; l < NB; ++l) out[c * NB + l] = acc[c][l];
+    if (partial) block_sumsq4(sq, partial);
 }
 
 // ------------------------------------------------------------------ SpMV
 // y = K (s .* x)   or   y = b - K x   (RESID), block-ELL, thread per row.
 // In RESID mode xscale (when not null) scales b instead: y = s .* b - K x.
 // MT: matrix element type; XT: element type of the input vector x.
+// In RESID mode with partial != NULL the block also writes the per-column
+// sums of y^2 (no early return then: every thread reaches the reduction).
 template <typename T, typename XT, bool RESID>
 __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col,
                                               const XT* __restrict__ x, const double* __restrict__ xscale,
                                               const double* __restrict__ b, double* __restrict__ y,
-    const int32_t* __restrict__ gate) {
+    const int32_t* __restrict__ gate, double* __restrict__ partial = nullptr) {
     if (gate && *gate == 0) return;
     const int i = xcd_row();
-    if (i >= n) return;
-    double acc[NC][NB];
-#pragma unroll
-    for (int c = 0; c < NC; ++c)
-#pragma unroll
-        for (int r = 0; r < NB; ++r) acc[c][r] = 0.0;
-#pragma unroll
-    for (int s = 0; s < KW; ++s) {
-        const int j = col[(int64_t)s * n + i];
-        const XT* xj = x + (int64_t)j * CB;
-        double xv[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) xv[q] = (double)xj[q];
-        T blk[25];
-        load_block(val, np, s, i, blk);
+    const bool valid = i < n;
+    if (!valid && !(RESID && partial)) return;
+    double sq[NC] = {0.0, 0.0, 0.0, 0.0};
+    if (valid) {
+        double acc[NC][NB];
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int r = 0; r < NB; ++r)
+            for (int r = 0; r < NB; ++r) acc[c][r] = 0.0;
 #pragma unroll
-                for (int q = 0; q < NB; ++q) acc[c][r] += (double)blk[r * NB + q] * xv[c * NB + q];
-    }
-    double* yi = y + (int64_t)i * CB;
-    if (RESID) {
-        const double* bi = b + (int64_t)i * CB;
+        for (int s = 0; s < KW; ++s) {
+            const int j = col[(int64_t)s * n + i];
+            const XT* xj = x + (int64_t)j * CB;
+            double xv[CB];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double sc = xscale ? xscale[c] : 1.0;
+            for (int q = 0; q < CB; ++q) xv[q] = (double)xj[q];
+            T blk[25];
+            load_block(val, np, s, i, blk);
 #pragma unroll
-            for (int r = 0; r < NB; ++r) yi[c * NB + r] = sc * bi[c * NB + r] - acc[c][r];
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NB; ++r)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) acc[c][r] += (double)blk[r * NB + q] * xv[c * NB + q];
         }
-    } else {
-        double sc[NC];
+        double* yi = y + (int64_t)i * CB;
+        if (RESID) {
+            const double* bi = b + (int64_t)i * CB;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) sc[c] = xscale ? xscale[c] : 1.0;
+            for (int c = 0; c < NC; ++c) {
+                const double sc = xscale ? xscale[c] : 1.0;
 #pragma unroll
-        for (int c = 0; c < NC; ++c)
+                for (int r = 0; r < NB; ++r) {
+                    const double v = sc * bi[c * NB + r] - acc[c][r];
+                    yi[c * NB + r] = v;
+                    sq[c] += v * v;
+                }
+            }
+        } else {
+            double sc[NC];
 #pragma unroll
-            for (int r = 0; r < NB; ++r) yi[c * NB + r] = sc[c] * acc[c][r];
+            for (int c = 0; c < NC; ++c) sc[c] = xscale ? xscale[c] : 1.0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NB; ++r) yi[c * NB + r] = sc[c] * acc[c][r];
+        }
     }
+    if (RESID && partial) block_sumsq4(sq, partial);
 }
 
 // ------------------------------------------------------------------ BILU(0) sweeps
@@ -565,27 +609,34 @@ struct Grp {
     static constexpr int T = CB / E;            // threads per cell
 };
 
-// out = w - sum_j h_j[c] scale_j[c] V_j   (out may alias w)
+// out = w - sum_j h_j[c] scale_j[c] V_j   (out may alias w).  With partial
+// != NULL the block also writes the per-column sums of out^2.
 __global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ V, int64_t vstride, int nvec,
                                               const double* __restrict__ h, const double* __restrict__ scale,
                                               const double* w, double* out,
-    const int32_t* __restrict__ gate) {
+    const int32_t* __restrict__ gate, double* __restrict__ partial) {
     if (gate && *gate == 0) return;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t i = t / 10;
-    const int p = (int)(t - i * 10);
-    if (i >= n) return;
-    const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
-    const int64_t off = i * CB + 2 * p;
-    const double2 w2 = *reinterpret_cast<const double2*>(w + off);
-    double a0 = w2.x, a1 = w2.y;
+    double sq[NC] = {0.0, 0.0, 0.0, 0.0};
+    const int64_t npair = (int64_t)n * 10;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npair; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / 10;
+        const int p = (int)(t - i * 10);
+        const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
+        const int64_t off = i * CB + 2 * p;
+        const double2 w2 = *reinterpret_cast<const double2*>(w + off);
+        double a0 = w2.x, a1 = w2.y;
 #pragma unroll 4
-    for (int j = 0; j < nvec; ++j) {
-        const double2 v = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
-        a0 -= h[j * NC + c0] * scale[j * NC + c0] * v.x;
-        a1 -= h[j * NC + c1] * scale[j * NC + c1] * v.y;
+        for (int j = 0; j < nvec; ++j) {
+            const double2 v = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
+            a0 -= h[j * NC + c0] * scale[j * NC + c0] * v.x;
+            a1 -= h[j * NC + c1] * scale[j * NC + c1] * v.y;
+        }
+        *reinterpret_cast<double2*>(out + off) = make_double2(a0, a1);
+        // columns of a pair: c0 == c1 except for pairs straddling a column
+#pragma unroll
+        for (int c = 0; c < NC; ++c) sq[c] += (c == c0 ? a0 * a0 : 0.0) + (c == c1 ? a1 * a1 : 0.0);
     }
-    *reinterpret_cast<double2*>(out + off) = make_double2(a0, a1);
+    if (partial) block_sumsq4(sq, partial);
 }
 
 // out = sum_j y_j[c] scale_j[c] V_j
@@ -630,18 +681,35 @@ __global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X
 
 // Sum partials of nval values in a fixed order: one wave per value.
 // mode 0: out[v] = sum;  mode 1: out[v] = sum * scale[v]
+// One block per value: each thread sums a strided subset with four
+// independent accumulators (loads in flight), then the block reduces them;
+// the order is fixed, so results are reproducible.
 __global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const double* __restrict__ partial,
                                                       const double* __restrict__ scale, double* __restrict__ out,
     const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    const int v = blockIdx.x * (TPB / 64) + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (v >= nval) return;
-    double s = 0.0;
-    for (int b = lane; b < nblk; b += 64) s += partial[(int64_t)v * nblk + b];
+    __shared__ double sh[TPB / 64];
+    const int v = blockIdx.x;
+    const double* p = partial + (int64_t)v * nblk;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    int b = threadIdx.x;
+    for (; b + 3 * TPB < nblk; b += 4 * TPB) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) a[k] += p[b + k * TPB];
+    }
+    for (int k = 0; b < nblk; b += TPB, ++k) a[k & 3] += p[b];
+    double s = (a[0] + a[1]) + (a[2] + a[3]);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-    if (lane == 0) out[v] = scale ? s * scale[v] : s;
+    if (lane == 0) sh[wid] = s;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / 64; ++q) t += sh[q];
+        out[v] = scale ? t * scale[v] : t;
+    }
 }
 
 // ------------------------------------------------------------------ GMRES bookkeeping (one wave)
@@ -1101,10 +1169,15 @@ static inline void check_launch(int kc) {
 
 
 
-void launch_rhs(gks_mesh* m, const double* W) {
+void launch_rhs(gks_mesh* m, const double* W, double* sq_out) {
     const int nt = m->d.nt;
-    PROFB(KC_RHS, nt * (3 * (4.0 + 40.0) + 4.0 + 4 * 8.0 * 4 + VB), hipLaunchKernelGGL(k_rhs, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.iperm, m->d.nbc,
-                                    m->d.a0c, W, m->w.R));
+    const int nb = nblocks(nt);
+    double* part = sq_out ? m->w.npart : nullptr;
+    PROFB(KC_RHS, nt * (3 * (4.0 + 40.0) + 4.0 + 4 * 8.0 * 4 + VB), hipLaunchKernelGGL(k_rhs, dim3(nb), dim3(TPB), 0, m->stream, nt, m->d.iperm, m->d.nbc,
+                                    m->d.a0c, W, m->w.R, part));
+    if (sq_out)
+        PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(NC), dim3(TPB), 0, m->stream, NC, nb, part, nullptr, sq_out,
+                                          nullptr));
 }
 
 void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y, const int32_t* gate) {
@@ -1119,10 +1192,15 @@ void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* g
                                          m->d.Kval, m->d.Kcol, x, nullptr, nullptr, y, gate));
 }
 
-void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate) {
+void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate, double* sq_out) {
     const int n = m->d.n;
-    PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, double, true>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, nullptr, b, y, gate));
+    const int nb = nblocks(n);
+    double* part = sq_out ? m->w.npart : nullptr;
+    PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, double, true>), dim3(nb), dim3(TPB), 0, m->stream, n, m->d.np,
+                                         m->d.Kval, m->d.Kcol, x, nullptr, b, y, gate, part));
+    if (sq_out)
+        PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(NC), dim3(TPB), 0, m->stream, NC, nb, part, nullptr, sq_out,
+                                          gate));
 }
 
 // The mixed form's inner iteration z = P(s .* v): inner_iters BILU(0)-
@@ -1266,15 +1344,20 @@ void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, i
     PROFB(kc, (double)n * (nvec + 1) * VB, hipLaunchKernelGGL(k_dots, dim3(nb, nch), dim3(TPB), 0, m->stream, n, V, vstride, nvec, w,
                                 m->w.partial, gate));
     const int nval = nvec * NC;
-    PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3((nval + 3) / 4), dim3(TPB), 0, m->stream, nval, nb,
+    PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(nval), dim3(TPB), 0, m->stream, nval, nb,
                                       m->w.partial, scale, out, gate));
 }
 
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                 const double* w, double* out, const int32_t* gate) {
+                 const double* w, double* out, const int32_t* gate, double* sq_out) {
     const int n = m->d.n;
-    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nblocks((int64_t)n * 10)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
-                                          h, scale, w, out, gate));
+    const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));   // grid-stride beyond
+    double* part = sq_out ? m->w.npart : nullptr;
+    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
+                                          h, scale, w, out, gate, part));
+    if (sq_out)
+        PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(NC), dim3(TPB), 0, m->stream, NC, nb, part, nullptr, sq_out,
+                                          gate));
 }
 
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
