@@ -94,11 +94,11 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
             "sample": "%s, %d steps in %.1f s" % (sample, steps, el)}
 
 
-def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, graphs: int = 1):
+def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, graphs: int = 1, limiter: int = 0):
     import torch
     import paper_1802_00704_amd as g
     t0 = time.perf_counter()
-    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1, graphs=graphs)
+    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1, graphs=graphs, limiter=limiter)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     W = torch.tensor(W0, dtype=torch.float64, device="cuda")
@@ -107,12 +107,14 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
     torch.cuda.synchronize()
     lat = []
     iters = []
+    limited = []
     t_start = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
         used, info = gm.step(W)
         lat.append(time.perf_counter() - t)
         iters.append(max(info["iters"]))
+        limited.append(info["limited"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     # Kernel durations: the same number of steps again with a HIP event pair
@@ -137,6 +139,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         "step_ms_p50": float(np.percentile(lat_ms, 50)),
         "step_ms_p99": float(np.percentile(lat_ms, 99)),
         "krylov_iters_per_step": float(np.mean(iters)),
+        "limited_cells_per_step": float(np.mean(limited)),
         "setup_s": setup_s,
         "stats": stats,
         "profile": prof,
@@ -210,6 +213,8 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=60,
                     help="requests of the serving stream to run after the throughput legs (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--no-limiter-leg", action="store_true",
+                    help="skip the extra run of the mixed form with the DWBAP limiter on")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X only; multi-GPU runs are not part of this build "
@@ -228,6 +233,21 @@ def main():
               flush=True)
     head = forms[0]
     r = res[head]
+    # the DWBAP limiter (section 3.3) on the same workload, mixed form
+    lim = None
+    if not args.no_limiter_leg:
+        rl = run_form(m, W0, g.GKS_MIXED, args.steps, args.warmup, not args.no_profile, args.graphs, limiter=1)
+        pl = rl["profile"].get("limit") if rl["profile"] else None
+        lim = {"ms_per_step": rl["ms_per_step"], "value": rl["value"],
+               "limited_cells_per_step": rl["limited_cells_per_step"],
+               "krylov_iters_per_step": rl["krylov_iters_per_step"]}
+        if pl and pl["ms"] > 0:
+            lim["kernel"] = {"avg_launch_us": round(pl["ms"] * 1e3 / max(1, pl["launches"]), 2),
+                             "achieved_GBs": round(pl["bytes"] / (pl["ms"] * 1e-3) / 1e9, 1),
+                             "frac_of_hbm_peak": round(pl["bytes"] / (pl["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                             "traffic": measured_traffic("limit")}
+        print("# mixed + limiter: %.4g cell-steps/s, %.3f ms/step, %.0f cells limited per step" %
+              (rl["value"], rl["ms_per_step"], rl["limited_cells_per_step"]), file=sys.stderr, flush=True)
     serving = serving_leg(args.serving_requests, args.serving_slots) if args.serving_requests > 0 else None
     if serving:
         print("# serving: %.4g cell-steps/s, step p50/p99 %.2f/%.2f ms, solve p50/p99 %.2f/%.2f ms" %
@@ -263,6 +283,7 @@ def main():
                        "serving_solve_p50": serving["solve_ms_p50"] if serving else None,
                        "serving_solve_p99": serving["solve_ms_p99"] if serving else None},
         "serving": serving,
+        "limiter": lim,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out))

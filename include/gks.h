@@ -116,6 +116,11 @@ typedef struct {
                                 adaptive (follows the first-cycle length of
                                 recent steps, re-capturing when it changes);
                                 k > 0 = exactly min(k, restart, max_iter)       */
+    int32_t limiter;         /* 1: gks_step limits the reconstruction with the
+                                DWBAP limiter of section 3.3 (Eqs. DWBAP,
+                                DWBAP_w, DWBAP_S) where the shock indicator of
+                                Eqs. ISD1-2 reaches 1, before the fluxes; the
+                                solver keeps the unlimited X.  0: off          */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -126,6 +131,7 @@ typedef struct {
     int32_t nonphys;         /* non-physical Gauss-point states met in the flux  */
     double  solve_ms;        /* host wall time of the reconstruction solve       */
     double  call_ms;         /* host wall time of the whole call                 */
+    int32_t limited;         /* cells the limiter changed in this step            */
 } gks_solve_info;
 
 /* Mesh statistics. */
@@ -202,6 +208,18 @@ int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st);
 int gks_profile_enable(gks_mesh* m, int enable);
 int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, double* total_ms,
                     double* total_bytes);
+
+/* DWBAP limiter of section 3.3 on caller coefficients: cells whose density
+ * shock indicator IS_i (Eq. ISD1) is at least `threshold` (Eq. ISD2 uses 1)
+ * get their derivatives replaced by the biased average of Eq. DWBAP over
+ * their own value and candidates from their face neighbours, with the
+ * weights of Eqs. DWBAP_w and DWBAP_S; the other cells are copied.  W
+ * [4][nt] and X, Xout [4][5][nt] are device arrays in the caller's cell
+ * order (the layouts of gks_step and gks_cls_reconstruct); Xout must not
+ * alias X.  n_limited (host, may be NULL) receives the number of limited
+ * cells.  Errors: GKS_EINVAL, GKS_EHIP. */
+int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold,
+              int32_t* n_limited);
 
 /* Apply the solve's preconditioner to four columns: Z = P(V), where P is
  * the BILU(0) factorisation of section 3.2 (form GKS_FP64: one forward and

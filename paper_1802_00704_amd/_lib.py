@@ -19,7 +19,7 @@ GKS_FP64, GKS_MIXED = 0, 1
 GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM = 0, 1
 
 EXPORTS = ("gks_params_default", "gks_mesh_create", "gks_cls_reconstruct", "gks_flux", "gks_step",
-           "gks_faces", "gks_mesh_get_stats", "gks_profile_enable", "gks_profile_get", "gks_apply_precond",
+           "gks_faces", "gks_mesh_get_stats", "gks_profile_enable", "gks_profile_get", "gks_apply_precond", "gks_limit",
            "gks_host_inspect", "gks_host_free", "gks_last_error", "gks_destroy")
 
 
@@ -49,17 +49,18 @@ class Params(C.Structure):
                 ("cfl", C.c_double), ("tol", C.c_double), ("restart", C.c_int32), ("max_iter", C.c_int32),
                 ("precision", C.c_int32), ("ordering", C.c_int32), ("inner_iters", C.c_int32),
                 ("exact_time", C.c_int32), ("nonphys_fallback", C.c_int32), ("all_quadratic", C.c_int32),
-                ("graphs", C.c_int32), ("graph_budget", C.c_int32)]
+                ("graphs", C.c_int32), ("graph_budget", C.c_int32), ("limiter", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32 * 4), ("restarts", C.c_int32 * 4), ("rel_resid", C.c_double * 4),
-                ("nonphys", C.c_int32), ("solve_ms", C.c_double), ("call_ms", C.c_double)]
+                ("nonphys", C.c_int32), ("solve_ms", C.c_double), ("call_ms", C.c_double),
+                ("limited", C.c_int32)]
 
     def as_dict(self):
         return {"iters": list(self.iters), "restarts": list(self.restarts),
                 "rel_resid": list(self.rel_resid), "nonphys": int(self.nonphys),
-                "solve_ms": float(self.solve_ms), "call_ms": float(self.call_ms)}
+                "solve_ms": float(self.solve_ms), "call_ms": float(self.call_ms), "limited": int(self.limited)}
 
 
 class Stats(C.Structure):
@@ -100,6 +101,8 @@ def lib():
         L.gks_step.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
         L.gks_step.restype = C.c_int
         L.gks_faces.argtypes = [vp, vp, vp]
+        L.gks_limit.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int32)]
+        L.gks_limit.restype = C.c_int
         L.gks_apply_precond.argtypes = [vp, vp, vp, C.c_int]
         L.gks_apply_precond.restype = C.c_int
         L.gks_faces.restype = C.c_int
@@ -265,6 +268,17 @@ class GksMesh:
         code = lib().gks_step(self._h, _dev(W, (4, self.nt), "W"), float(dt), C.byref(used), C.byref(info))
         _check(code, self._h)
         return used.value, info.as_dict()
+
+    def limit(self, W, X, threshold: float = 1.0, Xout=None):
+        """(Xout, n_limited): X limited by the DWBAP limiter (gks_limit)."""
+        import torch
+        if Xout is None:
+            Xout = torch.empty((4, 5, self.nt), dtype=torch.float64, device=X.device)
+        n = C.c_int32(0)
+        code = lib().gks_limit(self._h, _dev(W, (4, self.nt), "W"), _dev(X, (4, 5, self.nt), "X"),
+                               _dev(Xout, (4, 5, self.nt), "Xout"), float(threshold), C.byref(n))
+        _check(code, self._h)
+        return Xout, int(n.value)
 
     def apply_precond(self, V, form: int = 0, Z=None):
         """Z = P(V) with the solver's preconditioner (gks_apply_precond)."""

@@ -965,6 +965,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     }
     w.ks = dev_alloc<KrylovState>(m, 1);
     w.Xcell = dev_alloc<double>(m, (size_t)20 * nt);
+    if (prm.limiter) w.Xlim = dev_alloc<double>(m, (size_t)20 * nt);
     w.F = dev_alloc<double>(m, (size_t)4 * nf);
     w.Wn = dev_alloc<double>(m, (size_t)4 * nt);
     w.Wint = dev_alloc<double>(m, (size_t)4 * nt);
@@ -1128,7 +1129,12 @@ void issue_update_graph(gks_mesh* m) {
     Work& w = m->w;
     launch_copyout(m, w.X, w.Xcell);
     launch_zero_i32(m, w.counters, 4);
-    launch_flux(m, w.Wint, w.Xcell, w.dt_dev, w.F);
+    const double* Xf = w.Xcell;
+    if (m->prm.limiter) {
+        launch_limit(m, w.Wint, w.Xcell, w.Xlim, 1.0, w.counters + 2);
+        Xf = w.Xlim;
+    }
+    launch_flux(m, w.Wint, Xf, w.dt_dev, w.F);
     launch_update(m, w.Wint, w.F, w.Wn);
 }
 
@@ -1244,7 +1250,7 @@ bool params_ok(const gks_params& p) {
            p.max_iter >= 1 && p.mu >= 0.0 && p.tau_eps >= 0.0 && p.cls_w > 0.0 &&
            (p.precision == GKS_FP64 || p.precision == GKS_MIXED) &&
            (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
-           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0;
+           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == 1);
 }
 
 int fail(gks_mesh* m, const Fail& f) {
@@ -1277,6 +1283,7 @@ void gks_params_default(gks_params* p) {
     p->all_quadratic = 0;
     p->graphs = 1;
     p->graph_budget = 0;
+    p->limiter = 0;
 }
 
 int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_stream, gks_mesh** out) {
@@ -1351,6 +1358,28 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
         }
         if (st != GKS_OK) m->err = "GMRES did not converge within max_iter";
         return st;
+    } catch (const Fail& f) {
+        return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
+    }
+}
+
+int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int32_t* n_limited) {
+    if (!m) return GKS_EINVAL;
+    if (!W || !X || !Xout || (const void*)X == (const void*)Xout || !(threshold == threshold)) {
+        m->err = "gks_limit needs W, X, Xout (not aliasing X) and a threshold";
+        return GKS_EINVAL;
+    }
+    try {
+        launch_zero_i32(m, m->w.counters, 4);
+        launch_limit(m, W, X, Xout, threshold, m->w.counters + 2);
+        HIPCHK(hipMemcpyAsync(m->w.counters_host, m->w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                              m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+        prof_collect(m);
+        if (n_limited) *n_limited = m->w.counters_host[2];
+        return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
     } catch (const LaunchError& e) {
@@ -1471,13 +1500,21 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
                 return st;
             }
             launch_copyout(m, w.X, w.Xcell);
-            launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
+            const double* Xf = w.Xcell;
+            if (m->prm.limiter) {
+                launch_limit(m, W, w.Xcell, w.Xlim, 1.0, w.counters + 2);
+                Xf = w.Xlim;
+            }
+            launch_flux(m, W, Xf, w.dt_dev, w.F);
             launch_update(m, W, w.F, w.Wn);
         }
         HIPCHK(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));
         HIPCHK(hipMemcpyAsync(w.scal_host, w.dt_dev, sizeof(double), hipMemcpyDeviceToHost, m->stream));
         HIPCHK(hipStreamSynchronize(m->stream));
-        if (info) info->nonphys = w.counters_host[0];
+        if (info) {
+            info->nonphys = w.counters_host[0];
+            info->limited = w.counters_host[2];
+        }
         if (dt_used) *dt_used = w.scal_host[0];
         if ((w.counters_host[0] > 0 && !m->prm.nonphys_fallback) || w.counters_host[1] > 0) {
             prof_collect(m);

@@ -19,7 +19,7 @@ namespace gks {
 const char* kc_names[NPROF] = {"rhs",       "spmv",       "spmv_resid", "ilu_fwd",  "ilu_bwd",
                                "dots",      "axpy_dots",  "axpy_norm",  "finalize", "combine",
                                "axpy",      "copyout",    "flux",       "update",   "cfl",
-                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "", "", "", ""};
+                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "limit", "", "", ""};
 
 constexpr int TPB = 256;          // threads per block of the streaming kernels
 constexpr int RED_CHUNK = 8;      // vectors per block of the dot kernel
@@ -1153,6 +1153,193 @@ void prof_end(gks_mesh* m, int kc) {
 constexpr double VB = CB * 8.0;
 inline double spmv_bytes(int n, int esz, bool resid) { return n * (KW * 25.0 * esz + KW * 4.0 + (resid ? 3 : 2) * VB); }
 
+// ------------------------------------------------------------------ DWBAP limiter
+// Section 3.3: where the density shock indicator IS_i (Eq. ISD1) reaches
+// the threshold (1 in Eq. ISD2), the derivatives of every conserved variable
+// are replaced by L = tan(sum_j w_j atan(u_j)) over the cell's own value and
+// candidates from its face neighbours (Eq. DWBAP), with weights
+// w_j ~ (mean distance from r_j to the cell's face midpoints / h_i)^-S and
+// S = 1 / (sqrt(chi + 1e-8) + 0.05), chi = std / mean of the neighbours'
+// pressures (Eqs. DWBAP_w, DWBAP_S).  Hierarchical candidates: second
+// derivatives from the neighbours' second derivatives; first derivatives
+// from the plane through the cell averages of the remainder u - q_i (q_i:
+// the cell's quadratic part with limited second derivatives) over the cell
+// and each pair of neighbours, a pair weighing the mean of its two
+// neighbours' weights.  One thread per cell (cell order); the indicator
+// needs the neighbours' density polynomials only, and the full neighbour
+// data is read for limited cells alone.
+struct LimArgs {
+    int nt, nf;
+    const int32_t* own;
+    const int32_t* nbr;
+    const int32_t* cface;
+    const int32_t* nbc;   // [3][nt] face neighbour per slot (the cell itself: boundary)
+    const double* a0c;    // [3][5][nt] averages over the neighbour of the cell's basis
+    const double* gpd;
+    const double* cgeo;
+    const double* W;
+    const double* X;
+    double* Xout;
+    double gamma, threshold;
+    int all_quadratic;
+    int32_t* count;
+};
+
+__device__ __forceinline__ double dwbap_dev(const double* u, const double* w, int n) {
+    double s = 0.0;
+    for (int q = 0; q < n; ++q) s += w[q] * atan(u[q]);
+    return tan(s);
+}
+
+__global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
+    const int i = xcd_row();
+    if (i >= a.nt) return;
+    const int nt = a.nt;
+    const double ihi = a.cgeo[i], hi = 1.0 / ihi;
+    // second moments of cell i about its centroid, in units of h_i^2
+    const double mxx = a.cgeo[nt + i], mxy = a.cgeo[2 * nt + i], myy = a.cgeo[3 * nt + i];
+    // stencil: interior neighbours; dc = (r_j - r_i) / h_i
+    int nb[3], slot[3];
+    double dc[3][2];
+    int J = 0;
+    for (int s = 0; s < 3; ++s) {
+        const int j = a.nbc[(int64_t)s * nt + i];
+        if (j == i) continue;
+        nb[J] = j;
+        slot[J] = s;
+        dc[J][0] = a.a0c[((int64_t)s * 5 + 0) * nt + i];
+        dc[J][1] = a.a0c[((int64_t)s * 5 + 1) * nt + i];
+        ++J;
+    }
+    const bool boundary = J < 3;
+    const int ki = (boundary && !a.all_quadratic) ? 1 : 2;
+    double Xi[4][5], Wi[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        Wi[v] = a.W[(int64_t)v * nt + i];
+#pragma unroll
+        for (int l = 0; l < 5; ++l) Xi[v][l] = a.X[(int64_t)(v * 5 + l) * nt + i];
+    }
+    bool limit = false;
+    if (J > 0) {
+        // shock indicator on the density
+        const double own = Wi[0] - 0.5 * mxx * Xi[0][2] - mxy * Xi[0][3] - 0.5 * myy * Xi[0][4];
+        double num = 0.0, umax = Wi[0];
+        for (int n = 0; n < J; ++n) {
+            const int j = nb[n];
+            const double ihj = a.cgeo[j];
+            const double dx = -dc[n][0] * hi * ihj, dy = -dc[n][1] * hi * ihj;   // (r_i - r_j) / h_j
+            const double mxj = a.cgeo[nt + j], mxyj = a.cgeo[2 * nt + j], myj = a.cgeo[3 * nt + j];
+            double vj = a.W[j];
+            const double phi[5] = {dx, dy, 0.5 * (dx * dx - mxj), dx * dy - mxyj, 0.5 * (dy * dy - myj)};
+#pragma unroll
+            for (int l = 0; l < 5; ++l) vj += a.X[(int64_t)l * nt + j] * phi[l];
+            num += fabs(own - vj);
+            umax = fmax(umax, a.W[j]);
+        }
+        const double hk = ki == 2 ? hi * sqrt(hi) : hi;   // h_i^((k+1)/2)
+        const double IS = num / (J * hk * umax);
+        limit = IS >= a.threshold;
+    }
+    if (!limit) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int l = 0; l < 5; ++l) a.Xout[(int64_t)(v * 5 + l) * nt + i] = Xi[v][l];
+        return;
+    }
+    atomicAdd(a.count, 1);
+    // midpoints of the interior faces, relative to r_i, in units of h_i
+    double mid[3][2];
+    int nm = 0;
+    for (int k = 0; k < 3; ++k) {
+        const int cf = a.cface[(int64_t)k * nt + i];
+        const int f = cf >= 0 ? cf : ~cf;
+        const int side = cf >= 0 ? 0 : 1;
+        if ((side == 0 ? a.nbr[f] : a.own[f]) < 0) continue;
+        const int64_t nf = a.nf;
+        mid[nm][0] = 0.5 * (a.gpd[(2 * side) * nf + f] + a.gpd[(4 + 2 * side) * nf + f]);
+        mid[nm][1] = 0.5 * (a.gpd[(2 * side + 1) * nf + f] + a.gpd[(4 + 2 * side + 1) * nf + f]);
+        ++nm;
+    }
+    // weights
+    double p[3], pbar = 0.0;
+    for (int n = 0; n < J; ++n) {
+        const int j = nb[n];
+        const double r = a.W[j], mu = a.W[(int64_t)nt + j], mv = a.W[(int64_t)2 * nt + j], E = a.W[(int64_t)3 * nt + j];
+        p[n] = (a.gamma - 1.0) * (E - 0.5 * (mu * mu + mv * mv) / r);
+        pbar += p[n];
+    }
+    pbar /= J;
+    double var = 0.0;
+    for (int n = 0; n < J; ++n) var += (p[n] - pbar) * (p[n] - pbar);
+    const double chi = sqrt(var / J) / pbar;
+    const double S = 1.0 / (sqrt(chi + 1e-8) + 0.05);
+    double w[4], wsum = 0.0;
+    for (int q = 0; q <= J; ++q) {
+        const double cx = q == 0 ? 0.0 : dc[q - 1][0], cy = q == 0 ? 0.0 : dc[q - 1][1];
+        double D = 0.0;
+        for (int m = 0; m < nm; ++m) D += hypot(cx - mid[m][0], cy - mid[m][1]);
+        w[q] = pow(D / nm, -S);
+        wsum += w[q];
+    }
+    for (int q = 0; q <= J; ++q) w[q] /= wsum;
+    double Xl[4][5];
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int l = 0; l < 5; ++l) Xl[v][l] = Xi[v][l];
+    double u[4];
+    if (ki == 2) {
+        double h2[3];
+        for (int n = 0; n < J; ++n) h2[n] = a.cgeo[nb[n]] * a.cgeo[nb[n]];   // 1 / h_j^2
+        for (int v = 0; v < 4; ++v)
+            for (int l = 0; l < 3; ++l) {
+                u[0] = Xi[v][2 + l] * ihi * ihi;
+                for (int n = 0; n < J; ++n) u[n + 1] = a.X[(int64_t)(v * 5 + 2 + l) * nt + nb[n]] * h2[n];
+                Xl[v][2 + l] = dwbap_dev(u, w, J + 1) * hi * hi;
+            }
+    }
+    // first derivatives: plane gradients through remainder averages
+    double rem[3][4];
+    for (int n = 0; n < J; ++n) {
+        const int64_t b = (int64_t)slot[n] * 5;
+        const double a3 = a.a0c[(b + 2) * nt + i], a4 = a.a0c[(b + 3) * nt + i], a5 = a.a0c[(b + 4) * nt + i];
+        for (int v = 0; v < 4; ++v)
+            rem[n][v] = (a.W[(int64_t)v * nt + nb[n]] - Wi[v]) - (Xl[v][2] * a3 + Xl[v][3] * a4 + Xl[v][4] * a5);
+    }
+    double w1[4];
+    w1[0] = w[0];
+    for (int n = 0; n < J; ++n) w1[n + 1] = 0.5 * (w[n + 1] + w[(n + 1) % J + 1]);
+    double gx[3][4], gy[3][4];
+    for (int n = 0; n < J; ++n) {
+        const int m2 = (n + 1) % J;
+        const double a11 = dc[n][0], a12 = dc[n][1], a21 = dc[m2][0], a22 = dc[m2][1];
+        const double det = a11 * a22 - a12 * a21;
+        for (int v = 0; v < 4; ++v) {
+            if (J < 2 || fabs(det) < 1e-12) {
+                gx[n][v] = Xi[v][0];
+                gy[n][v] = Xi[v][1];
+            } else {
+                gx[n][v] = (a22 * rem[n][v] - a12 * rem[m2][v]) / det;
+                gy[n][v] = (a11 * rem[m2][v] - a21 * rem[n][v]) / det;
+            }
+        }
+    }
+    for (int v = 0; v < 4; ++v) {
+        u[0] = Xi[v][0] * ihi;
+        for (int n = 0; n < J; ++n) u[n + 1] = gx[n][v] * ihi;
+        Xl[v][0] = dwbap_dev(u, w1, J + 1) * hi;
+        u[0] = Xi[v][1] * ihi;
+        for (int n = 0; n < J; ++n) u[n + 1] = gy[n][v] * ihi;
+        Xl[v][1] = dwbap_dev(u, w1, J + 1) * hi;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int l = 0; l < 5; ++l) a.Xout[(int64_t)(v * 5 + l) * nt + i] = Xl[v][l];
+}
+
 static inline void check_launch(int kc) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) throw LaunchError{e, kc_names[kc]};
@@ -1441,6 +1628,31 @@ void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn) {
     const int nt = m->d.nt;
     PROFB(KC_UPDATE, (double)nt * (12.0 + 8.0 + 64.0 + 3 * 32.0), hipLaunchKernelGGL(k_update, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.nf,
                                        m->d.cface, m->d.area, W, F, Wn, m->prm.gamma, m->w.counters + 1));
+}
+
+void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int32_t* count) {
+    LimArgs a;
+    a.nt = m->d.nt;
+    a.nf = m->d.nf;
+    a.own = m->d.own;
+    a.nbr = m->d.nbr;
+    a.cface = m->d.cface;
+    a.nbc = m->d.nbc;
+    a.a0c = m->d.a0c;
+    a.gpd = m->d.gpd;
+    a.cgeo = m->d.cgeo;
+    a.W = W;
+    a.X = X;
+    a.Xout = Xout;
+    a.gamma = m->prm.gamma;
+    a.threshold = threshold;
+    a.all_quadratic = m->prm.all_quadratic;
+    a.count = count;
+    // bytes of the common case (cell not limited): own W, X and moments, its
+    // neighbour slots and offsets; per neighbour its density polynomial and
+    // geometry; X written
+    const double by = (double)a.nt * (4 * 8.0 + 20 * 8.0 + 32.0 + 12.0 + 6 * 8.0 + 3 * (8.0 + 5 * 8.0 + 4 * 8.0) + 20 * 8.0);
+    PROFB(KC_LIMIT, by, hipLaunchKernelGGL(k_limit, dim3(nblocks(a.nt)), dim3(TPB), 0, m->stream, a));
 }
 
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out) {
