@@ -959,6 +959,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     w.nblk_red = std::max(1, std::min(1024, (n + 255) / 256));
     w.partial = dev_alloc<double>(m, (size_t)w.nblk_red * (MAXM + 1) * NC);
     w.npart = dev_alloc<double>(m, (size_t)NC * (((size_t)n * 10 + 255) / 256 + 1));
+    w.dpart = dev_alloc<double>(m, (size_t)FUSED_DOTS_MAX * NC * (std::max<size_t>((n + 255) / 256, 2048) + 1));
     {
         std::vector<double> ones((size_t)(MAXM + 1) * NC, 1.0);
         w.ones = dev_upload(m, ones);
@@ -1027,17 +1028,28 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
     double* vk = w.V + (int64_t)k * vs;
     double* vk1 = w.V + (int64_t)(k + 1) * vs;
     const double* sk = &ks->scale[k][0];
+    const bool fused = k + 1 <= FUSED_DOTS_MAX;
     if (m->prm.precision == GKS_MIXED) {
         float* zk = w.Z + (int64_t)k * vs;
         launch_mx_precond(m, vk, sk, zk, gate);
-        launch_spmv64_f32x(m, zk, w.w, gate);
+        if (fused)
+            launch_spmv64_f32x_dots(m, zk, w.w, w.V, vs, k + 1, &ks->scale[0][0], &ks->h1[0][0], gate);
+        else
+            launch_spmv64_f32x(m, zk, w.w, gate);
     } else {
         launch_ilu(m, vk, sk, w.t1, w.t2, gate);
-        launch_spmv64(m, w.t2, nullptr, w.w, gate);
+        if (fused)
+            launch_spmv64_dots(m, w.t2, w.w, w.V, vs, k + 1, &ks->scale[0][0], &ks->h1[0][0], gate);
+        else
+            launch_spmv64(m, w.t2, nullptr, w.w, gate);
     }
-    launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0], gate);
-    launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, gate);
-    launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0], gate);
+    if (fused) {
+        launch_axpy_dots(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, &ks->h2[0][0], gate);
+    } else {
+        launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0], gate);
+        launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, gate);
+        launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0], gate);
+    }
     launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, gate, ks->sq);
     launch_ctl(m, 2);
 }

@@ -131,6 +131,7 @@ struct Work {
     float* df = nullptr;          // [n+1][CB] mixed inner sweeps: correction
     float* bf = nullptr;          // [n+1][CB] mixed inner sweeps: FP32 right-hand side
     double* npart = nullptr;      // per-block partial sums of the fused norms: [4][blocks of 10 n threads]
+    double* dpart = nullptr;      // per-block partial dots of the fused Gram-Schmidt passes
     float* Xp = nullptr;          // [n][CB] solution of the step before the last (FP32)
     float* Xpp = nullptr;         // [n][CB] the one before that (FP32)
     double* w = nullptr;          // [n+1][CB]
@@ -216,6 +217,16 @@ void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, i
                         const double* scale, double* out, const int32_t* gate = nullptr);
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
                  const double* w, double* out, const int32_t* gate = nullptr, double* sq_out = nullptr);
+// Fused Gram-Schmidt passes for nvec <= FUSED_DOTS_MAX basis vectors:
+// y = K x together with out = scale .* (V^T y), and the update out = w - V h
+// together with dots_out = scale .* (V^T out).
+constexpr int FUSED_DOTS_MAX = 8;
+void launch_spmv64_dots(gks_mesh* m, const double* x, double* y, const double* V, int64_t vstride, int nvd,
+                        const double* scale, double* out, const int32_t* gate = nullptr);
+void launch_spmv64_f32x_dots(gks_mesh* m, const float* x, double* y, const double* V, int64_t vstride, int nvd,
+                             const double* scale, double* out, const int32_t* gate = nullptr);
+void launch_axpy_dots(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
+                      const double* w, double* out, double* dots_out, const int32_t* gate = nullptr);
 // nvec_dev: when non-null the number of vectors is min(nvec, *nvec_dev)
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);

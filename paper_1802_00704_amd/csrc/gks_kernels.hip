@@ -22,7 +22,7 @@ const char* kc_names[NPROF] = {"rhs",       "spmv",       "spmv_resid", "ilu_fwd
                                "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "limit", "", "", ""};
 
 constexpr int TPB = 256;          // threads per block of the streaming kernels
-constexpr int RED_CHUNK = 8;      // vectors per block of the dot kernel
+constexpr int RED_CHUNK = FUSED_DOTS_MAX;   // vectors per block of the dot kernels
 
 static inline int nblocks(int64_t n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
 // grid of the Gram-Schmidt update (grid-stride beyond): 8 blocks per CU
@@ -201,6 +201,125 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict
         }
     }
     if (RESID && partial) block_sumsq4(sq, partial);
+}
+
+// Per-column dot products d[j][c] (j < nj <= RED_CHUNK) of a thread, reduced
+// over the block in a fixed order to partial[(j * NC + c) * gridDim.x +
+// blockIdx.x].  Every thread of the block must call it.
+__device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int nj, double* __restrict__ partial) {
+    __shared__ double sh[RED_CHUNK * NC][TPB / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            double v = d[j][c];
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) sh[j * NC + c][wid] = v;
+        }
+    __syncthreads();
+    if (threadIdx.x < nj * NC) {
+        double t = 0.0;
+#pragma unroll
+        for (int q = 0; q < TPB / 64; ++q) t += sh[threadIdx.x][q];
+        const int j = threadIdx.x / NC, c = threadIdx.x % NC;
+        partial[((int64_t)j * NC + c) * gridDim.x + blockIdx.x] = t;
+    }
+}
+
+// y = K x (FP64 K) and, in the same pass, the first Gram-Schmidt products
+// V_j . y for j < nvd <= RED_CHUNK (block partials to dpart).
+template <typename XT>
+__global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* __restrict__ val,
+                                                   const int32_t* __restrict__ col, const XT* __restrict__ x,
+                                                   double* __restrict__ y, const double* __restrict__ V,
+                                                   int64_t vstride, int nvd, double* __restrict__ dpart,
+                                                   const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
+    const int i = xcd_row();
+    double d[RED_CHUNK][NC];
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) d[j][c] = 0.0;
+    if (i < n) {
+        double acc[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+#pragma unroll
+        for (int s = 0; s < KW; ++s) {
+            const int j = col[(int64_t)s * n + i];
+            const XT* xj = x + (int64_t)j * CB;
+            double xv[CB];
+#pragma unroll
+            for (int q = 0; q < CB; ++q) xv[q] = (double)xj[q];
+            double blk[25];
+            load_block(val, np, s, i, blk);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NB; ++r)
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) acc[c * NB + r] += blk[r * NB + q] * xv[c * NB + q];
+        }
+        double* yi = y + (int64_t)i * CB;
+#pragma unroll
+        for (int q = 0; q < CB; ++q) yi[q] = acc[q];
+#pragma unroll
+        for (int j = 0; j < RED_CHUNK; ++j) {
+            if (j < nvd) {
+                const double* vi = V + (int64_t)j * vstride + (int64_t)i * CB;
+#pragma unroll
+                for (int c = 0; c < NC; ++c)
+#pragma unroll
+                    for (int l = 0; l < NB; ++l) d[j][c] += vi[c * NB + l] * acc[c * NB + l];
+            }
+        }
+    }
+    block_dots(d, nvd, dpart);
+}
+
+// out = w - sum_j h_j[c] scale_j[c] V_j and, in the same pass, the second
+// Gram-Schmidt products V_j . out for j < nvec <= RED_CHUNK (block partials
+// to dpart).  Grid-stride over 16-byte groups as k_axpy; out may alias w.
+__global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                                   const double* __restrict__ h, const double* __restrict__ scale,
+                                                   const double* w, double* out, double* __restrict__ dpart,
+                                                   const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
+    double d[RED_CHUNK][NC];
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) d[j][c] = 0.0;
+    const int64_t npair = (int64_t)n * 10;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npair; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = t / 10;
+        const int p = (int)(t - i * 10);
+        const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
+        const int64_t off = i * CB + 2 * p;
+        const double2 w2 = *reinterpret_cast<const double2*>(w + off);
+        double a0 = w2.x, a1 = w2.y;
+        double2 vv[RED_CHUNK];
+#pragma unroll
+        for (int j = 0; j < RED_CHUNK; ++j) {
+            if (j < nvec) {
+                vv[j] = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
+                a0 -= h[j * NC + c0] * scale[j * NC + c0] * vv[j].x;
+                a1 -= h[j * NC + c1] * scale[j * NC + c1] * vv[j].y;
+            }
+        }
+        *reinterpret_cast<double2*>(out + off) = make_double2(a0, a1);
+#pragma unroll
+        for (int j = 0; j < RED_CHUNK; ++j) {
+            if (j < nvec) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) d[j][c] += (c == c0 ? vv[j].x * a0 : 0.0) + (c == c1 ? vv[j].y * a1 : 0.0);
+            }
+        }
+    }
+    block_dots(d, nvec, dpart);
 }
 
 // ------------------------------------------------------------------ BILU(0) sweeps
@@ -1377,6 +1496,40 @@ void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* g
     const int n = m->d.n;
     PROFB(KC_SPMV, n * (KW * 25.0 * 8 + KW * 4.0 + VB / 2 + VB), hipLaunchKernelGGL((k_spmv<double, float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
                                          m->d.Kval, m->d.Kcol, x, nullptr, nullptr, y, gate));
+}
+
+// y = K x with the products V_j . y (j < nvd <= RED_CHUNK) reduced to
+// out[j * NC + c] * scale[j * NC + c]
+template <typename XT>
+static void spmv_dots(gks_mesh* m, const XT* x, double* y, const double* V, int64_t vstride, int nvd,
+                      const double* scale, double* out, const int32_t* gate) {
+    const int n = m->d.n;
+    const int nb = nblocks(n);
+    const double by = n * (KW * 25.0 * 8 + KW * 4.0 + (double)sizeof(XT) * CB + VB + nvd * VB);
+    PROFB(KC_SPMV, by, hipLaunchKernelGGL(k_spmv_dots<XT>, dim3(nb), dim3(TPB), 0, m->stream, n, m->d.np, m->d.Kval,
+                                          m->d.Kcol, x, y, V, vstride, nvd, m->w.dpart, gate));
+    PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(nvd * NC), dim3(TPB), 0, m->stream, nvd * NC, nb, m->w.dpart,
+                                      scale, out, gate));
+}
+
+void launch_spmv64_dots(gks_mesh* m, const double* x, double* y, const double* V, int64_t vstride, int nvd,
+                        const double* scale, double* out, const int32_t* gate) {
+    spmv_dots<double>(m, x, y, V, vstride, nvd, scale, out, gate);
+}
+
+void launch_spmv64_f32x_dots(gks_mesh* m, const float* x, double* y, const double* V, int64_t vstride, int nvd,
+                             const double* scale, double* out, const int32_t* gate) {
+    spmv_dots<float>(m, x, y, V, vstride, nvd, scale, out, gate);
+}
+
+void launch_axpy_dots(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
+                      const double* w, double* out, double* dots_out, const int32_t* gate) {
+    const int n = m->d.n;
+    const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));
+    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy_dots, dim3(nb), dim3(TPB), 0, m->stream, n, V, vstride,
+                                                                   nvec, h, scale, w, out, m->w.dpart, gate));
+    PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(nvec * NC), dim3(TPB), 0, m->stream, nvec * NC, nb, m->w.dpart,
+                                      scale, dots_out, gate));
 }
 
 void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate, double* sq_out) {
