@@ -51,6 +51,12 @@ def workload(name: str):
         W = gi.density_advection_ic(m)
         desc = "density advection, periodic JSS 512x512 on [0,2]^2, 524,288 triangles, CFL 0.5, CLS tol 1e-10"
         return m, W, desc, {}
+    if name == "acoustic_pulse_1m":
+        m = gi.jss_mesh(708, 708, 6, Lx=1.0, Ly=1.0)
+        W = gi.acoustic_pulse_ic(m)
+        desc = ("acoustic pressure pulse (amplitude 0.01, half width 0.04), periodic JSS 708x708 on [0,1]^2, "
+                "1,002,528 triangles, CFL 0.5, CLS tol 1e-10")
+        return m, W, desc, {}
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -70,6 +76,11 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
         W = gi.shock_vortex_ic(m)
         sample = "shock-vortex JSS 100x50 (10,000 triangles), same family at 10x coarser h"
         prm = scheme.Params(fallback=True)
+    elif name == "acoustic_pulse_1m":
+        m = gi.jss_mesh(71, 71, 6, Lx=1.0, Ly=1.0)
+        W = gi.acoustic_pulse_ic(m)
+        sample = "acoustic pulse JSS 71x71 (10,082 triangles), same family at 10x coarser h"
+        prm = scheme.Params()
     else:
         m = gi.jss_mesh(64, 64, 2)
         W = gi.density_advection_ic(m)
@@ -203,7 +214,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="shock_vortex_1m", choices=["shock_vortex_1m", "advection_512"])
+    ap.add_argument("--workload", default="shock_vortex_1m",
+                    choices=["shock_vortex_1m", "advection_512", "acoustic_pulse_1m"])
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")

@@ -232,6 +232,22 @@ def density_advection_exact(mesh: Mesh, t: float, **kw) -> np.ndarray:
     return density_advection_ic(mesh, t=t, **kw)
 
 
+def acoustic_pulse_ic(mesh: Mesh, gamma: float = 1.4, amp: float = 0.01, half_width: float = 0.04,
+                      center=(0.5, 0.5)) -> np.ndarray:
+    """Cell averages [4, nt] of the acoustic pressure pulse (paper section
+    4.5): rho = 1, u = v = 0, p = 1 + amp * exp(-alpha eta^2) with
+    eta = |x - center| and alpha = ln 2 / half_width^2."""
+    alpha = math.log(2.0) / half_width ** 2
+    cx, cy = center
+
+    def p_fn(x, y):
+        return (1.0 + amp * np.exp(-alpha * ((x - cx) ** 2 + (y - cy) ** 2)))[None]
+
+    p = cell_average(mesh, p_fn)[0]
+    rho = np.ones_like(p)
+    return prim_to_cons(rho, np.zeros_like(p), np.zeros_like(p), p, gamma)
+
+
 def shock_vortex_states(gamma: float = 1.4, mach: float = 1.1):
     """Pre-shock (rho, u, v, p) = (1, Ma sqrt(gamma), 0, 1) and the post-shock
     state from the Rankine-Hugoniot relations of a stationary normal shock."""
