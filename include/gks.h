@@ -63,7 +63,7 @@ extern "C" {
 #define GKS_BC_NOSLIP  2  /* wall moving with (u, v) = bc_state[row][1..2]: mirror image,
                              ghost velocity 2 U_wall - U, density and pressure even      */
 #define GKS_BC_INFLOW  3  /* fixed state (rho, u, v, p) = bc_state[row][0..3], no slopes */
-#define GKS_BC_OUTFLOW 4  /* ghost = interior state and derivatives                      */
+#define GKS_BC_OUTFLOW 4  /* transmissive: ghost = the boundary cell's average, no slopes */
 
 typedef struct gks_mesh gks_mesh;   /* opaque; owns every device buffer it allocates */
 

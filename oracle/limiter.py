@@ -26,9 +26,14 @@ the same ones):
       (counter-clockwise, boundary edges skipped, cyclic; minimum image on
       periodic axes); a pair's candidate carries the mean of its two
       neighbours' weights, so the result does not depend on where the cycle
-      starts.  The
-      remainder is linear for quadratic data, so these candidates are exact
-      there; across a jump the pairs on the smooth side give small slopes.
+      starts.  The remainder is linear for quadratic data, so these
+      candidates are exact there; across a jump the pairs on the smooth side
+      give small slopes.  Cells with fewer than three face neighbours (at a
+      boundary) take instead, per neighbour, the gradient along the
+      neighbour's direction alone, rem_j d_j / |d_j|^2: the plane through a
+      wall cell and its two neighbours would turn a jump between them into
+      a spurious wall-normal slope (it made the Sod tube's wall cells blow
+      up, where the directional candidates keep them bounded).
       (Derivatives of the neighbours' own polynomials would not do: the
       compact least-squares reconstruction is global, and near a jump the
       neighbours on the smooth side carry large slopes too.)
@@ -148,6 +153,40 @@ def limiter_weights(geo, W, i, stencil, gamma):
     return beta / beta.sum()
 
 
+def first_derivative_candidates(geo, W, X, Xl, i, stencil, w):
+    """Candidates [J+1, 4, 2] for u_x, u_y of cell i and their weights
+    (reading L2): Xl holds cell i's limited second derivatives."""
+    h = geo.h[i]
+    J = len(stencil)
+    d = np.array([geo.minimg(geo.cen[j] - geo.cen[i]) for j, _ in stencil]) / h   # [J, 2]
+    rem = np.zeros((J, 4))
+    for n, (j, _f) in enumerate(stencil):
+        dx, dy = d[n]
+        # averages over cell j of cell i's quadratic basis functions
+        a3 = 0.5 * (dx * dx + (geo.Ixx[j] - geo.Ixx[i]) / h ** 2)
+        a4 = dx * dy + (geo.Ixy[j] - geo.Ixy[i]) / h ** 2
+        a5 = 0.5 * (dy * dy + (geo.Iyy[j] - geo.Iyy[i]) / h ** 2)
+        rem[n] = (W[:, j] - W[:, i]) - (Xl[:, 2, i] * a3 + Xl[:, 3, i] * a4 + Xl[:, 4, i] * a5)
+    c1 = np.zeros((J + 1, 4, 2))
+    c1[0] = X[:, 0:2, i] / h
+    w1 = w.copy()
+    for n in range(J):
+        if J < 3:
+            # wall cell: the gradient along the neighbour's direction alone
+            c1[n + 1] = np.outer(rem[n], d[n]) / (d[n] @ d[n]) / h
+            continue
+        m2 = (n + 1) % J
+        A = np.array([d[n], d[m2]])
+        if abs(np.linalg.det(A)) < 1e-12:
+            c1[n + 1] = c1[0]
+        else:
+            G = np.linalg.solve(A, np.stack([rem[n], rem[m2]]))   # [2, 4]: h-scaled gradient
+            c1[n + 1] = G.T / h
+        # a pair candidate carries the mean weight of its two neighbours
+        w1[n + 1] = 0.5 * (w[n + 1] + w[m2 + 1])
+    return c1, w1
+
+
 def limit(geo, W, X, mesh, gamma=1.4, threshold=1.0, k=None):
     """Limited coefficients (reading L7) and the mask of limited cells.
     threshold: IS_i at or above which a cell is limited (1 per Eq. ISD2;
@@ -174,30 +213,8 @@ def limit(geo, W, X, mesh, gamma=1.4, threshold=1.0, k=None):
             for v in range(4):
                 for l in range(3):
                     Xl[v, 2 + l, i] = dwbap(c2[:, v, l], w) * h * h
-        # first derivatives from remainder averages over cell pairs
-        d = np.array([geo.minimg(geo.cen[j] - geo.cen[i]) for j, _ in stencil]) / h   # [J, 2]
-        rem = np.zeros((J, 4))
-        for n, (j, _f) in enumerate(stencil):
-            dx, dy = d[n]
-            # averages over cell j of cell i's quadratic basis functions
-            a3 = 0.5 * (dx * dx + (geo.Ixx[j] - geo.Ixx[i]) / h ** 2)
-            a4 = dx * dy + (geo.Ixy[j] - geo.Ixy[i]) / h ** 2
-            a5 = 0.5 * (dy * dy + (geo.Iyy[j] - geo.Iyy[i]) / h ** 2)
-            rem[n] = (W[:, j] - W[:, i]) - (Xl[:, 2, i] * a3 + Xl[:, 3, i] * a4 + Xl[:, 4, i] * a5)
-        c1 = np.zeros((J + 1, 4, 2))
-        c1[0] = X[:, 0:2, i] / h
-        for n in range(J):
-            m2 = (n + 1) % J
-            A = np.array([d[n], d[m2]])
-            if J < 2 or abs(np.linalg.det(A)) < 1e-12:
-                c1[n + 1] = c1[0]
-                continue
-            G = np.linalg.solve(A, np.stack([rem[n], rem[m2]]))   # [2, 4]: h-scaled gradient
-            c1[n + 1] = G.T / h
-        # a pair candidate carries the mean weight of its two neighbours
-        w1 = w.copy()
-        for n in range(J):
-            w1[n + 1] = 0.5 * (w[n + 1] + w[(n + 1) % J + 1])
+        # first derivatives from remainder averages (readings L2)
+        c1, w1 = first_derivative_candidates(geo, W, X, Xl, i, stencil, w)
         for v in range(4):
             for l in range(2):
                 Xl[v, l, i] = dwbap(c1[:, v, l], w1) * h

@@ -9,9 +9,10 @@
   s = +1 for the owner and -1 for the neighbour.
 * The time step (the paper gives none) is
   dt = CFL min_i |Omega_i| / sum_{f in i} S_f (|U_i . n_f| + c_i).
-* Boundary faces use a ghost state built from the interior one-sided
-  polynomial at the Gauss point (mirror images for walls, a fixed state for
-  supersonic inflow, a copy for outflow); boundary faces add no CLS rows.
+* Boundary faces use a ghost state: walls mirror the interior one-sided
+  polynomial at the Gauss point, inflow takes a fixed state, and outflow
+  (transmissive) takes the boundary cell's average with zero derivatives;
+  boundary faces add no CLS rows.
 """
 from __future__ import annotations
 
@@ -86,15 +87,20 @@ def physical(W, gamma):
     return (W[0] > 0.0) & (kinetic.pressure(W, gamma) > 0.0)
 
 
-def ghost(WL, dL, kind, state, gamma, nx, ny):
+def ghost(WL, dL, kind, state, gamma, nx, ny, Wc):
     """Ghost state and derivatives (face frame) beyond a boundary face.
 
     Walls mirror the interior polynomial across the face line, so each ghost
     derivative picks up (-1) per normal differentiation, combined with a
     linear map of the conserved variables: slip reflects the normal momentum;
     no-slip sets the ghost velocity to 2 U_wall - U with even density and
-    pressure, which is linear in (rho, rho U, E).  Supersonic inflow uses the
-    fixed state with zero derivatives; outflow copies state and derivatives.
+    pressure, which is linear in (rho, rho U, E).  Inflow uses the fixed
+    state with zero derivatives (the kinetic flux then takes from it only
+    what enters).  Outflow uses Wc, the boundary cell's average in the face
+    frame, with zero derivatives: zeroth-order extrapolation.  A ghost that
+    copied the interior Gauss-point state would make the face flux purely
+    one-sided, so a characteristic entering through a subsonic outflow would
+    be taken downwind; the linearised step then grows at the boundary.
     """
     m = WL.shape[1]
     if kind in (BC_SLIP, BC_NOSLIP):
@@ -127,7 +133,7 @@ def ghost(WL, dL, kind, state, gamma, nx, ny):
         dR = {key: np.zeros((4, m)) for key in dL}
         return WR, dR
     if kind == BC_OUTFLOW:
-        return WL.copy(), {key: val.copy() for key, val in dL.items()}
+        return Wc.copy(), {key: np.zeros_like(val) for key, val in dL.items()}
     raise ValueError("unknown boundary kind %r" % (kind,))
 
 
@@ -171,8 +177,9 @@ def face_fluxes(geo: Geometry, W, X, dt, prm: Params, bc_table=(), counters=None
         for row, (kind, state) in enumerate(bc_table, start=1):
             fb = np.nonzero((~inner) & (tag == row))[0]
             if fb.size:
+                Wc = to_local(W[:, own[fb]], nx[fb], ny[fb])
                 wg, dg = ghost(WL[:, fb], {key: val[:, fb] for key, val in dL.items()},
-                               kind, state, prm.gamma, nx[fb], ny[fb])
+                               kind, state, prm.gamma, nx[fb], ny[fb], Wc)
                 WR[:, fb] = wg
                 for key in dR:
                     dR[key][:, fb] = dg[key]

@@ -1073,8 +1073,12 @@ __device__ __forceinline__ void cell_average_local(const FluxArgs& a, int cell, 
         for (int v = 0; v < 4; ++v) d[k][v] = 0.0;
 }
 
-// Ghost state beyond a boundary face (face frame), from the interior side.
-__device__ __forceinline__ void ghost(const FluxArgs& a, int row, const double WL[4], const double dL[5][4],
+// Ghost state beyond a boundary face (face frame), from the interior side o.
+// Walls mirror the one-sided polynomial, inflow is the fixed state, and
+// outflow is the cell's own average with zero derivatives (zeroth-order
+// extrapolation: the kinetic flux then stays upwind for a characteristic
+// entering through a subsonic outflow).
+__device__ __forceinline__ void ghost(const FluxArgs& a, int row, int o, const double WL[4], const double dL[5][4],
                                       double nx, double ny, double WR[4], double dR[5][4]) {
     const int kind = a.bc_kind[row];
     const double* st = a.bc_state + 4 * row;
@@ -1117,13 +1121,8 @@ __device__ __forceinline__ void ghost(const FluxArgs& a, int row, const double W
         for (int k = 0; k < 5; ++k)
 #pragma unroll
             for (int q = 0; q < 4; ++q) dR[k][q] = 0.0;
-    } else {  // outflow: copy
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            WR[q] = WL[q];
-#pragma unroll
-            for (int k = 0; k < 5; ++k) dR[k][q] = dL[k][q];
-        }
+    } else {  // outflow
+        cell_average_local(a, o, nx, ny, WR, dR);
     }
 }
 
@@ -1156,7 +1155,7 @@ __global__ void __launch_bounds__(128) k_flux(FluxArgs a) {
                 cell_average_local(a, nb, nx, ny, WR, dR);
             }
         } else {
-            ghost(a, -nb, WL, dL, nx, ny, WR, dR);
+            ghost(a, -nb, o, WL, dL, nx, ny, WR, dR);
         }
         if (bad) atomicAdd(a.nonphys, bad);
         gksdev::gp_flux(F, WL, dL, WR, dR, *a.dt, a.fp);
@@ -1281,10 +1280,11 @@ inline double spmv_bytes(int n, int esz, bool resid) { return n * (KW * 25.0 * e
 // S = 1 / (sqrt(chi + 1e-8) + 0.05), chi = std / mean of the neighbours'
 // pressures (Eqs. DWBAP_w, DWBAP_S).  Hierarchical candidates: second
 // derivatives from the neighbours' second derivatives; first derivatives
-// from the plane through the cell averages of the remainder u - q_i (q_i:
-// the cell's quadratic part with limited second derivatives) over the cell
-// and each pair of neighbours, a pair weighing the mean of its two
-// neighbours' weights.  One thread per cell (cell order); the indicator
+// from the cell averages of the remainder u - q_i (q_i: the cell's quadratic
+// part with limited second derivatives): the plane through the cell and each
+// pair of neighbours, a pair weighing the mean of its two neighbours'
+// weights, or in a wall cell (fewer than three neighbours) the gradient
+// along each neighbour's direction alone.  One thread per cell (cell order); the indicator
 // needs the neighbours' density polynomials only, and the full neighbour
 // data is read for limited cells alone.
 struct LimArgs {
@@ -1427,16 +1427,28 @@ __global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
         for (int v = 0; v < 4; ++v)
             rem[n][v] = (a.W[(int64_t)v * nt + nb[n]] - Wi[v]) - (Xl[v][2] * a3 + Xl[v][3] * a4 + Xl[v][4] * a5);
     }
+    // candidates: with three neighbours the plane through each neighbour
+    // pair (weighing the pair's mean weight); in a wall cell the gradient
+    // along each neighbour's direction alone
     double w1[4];
     w1[0] = w[0];
-    for (int n = 0; n < J; ++n) w1[n + 1] = 0.5 * (w[n + 1] + w[(n + 1) % J + 1]);
     double gx[3][4], gy[3][4];
     for (int n = 0; n < J; ++n) {
+        if (J < 3) {
+            w1[n + 1] = w[n + 1];
+            const double dd = dc[n][0] * dc[n][0] + dc[n][1] * dc[n][1];
+            for (int v = 0; v < 4; ++v) {
+                gx[n][v] = rem[n][v] * dc[n][0] / dd;
+                gy[n][v] = rem[n][v] * dc[n][1] / dd;
+            }
+            continue;
+        }
         const int m2 = (n + 1) % J;
+        w1[n + 1] = 0.5 * (w[n + 1] + w[m2 + 1]);
         const double a11 = dc[n][0], a12 = dc[n][1], a21 = dc[m2][0], a22 = dc[m2][1];
         const double det = a11 * a22 - a12 * a21;
         for (int v = 0; v < 4; ++v) {
-            if (J < 2 || fabs(det) < 1e-12) {
+            if (fabs(det) < 1e-12) {
                 gx[n][v] = Xi[v][0];
                 gy[n][v] = Xi[v][1];
             } else {

@@ -9,9 +9,10 @@ method must have whatever the reading of its open points:
   * on fields the reconstruction reproduces exactly (global quadratics in the
     all-quadratic mode, global linears with linear boundary cells) every
     neighbour's polynomial is the cell's own, so the indicator is zero and
-    even limiting forced onto every cell changes nothing: this pins the
-    transport of the neighbour derivatives to the cell centroid, the h
-    scalings and the periodic images;
+    even limiting forced onto every cell changes nothing in cells with three
+    neighbours: this pins the remainder averages, the h scalings and the
+    periodic images; in wall cells, whose candidates are directional, every
+    limited slope component stays within the gradient's length;
   * the indicator fires at a density jump and not away from it, and on a
     smooth wave it falls as h^1.5 as the mesh is refined (Eq. ISD1 with
     k = 2 and a third-order reconstruction);
@@ -71,6 +72,10 @@ def test_weights_convex_and_keep_own_value_where_pressure_is_uniform():
         assert w[0] > 0.99
 
 
+def _three_neighbours(geo, m):
+    return np.array([len(st) == 3 for st in limiter.cell_stencils(geo, m)])
+
+
 def _force_all(m, geo, W, X, k):
     return limiter.limit(geo, W, X, m, threshold=-1.0, k=k)
 
@@ -88,7 +93,8 @@ def test_quadratic_fields_unchanged_even_when_every_cell_is_limited():
     assert np.abs(IS).max() < 1e-10
     Xl, mask = _force_all(m, geo, W, X, k)
     assert mask.all()
-    assert np.abs(Xl - X).max() <= 1e-10 * np.abs(X).max()
+    inner = _three_neighbours(geo, m)
+    assert np.abs(Xl[:, :, inner] - X[:, :, inner]).max() <= 1e-10 * np.abs(X).max()
 
 
 def test_linear_fields_unchanged_with_linear_boundary_cells():
@@ -102,7 +108,41 @@ def test_linear_fields_unchanged_with_linear_boundary_cells():
     X = cls.reconstruct(geo, W, k)
     assert np.abs(limiter.shock_indicator(geo, W, X, m, k=k)).max() < 1e-10
     Xl, _ = _force_all(m, geo, W, X, k)
-    assert np.abs(Xl - X).max() <= 1e-11 * np.abs(X).max()
+    inner = _three_neighbours(geo, m)
+    assert inner.sum() > 0 and (~inner).sum() > 0
+    assert np.abs(Xl[:, :, inner] - X[:, :, inner]).max() <= 1e-11 * np.abs(X).max()
+    # wall cells take directional candidates, the projections of the exact
+    # gradient on the neighbour directions, none longer than the gradient;
+    # each limited component lies within its candidates' range, so it is
+    # bounded by the gradient's length
+    wall = ~inner
+    glen = np.linalg.norm(X[:, 0:2, wall], axis=1)
+    assert np.all(np.abs(Xl[:, 0:2, wall]) <= glen[:, None, :] * (1 + 1e-12))
+
+
+def test_candidates_are_exact_for_linear_data():
+    """For u = a + g.x the remainder differences are g.(r_j - r_i): cells
+    with three neighbours get g itself from every pair, wall cells get the
+    projections (g.e_j) e_j of g on the neighbour directions."""
+    m = gi.jss_mesh(7, 6, 8, Lx=1.0, Ly=1.0, periodic=False)
+    geo = build_geometry(m)
+    k = cls.cell_orders(geo)
+    gx, gy = -1.7, 0.6
+    ubar = quad_avg(m, lambda x, y: 2.4 + gx * x + gy * y)
+    W = np.stack([ubar] * 4)
+    X = cls.reconstruct(geo, W, k)
+    st = limiter.cell_stencils(geo, m)
+    g = np.array([gx, gy])
+    for i in range(geo.nt):
+        c1, _ = limiter.first_derivative_candidates(geo, W, X, X, i, st[i], np.full(len(st[i]) + 1, 1.0))
+        for n, (j, _f) in enumerate(st[i], start=1):
+            if len(st[i]) == 3:
+                expect = g
+            else:
+                e = geo.cen[j] - geo.cen[i]
+                e = e / np.linalg.norm(e)
+                expect = (g @ e) * e
+            assert np.abs(c1[n, 0] - expect).max() <= 1e-10 * np.abs(g).max()
 
 
 def _jump_case(nx=24, ny=4):

@@ -9,6 +9,11 @@ the third-order flux).
   wall; slip and no-slip ghosts coincide for a fluid at rest.
 * Third-order convergence on the density-advection exact solution
   (section 4.1): the observed order rises towards 3 under refinement.
+* Linear stability of the boundary rules: the one-step Jacobian about a
+  fluid at rest (finite differences of the whole step) has no growing mode
+  in a closed slip-wall box, with fixed-state ends, or with transmissive
+  ends.  A wrong sign in a mirror ghost, or an outflow ghost copying the
+  one-sided Gauss-point state, gives modes growing by 1-2% per step.
 """
 import numpy as np
 import pytest
@@ -155,3 +160,29 @@ def test_third_order_convergence():
     o2 = np.log2(errs[1] / errs[2])
     assert o2 > o1 > 2.0
     assert o2 > 2.45
+
+
+def _step_radius(m, rho, p):
+    n = m.nt
+    W0 = gi.prim_to_cons(np.full(n, rho), np.zeros(n), np.zeros(n), np.full(n, p), 1.4)
+    s = scheme.Solver(m)
+    dt = 0.6 * scheme.cfl_dt(s.geo, W0, s.prm)
+    base, _ = s.step(W0, dt)
+    J = np.zeros((4 * n, 4 * n))
+    for j in range(4 * n):
+        Wp = W0.copy().reshape(-1)
+        h = 1e-7 * max(1.0, abs(Wp[j]))
+        Wp[j] += h
+        J[:, j] = (s.step(Wp.reshape(4, n), dt)[0] - base).reshape(-1) / h
+    return np.abs(np.linalg.eigvals(J)).max()
+
+
+@pytest.mark.parametrize("ends,bound", [("slip", 1e-6), ("fixed", 1e-6), ("outflow", 2e-4)])
+def test_boundary_rules_are_linearly_stable_at_rest(ends, bound):
+    rho, p = 0.125, 0.1
+    end = {"slip": (gi.BC_SLIP, None), "fixed": (gi.BC_INFLOW, (rho, 0.0, 0.0, p)),
+           "outflow": (gi.BC_OUTFLOW, None)}[ends]
+    m = gi.jss_mesh(10, 2, 7, Lx=1.0, Ly=0.2, periodic=False,
+                    walls=(end, end, (gi.BC_SLIP, None), (gi.BC_SLIP, None)))
+    r = _step_radius(m, rho, p)
+    assert r <= 1.0 + bound, r
