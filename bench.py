@@ -226,7 +226,7 @@ def main():
                     help="requests of the serving stream to run after the throughput legs (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-limiter-leg", action="store_true",
-                    help="skip the extra run of the mixed form with the DWBAP limiter on")
+                    help="skip the extra runs of the mixed form with the DWBAP limiter on")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X only; multi-GPU runs are not part of this build "
@@ -245,21 +245,26 @@ def main():
               flush=True)
     head = forms[0]
     r = res[head]
-    # the DWBAP limiter (section 3.3) on the same workload, mixed form
+    # the DWBAP limiter (section 3.3) on the same workload, mixed form, in
+    # conserved and in characteristic variables (section 4.2)
     lim = None
     if not args.no_limiter_leg:
-        rl = run_form(m, W0, g.GKS_MIXED, args.steps, args.warmup, not args.no_profile, args.graphs, limiter=1)
-        pl = rl["profile"].get("limit") if rl["profile"] else None
-        lim = {"ms_per_step": rl["ms_per_step"], "value": rl["value"],
-               "limited_cells_per_step": rl["limited_cells_per_step"],
-               "krylov_iters_per_step": rl["krylov_iters_per_step"]}
-        if pl and pl["ms"] > 0:
-            lim["kernel"] = {"avg_launch_us": round(pl["ms"] * 1e3 / max(1, pl["launches"]), 2),
-                             "achieved_GBs": round(pl["bytes"] / (pl["ms"] * 1e-3) / 1e9, 1),
-                             "frac_of_hbm_peak": round(pl["bytes"] / (pl["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-                             "traffic": measured_traffic("limit")}
-        print("# mixed + limiter: %.4g cell-steps/s, %.3f ms/step, %.0f cells limited per step" %
-              (rl["value"], rl["ms_per_step"], rl["limited_cells_per_step"]), file=sys.stderr, flush=True)
+        lim = {}
+        for name, variables in (("conservative", g.LIMIT_CONSERVATIVE), ("characteristic", g.LIMIT_CHARACTERISTIC)):
+            rl = run_form(m, W0, g.GKS_MIXED, args.steps, args.warmup, not args.no_profile, args.graphs,
+                          limiter=variables)
+            pl = rl["profile"].get("limit") if rl["profile"] else None
+            leg = {"ms_per_step": rl["ms_per_step"], "value": rl["value"],
+                   "limited_cells_per_step": rl["limited_cells_per_step"],
+                   "krylov_iters_per_step": rl["krylov_iters_per_step"]}
+            if pl and pl["ms"] > 0:
+                leg["kernel"] = {"avg_launch_us": round(pl["ms"] * 1e3 / max(1, pl["launches"]), 2),
+                                 "achieved_GBs": round(pl["bytes"] / (pl["ms"] * 1e-3) / 1e9, 1),
+                                 "frac_of_hbm_peak": round(pl["bytes"] / (pl["ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                                 "traffic": measured_traffic("limit") if name == "conservative" else None}
+            lim[name] = leg
+            print("# mixed + limiter (%s variables): %.4g cell-steps/s, %.3f ms/step, %.0f cells limited per step" %
+                  (name, rl["value"], rl["ms_per_step"], rl["limited_cells_per_step"]), file=sys.stderr, flush=True)
     serving = serving_leg(args.serving_requests, args.serving_slots) if args.serving_requests > 0 else None
     if serving:
         print("# serving: %.4g cell-steps/s, step p50/p99 %.2f/%.2f ms, solve p50/p99 %.2f/%.2f ms" %

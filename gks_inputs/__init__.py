@@ -235,7 +235,7 @@ def density_advection_exact(mesh: Mesh, t: float, **kw) -> np.ndarray:
 def acoustic_pulse_ic(mesh: Mesh, gamma: float = 1.4, amp: float = 0.01, half_width: float = 0.04,
                       center=(0.5, 0.5)) -> np.ndarray:
     """Cell averages [4, nt] of the acoustic pressure pulse (paper section
-    4.5): rho = 1, u = v = 0, p = 1 + amp * exp(-alpha eta^2) with
+    4.4): rho = 1, u = v = 0, p = 1 + amp * exp(-alpha eta^2) with
     eta = |x - center| and alpha = ln 2 / half_width^2."""
     alpha = math.log(2.0) / half_width ** 2
     cx, cy = center

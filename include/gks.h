@@ -65,6 +65,10 @@ extern "C" {
 #define GKS_BC_INFLOW  3  /* fixed state (rho, u, v, p) = bc_state[row][0..3], no slopes */
 #define GKS_BC_OUTFLOW 4  /* transmissive: ghost = the boundary cell's average, no slopes */
 
+/* variables the limiter acts on (gks_params.limiter, gks_limit) */
+#define GKS_LIMIT_CONSERVATIVE   1
+#define GKS_LIMIT_CHARACTERISTIC 2
+
 typedef struct gks_mesh gks_mesh;   /* opaque; owns every device buffer it allocates */
 
 /* Mesh description.  Host arrays are copied at creation; the caller may free
@@ -116,11 +120,13 @@ typedef struct {
                                 adaptive (follows the first-cycle length of
                                 recent steps, re-capturing when it changes);
                                 k > 0 = exactly min(k, restart, max_iter)       */
-    int32_t limiter;         /* 1: gks_step limits the reconstruction with the
+    int32_t limiter;         /* GKS_LIMIT_CONSERVATIVE or _CHARACTERISTIC:
+                                gks_step limits the reconstruction with the
                                 DWBAP limiter of section 3.3 (Eqs. DWBAP,
                                 DWBAP_w, DWBAP_S) where the shock indicator of
-                                Eqs. ISD1-2 reaches 1, before the fluxes; the
-                                solver keeps the unlimited X.  0: off          */
+                                Eqs. ISD1-2 reaches 1, before the fluxes, in
+                                those variables; the solver keeps the
+                                unlimited X.  0: off                          */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -213,13 +219,17 @@ int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, d
  * shock indicator IS_i (Eq. ISD1) is at least `threshold` (Eq. ISD2 uses 1)
  * get their derivatives replaced by the biased average of Eq. DWBAP over
  * their own value and candidates from their face neighbours, with the
- * weights of Eqs. DWBAP_w and DWBAP_S; the other cells are copied.  W
- * [4][nt] and X, Xout [4][5][nt] are device arrays in the caller's cell
- * order (the layouts of gks_step and gks_cls_reconstruct); Xout must not
- * alias X.  n_limited (host, may be NULL) receives the number of limited
- * cells.  Errors: GKS_EINVAL, GKS_EHIP. */
+ * weights of Eqs. DWBAP_w and DWBAP_S; the other cells are copied.
+ * variables: GKS_LIMIT_CONSERVATIVE limits each conserved variable;
+ * GKS_LIMIT_CHARACTERISTIC (the variant of section 4.2) limits the
+ * characteristic variables of the Euler equations along the cell's density
+ * gradient, at its average state, and maps them back.  W [4][nt] and X,
+ * Xout [4][5][nt] are device arrays in the caller's cell order (the layouts
+ * of gks_step and gks_cls_reconstruct); Xout must not alias X.  n_limited
+ * (host, may be NULL) receives the number of limited cells.
+ * Errors: GKS_EINVAL, GKS_EHIP. */
 int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold,
-              int32_t* n_limited);
+              int32_t variables, int32_t* n_limited);
 
 /* Apply the solve's preconditioner to four columns: Z = P(V), where P is
  * the BILU(0) factorisation of section 3.2 (form GKS_FP64: one forward and

@@ -3,7 +3,7 @@
 TEST INFRASTRUCTURE ONLY: imported by tests/, __graft_entry__.smoke() and
 bench.py's CPU-baseline leg, never by the library.
 
-Acoustic pressure pulse (section 4.5, Eq. cirPulseSolution): the linear
+Acoustic pressure pulse (section 4.4, Eq. cirPulseSolution): the linear
 acoustics solution of a Gaussian pressure perturbation at rest,
     p - p_inf = eps / (2 alpha) * int_0^inf exp(-xi^2 / (4 alpha))
                 cos(c xi t) J0(xi eta) xi d xi,

@@ -54,6 +54,15 @@ the same ones):
   L7  All cells are limited at once from the unlimited coefficients; the
       limited coefficients feed the flux, the solver keeps the unlimited ones.
   L8  Linear (boundary) cells keep X3..X5 = 0 and limit X1, X2.
+  L9  Limiting in characteristic variables (the variant of section 4.2):
+      each derivative's four candidates, one per conserved variable, are
+      mapped to characteristic variables with the left eigenvectors of the
+      Euler flux Jacobian along a direction n, at cell i's average state;
+      each characteristic field is limited by Eq. DWBAP with the same
+      weights; the result is mapped back with the right eigenvectors.  One
+      basis serves all five derivatives of the cell.  n is the direction of
+      cell i's unlimited density gradient (the normal of a shock or contact
+      through the cell), the x axis where that gradient vanishes.
 """
 from __future__ import annotations
 
@@ -153,6 +162,32 @@ def limiter_weights(geo, W, i, stencil, gamma):
     return beta / beta.sum()
 
 
+def characteristic_basis(Wc, gamma, n):
+    """Right eigenvectors [4, 4] (columns) of the Jacobian of the Euler flux
+    F(W) . n with respect to the conserved variables, at state Wc, for unit
+    n; eigenvalues u_n - c, u_n, u_n, u_n + c.  Columns: the acoustic wave
+    against n, the entropy wave, the shear wave, the acoustic wave along n."""
+    rho = Wc[0]
+    u, v = Wc[1] / rho, Wc[2] / rho
+    p = (gamma - 1.0) * (Wc[3] - 0.5 * rho * (u * u + v * v))
+    c = np.sqrt(gamma * p / rho)
+    H = (Wc[3] + p) / rho
+    nx, ny = n
+    un = u * nx + v * ny
+    ut = -u * ny + v * nx
+    return np.array([[1.0, 1.0, 0.0, 1.0],
+                     [u - c * nx, u, -ny, u + c * nx],
+                     [v - c * ny, v, nx, v + c * ny],
+                     [H - c * un, 0.5 * (u * u + v * v), ut, H + c * un]])
+
+
+def limiting_direction(X, i):
+    """Unit direction of cell i's unlimited density gradient (reading L9)."""
+    g = X[0, 0:2, i]
+    nrm = np.hypot(g[0], g[1])
+    return np.array([1.0, 0.0]) if nrm == 0.0 else g / nrm
+
+
 def first_derivative_candidates(geo, W, X, Xl, i, stencil, w):
     """Candidates [J+1, 4, 2] for u_x, u_y of cell i and their weights
     (reading L2): Xl holds cell i's limited second derivatives."""
@@ -187,11 +222,14 @@ def first_derivative_candidates(geo, W, X, Xl, i, stencil, w):
     return c1, w1
 
 
-def limit(geo, W, X, mesh, gamma=1.4, threshold=1.0, k=None):
+def limit(geo, W, X, mesh, gamma=1.4, threshold=1.0, k=None, variables="conservative"):
     """Limited coefficients (reading L7) and the mask of limited cells.
     threshold: IS_i at or above which a cell is limited (1 per Eq. ISD2;
     tests lower it to force limiting everywhere); k: cell orders (default:
-    linear boundary cells)."""
+    linear boundary cells); variables: "conservative" (reading L1) or
+    "characteristic" (reading L9)."""
+    if variables not in ("conservative", "characteristic"):
+        raise ValueError(variables)
     st = cell_stencils(geo, mesh)
     k = cell_orders(geo) if k is None else k
     IS = shock_indicator(geo, W, X, mesh, st, k)
@@ -204,18 +242,27 @@ def limit(geo, W, X, mesh, gamma=1.4, threshold=1.0, k=None):
         h = geo.h[i]
         J = len(stencil)
         w = limiter_weights(geo, W, i, stencil, gamma)
+        if variables == "characteristic":
+            R = characteristic_basis(W[:, i], gamma, limiting_direction(X, i))
+            Lft = np.linalg.inv(R)
+
+        def limited(cands, wts):
+            # cands [J+1, 4]: one candidate vector of conserved variables per row
+            if variables == "conservative":
+                return np.array([dwbap(cands[:, q], wts) for q in range(4)])
+            ch = cands @ Lft.T
+            return R @ np.array([dwbap(ch[:, q], wts) for q in range(4)])
+
         # second derivatives u_xx, u_xy, u_yy: own and the neighbours'
         if k[i] == 2:
             c2 = np.zeros((J + 1, 4, 3))
             c2[0] = X[:, 2:5, i] / h ** 2
             for n, (j, _f) in enumerate(stencil, start=1):
                 c2[n] = X[:, 2:5, j] / geo.h[j] ** 2
-            for v in range(4):
-                for l in range(3):
-                    Xl[v, 2 + l, i] = dwbap(c2[:, v, l], w) * h * h
+            for l in range(3):
+                Xl[:, 2 + l, i] = limited(c2[:, :, l], w) * h * h
         # first derivatives from remainder averages (readings L2)
         c1, w1 = first_derivative_candidates(geo, W, X, Xl, i, stencil, w)
-        for v in range(4):
-            for l in range(2):
-                Xl[v, l, i] = dwbap(c1[:, v, l], w1) * h
+        for l in range(2):
+            Xl[:, l, i] = limited(c1[:, :, l], w1) * h
     return Xl, mask

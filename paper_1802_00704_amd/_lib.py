@@ -15,6 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgks.so")
 
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EHIP, GKS_ENOCONV, GKS_ENONPHYS = 0, -1, -2, -3, -4, -5
+LIMIT_CONSERVATIVE, LIMIT_CHARACTERISTIC = 1, 2
 GKS_FP64, GKS_MIXED = 0, 1
 GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM = 0, 1
 
@@ -101,7 +102,7 @@ def lib():
         L.gks_step.argtypes = [vp, vp, C.c_double, C.POINTER(C.c_double), C.POINTER(SolveInfo)]
         L.gks_step.restype = C.c_int
         L.gks_faces.argtypes = [vp, vp, vp]
-        L.gks_limit.argtypes = [vp, vp, vp, vp, C.c_double, C.POINTER(C.c_int32)]
+        L.gks_limit.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_int32)]
         L.gks_limit.restype = C.c_int
         L.gks_apply_precond.argtypes = [vp, vp, vp, C.c_int]
         L.gks_apply_precond.restype = C.c_int
@@ -269,14 +270,16 @@ class GksMesh:
         _check(code, self._h)
         return used.value, info.as_dict()
 
-    def limit(self, W, X, threshold: float = 1.0, Xout=None):
-        """(Xout, n_limited): X limited by the DWBAP limiter (gks_limit)."""
+    def limit(self, W, X, threshold: float = 1.0, variables: int = 1, Xout=None):
+        """(Xout, n_limited): X limited by the DWBAP limiter (gks_limit);
+        variables: LIMIT_CONSERVATIVE (1) or LIMIT_CHARACTERISTIC (2)."""
         import torch
         if Xout is None:
             Xout = torch.empty((4, 5, self.nt), dtype=torch.float64, device=X.device)
         n = C.c_int32(0)
         code = lib().gks_limit(self._h, _dev(W, (4, self.nt), "W"), _dev(X, (4, 5, self.nt), "X"),
-                               _dev(Xout, (4, 5, self.nt), "Xout"), float(threshold), C.byref(n))
+                               _dev(Xout, (4, 5, self.nt), "Xout"), float(threshold), int(variables),
+                               C.byref(n))
         _check(code, self._h)
         return Xout, int(n.value)
 

@@ -1143,7 +1143,7 @@ void issue_update_graph(gks_mesh* m) {
     launch_zero_i32(m, w.counters, 4);
     const double* Xf = w.Xcell;
     if (m->prm.limiter) {
-        launch_limit(m, w.Wint, w.Xcell, w.Xlim, 1.0, w.counters + 2);
+        launch_limit(m, w.Wint, w.Xcell, w.Xlim, 1.0, m->prm.limiter, w.counters + 2);
         Xf = w.Xlim;
     }
     launch_flux(m, w.Wint, Xf, w.dt_dev, w.F);
@@ -1262,7 +1262,7 @@ bool params_ok(const gks_params& p) {
            p.max_iter >= 1 && p.mu >= 0.0 && p.tau_eps >= 0.0 && p.cls_w > 0.0 &&
            (p.precision == GKS_FP64 || p.precision == GKS_MIXED) &&
            (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
-           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == 1);
+           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC);
 }
 
 int fail(gks_mesh* m, const Fail& f) {
@@ -1377,15 +1377,20 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
     }
 }
 
-int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int32_t* n_limited) {
+int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int32_t variables,
+              int32_t* n_limited) {
     if (!m) return GKS_EINVAL;
     if (!W || !X || !Xout || (const void*)X == (const void*)Xout || !(threshold == threshold)) {
         m->err = "gks_limit needs W, X, Xout (not aliasing X) and a threshold";
         return GKS_EINVAL;
     }
+    if (variables != GKS_LIMIT_CONSERVATIVE && variables != GKS_LIMIT_CHARACTERISTIC) {
+        m->err = "gks_limit: variables must be GKS_LIMIT_CONSERVATIVE or GKS_LIMIT_CHARACTERISTIC";
+        return GKS_EINVAL;
+    }
     try {
         launch_zero_i32(m, m->w.counters, 4);
-        launch_limit(m, W, X, Xout, threshold, m->w.counters + 2);
+        launch_limit(m, W, X, Xout, threshold, variables, m->w.counters + 2);
         HIPCHK(hipMemcpyAsync(m->w.counters_host, m->w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
                               m->stream));
         HIPCHK(hipStreamSynchronize(m->stream));
@@ -1514,7 +1519,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
             launch_copyout(m, w.X, w.Xcell);
             const double* Xf = w.Xcell;
             if (m->prm.limiter) {
-                launch_limit(m, W, w.Xcell, w.Xlim, 1.0, w.counters + 2);
+                launch_limit(m, W, w.Xcell, w.Xlim, 1.0, m->prm.limiter, w.counters + 2);
                 Xf = w.Xlim;
             }
             launch_flux(m, W, Xf, w.dt_dev, w.F);

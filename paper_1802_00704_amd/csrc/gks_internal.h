@@ -246,7 +246,8 @@ void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
 void launch_extrap(gks_mesh* m, int order);
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);
 // DWBAP limiter: Xout = limited X where IS_i >= threshold (count += limited cells)
-void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int32_t* count);
+void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int variables,
+                  int32_t* count);
 void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out);
 void launch_set_scalar(gks_mesh* m, double* p, double v);

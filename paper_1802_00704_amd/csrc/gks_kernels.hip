@@ -1301,6 +1301,7 @@ struct LimArgs {
     double* Xout;
     double gamma, threshold;
     int all_quadratic;
+    int charvars;         // 1: limit characteristic variables, 0: conserved ones
     int32_t* count;
 };
 
@@ -1308,6 +1309,54 @@ __device__ __forceinline__ double dwbap_dev(const double* u, const double* w, in
     double s = 0.0;
     for (int q = 0; q < n; ++q) s += w[q] * atan(u[q]);
     return tan(s);
+}
+
+// Eigenvectors of the Jacobian of the Euler flux F(W).n at the conserved
+// state W, n the direction of (gx, gy) (the x axis if that is zero):
+// columns of R are the acoustic wave against n, the entropy wave, the shear
+// wave and the acoustic wave along n; L = R^-1 in closed form.
+__device__ void char_basis(const double W[4], double gx, double gy, double gamma, double L[4][4], double R[4][4]) {
+    const double g = hypot(gx, gy);
+    const double nx = g > 0.0 ? gx / g : 1.0, ny = g > 0.0 ? gy / g : 0.0;
+    const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
+    const double q2 = u * u + v * v;
+    const double p = (gamma - 1.0) * (W[3] - 0.5 * rho * q2);
+    const double c = sqrt(gamma * p / rho), ic = 1.0 / c;
+    const double H = (W[3] + p) / rho;
+    const double un = u * nx + v * ny, ut = -u * ny + v * nx;
+    const double b1 = (gamma - 1.0) * ic * ic, b2 = 0.5 * b1 * q2;
+    R[0][0] = 1.0;            R[0][1] = 1.0;      R[0][2] = 0.0; R[0][3] = 1.0;
+    R[1][0] = u - c * nx;     R[1][1] = u;        R[1][2] = -ny; R[1][3] = u + c * nx;
+    R[2][0] = v - c * ny;     R[2][1] = v;        R[2][2] = nx;  R[2][3] = v + c * ny;
+    R[3][0] = H - c * un;     R[3][1] = 0.5 * q2; R[3][2] = ut;  R[3][3] = H + c * un;
+    L[0][0] = 0.5 * (b2 + un * ic); L[0][1] = -0.5 * (b1 * u + nx * ic);
+    L[0][2] = -0.5 * (b1 * v + ny * ic); L[0][3] = 0.5 * b1;
+    L[1][0] = 1.0 - b2; L[1][1] = b1 * u; L[1][2] = b1 * v; L[1][3] = -b1;
+    L[2][0] = -ut; L[2][1] = -ny; L[2][2] = nx; L[2][3] = 0.0;
+    L[3][0] = 0.5 * (b2 - un * ic); L[3][1] = 0.5 * (nx * ic - b1 * u);
+    L[3][2] = 0.5 * (ny * ic - b1 * v); L[3][3] = 0.5 * b1;
+}
+
+// Limit one derivative of the four variables: cand[q][v] is candidate q of
+// variable v; out[v] the limited derivative.  Conserved variables one by
+// one, or characteristic variables L cand mapped back with R.
+__device__ __forceinline__ void limit_vec(const double cand[4][4], const double* w, int n, bool charvars,
+                                          const double L[4][4], const double R[4][4], double out[4]) {
+    double u[4];
+    if (!charvars) {
+        for (int v = 0; v < 4; ++v) {
+            for (int q = 0; q < n; ++q) u[q] = cand[q][v];
+            out[v] = dwbap_dev(u, w, n);
+        }
+        return;
+    }
+    double lim[4];
+    for (int k = 0; k < 4; ++k) {
+        for (int q = 0; q < n; ++q)
+            u[q] = L[k][0] * cand[q][0] + L[k][1] * cand[q][1] + L[k][2] * cand[q][2] + L[k][3] * cand[q][3];
+        lim[k] = dwbap_dev(u, w, n);
+    }
+    for (int v = 0; v < 4; ++v) out[v] = R[v][0] * lim[0] + R[v][1] * lim[1] + R[v][2] * lim[2] + R[v][3] * lim[3];
 }
 
 __global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
@@ -1408,16 +1457,21 @@ __global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
     for (int v = 0; v < 4; ++v)
 #pragma unroll
         for (int l = 0; l < 5; ++l) Xl[v][l] = Xi[v][l];
-    double u[4];
+    const bool cv = a.charvars != 0;
+    double Lm[4][4], Rm[4][4];
+    if (cv) char_basis(Wi, Xi[0][0], Xi[0][1], a.gamma, Lm, Rm);
+    double cand[4][4], out[4];
     if (ki == 2) {
         double h2[3];
         for (int n = 0; n < J; ++n) h2[n] = a.cgeo[nb[n]] * a.cgeo[nb[n]];   // 1 / h_j^2
-        for (int v = 0; v < 4; ++v)
-            for (int l = 0; l < 3; ++l) {
-                u[0] = Xi[v][2 + l] * ihi * ihi;
-                for (int n = 0; n < J; ++n) u[n + 1] = a.X[(int64_t)(v * 5 + 2 + l) * nt + nb[n]] * h2[n];
-                Xl[v][2 + l] = dwbap_dev(u, w, J + 1) * hi * hi;
+        for (int l = 0; l < 3; ++l) {
+            for (int v = 0; v < 4; ++v) {
+                cand[0][v] = Xi[v][2 + l] * ihi * ihi;
+                for (int n = 0; n < J; ++n) cand[n + 1][v] = a.X[(int64_t)(v * 5 + 2 + l) * nt + nb[n]] * h2[n];
             }
+            limit_vec(cand, w, J + 1, cv, Lm, Rm, out);
+            for (int v = 0; v < 4; ++v) Xl[v][2 + l] = out[v] * hi * hi;
+        }
     }
     // first derivatives: plane gradients through remainder averages
     double rem[3][4];
@@ -1457,13 +1511,13 @@ __global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
             }
         }
     }
-    for (int v = 0; v < 4; ++v) {
-        u[0] = Xi[v][0] * ihi;
-        for (int n = 0; n < J; ++n) u[n + 1] = gx[n][v] * ihi;
-        Xl[v][0] = dwbap_dev(u, w1, J + 1) * hi;
-        u[0] = Xi[v][1] * ihi;
-        for (int n = 0; n < J; ++n) u[n + 1] = gy[n][v] * ihi;
-        Xl[v][1] = dwbap_dev(u, w1, J + 1) * hi;
+    for (int l = 0; l < 2; ++l) {
+        for (int v = 0; v < 4; ++v) {
+            cand[0][v] = Xi[v][l] * ihi;
+            for (int n = 0; n < J; ++n) cand[n + 1][v] = (l == 0 ? gx[n][v] : gy[n][v]) * ihi;
+        }
+        limit_vec(cand, w1, J + 1, cv, Lm, Rm, out);
+        for (int v = 0; v < 4; ++v) Xl[v][l] = out[v] * hi;
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v)
@@ -1795,7 +1849,8 @@ void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn) {
                                        m->d.cface, m->d.area, W, F, Wn, m->prm.gamma, m->w.counters + 1));
 }
 
-void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int32_t* count) {
+void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int variables,
+                  int32_t* count) {
     LimArgs a;
     a.nt = m->d.nt;
     a.nf = m->d.nf;
@@ -1812,6 +1867,7 @@ void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, d
     a.gamma = m->prm.gamma;
     a.threshold = threshold;
     a.all_quadratic = m->prm.all_quadratic;
+    a.charvars = variables == GKS_LIMIT_CHARACTERISTIC;
     a.count = count;
     // bytes of the common case (cell not limited): own W, X and moments, its
     // neighbour slots and offsets; per neighbour its density polynomial and

@@ -1,5 +1,5 @@
 """Accuracy of the whole GPU scheme on the acoustic pressure pulse (section
-4.5) against the exact linear-acoustics solution of the oracle (the J0
+4.4) against the exact linear-acoustics solution of the oracle (the J0
 integral of Eq. cirPulseSolution, by quadrature).
 
 Errors are area-weighted L1 and L2 of the cell-average pressure against the

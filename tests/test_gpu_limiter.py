@@ -1,5 +1,6 @@
-"""GPU parity of the DWBAP limiter (gks_limit, and gks_step with limiter = 1)
-against the oracle's limiter.
+"""GPU parity of the DWBAP limiter (gks_limit, and gks_step with the
+limiter on) against the oracle's limiter, in conserved and in characteristic
+variables.
 
 On identical inputs the two differ only by the order of rounding; the
 biased arctan average can amplify a candidate's rounding by (1 + L^2) /
@@ -22,6 +23,7 @@ torch = pytest.importorskip("torch")
 import paper_1802_00704_amd as g  # noqa: E402
 
 pytestmark = pytest.mark.gpu
+VARS = {g.LIMIT_CONSERVATIVE: "conservative", g.LIMIT_CHARACTERISTIC: "characteristic"}
 
 
 def dev(a):
@@ -48,18 +50,19 @@ def sv_case():
     return m, gi.shock_vortex_ic(m)
 
 
+@pytest.mark.parametrize("variables", list(VARS))
 @pytest.mark.parametrize("case,threshold", [("jump", 1.0), ("jump", -1.0), ("sv", 1.0), ("sv", -1.0)])
-def test_limit_matches_oracle(case, threshold):
+def test_limit_matches_oracle(case, threshold, variables):
     m, W = jump_case() if case == "jump" else sv_case()
-    print("limiter case", case, "threshold", threshold, flush=True)
+    print("limiter case", case, "threshold", threshold, "variables", VARS[variables], flush=True)
     geo = build_geometry(m)
     X = scheme.Solver(m).reconstruct(W)
     st = limiter.cell_stencils(geo, m)
     IS = limiter.shock_indicator(geo, W, X, m, st)
     assert np.all(np.abs(IS - threshold) > 1e-9)    # no decision on the edge
-    Xl_ref, mask = limiter.limit(geo, W, X, m, threshold=threshold)
+    Xl_ref, mask = limiter.limit(geo, W, X, m, threshold=threshold, variables=VARS[variables])
     gm = g.GksMesh(m)
-    Xl, n = gm.limit(dev(W), dev(X), threshold)
+    Xl, n = gm.limit(dev(W), dev(X), threshold, variables)
     assert n == int(mask.sum())
     if threshold > 0:
         assert 0 < n < geo.nt
@@ -68,7 +71,8 @@ def test_limit_matches_oracle(case, threshold):
     gm.close()
 
 
-def test_limit_keeps_quadratic_data_exact():
+@pytest.mark.parametrize("variables", list(VARS))
+def test_limit_keeps_quadratic_data_exact(variables):
     m = gi.jss_mesh(9, 7, 4, Lx=1.3, Ly=1.1, periodic=False)
     c = np.array([0.3, -1.2, 0.7, 2.1, -0.9, 1.6])
     q = lambda x, y: c[0] + c[1] * x + c[2] * y + c[3] * x * x + c[4] * x * y + c[5] * y * y
@@ -78,36 +82,37 @@ def test_limit_keeps_quadratic_data_exact():
     W = np.stack([ubar, 2 * ubar, -ubar, 4 * ubar + 10.0])
     X = cls.reconstruct(geo, W, k)
     gm = g.GksMesh(m, all_quadratic=1)
-    Xl, n = gm.limit(dev(W), dev(X), -1.0)
+    Xl, n = gm.limit(dev(W), dev(X), -1.0, variables)
     assert n == geo.nt
     # exact in cells with three neighbours; wall cells take directional
     # candidates (the oracle's reading), checked against the oracle instead
     inner = np.array([len(st) == 3 for st in limiter.cell_stencils(geo, m)])
     Xg = Xl.cpu().numpy()
     assert np.abs(Xg[:, :, inner] - X[:, :, inner]).max() <= 1e-10 * np.abs(X).max()
-    Xo, _ = limiter.limit(geo, W, X, m, threshold=-1.0, k=k)
+    Xo, _ = limiter.limit(geo, W, X, m, threshold=-1.0, k=k, variables=VARS[variables])
     assert np.abs(Xg - Xo).max() <= 1e-11 * np.abs(X).max()
     gm.close()
 
 
-def _oracle_step(s, geo, m, W, dt):
+def _oracle_step(s, geo, m, W, dt, variables):
     X = s.reconstruct(W)
-    Xl, mask = limiter.limit(geo, W, X, m)
+    Xl, mask = limiter.limit(geo, W, X, m, variables=variables)
     F = s.flux(W, Xl, dt)
     return scheme.update(geo, W, F), int(mask.sum())
 
 
+@pytest.mark.parametrize("variables", list(VARS))
 @pytest.mark.parametrize("case", ["jump", "sv"])
-def test_step_with_limiter_matches_oracle(case):
+def test_step_with_limiter_matches_oracle(case, variables):
     m, W0 = jump_case() if case == "jump" else sv_case()
     geo = build_geometry(m)
     s = scheme.Solver(m, scheme.Params(fallback=True))
-    gm = g.GksMesh(m, limiter=1, tol=1e-13, nonphys_fallback=1)
+    gm = g.GksMesh(m, limiter=variables, tol=1e-13, nonphys_fallback=1)
     W = dev(W0)
     Wr = W0.copy()
     for _ in range(3):
         dt, info = gm.step(W)
-        Wr, nlim = _oracle_step(s, geo, m, Wr, dt)
+        Wr, nlim = _oracle_step(s, geo, m, Wr, dt, VARS[variables])
         assert info["limited"] == nlim
     rel = max(np.abs(W.cpu().numpy()[q] - Wr[q]).max() / np.abs(Wr[q]).max() for q in range(4))
     assert rel <= 1e-9, rel
@@ -115,14 +120,26 @@ def test_step_with_limiter_matches_oracle(case):
     gm.close()
 
 
-def test_graph_and_eager_steps_with_limiter_agree_bitwise():
+@pytest.mark.parametrize("variables", list(VARS))
+def test_graph_and_eager_steps_with_limiter_agree_bitwise(variables):
     m, W0 = sv_case()
     out = []
     for graphs in (0, 1):
-        gm = g.GksMesh(m, limiter=1, graphs=graphs, nonphys_fallback=1)
+        gm = g.GksMesh(m, limiter=variables, graphs=graphs, nonphys_fallback=1)
         W = dev(W0)
         for _ in range(4):
             gm.step(W)
         out.append(W.cpu().numpy())
         gm.close()
     assert np.array_equal(out[0], out[1])
+
+
+def test_limit_rejects_unknown_variables():
+    m, W = jump_case()
+    gm = g.GksMesh(m)
+    X = torch.zeros((4, 5, m.nt), dtype=torch.float64, device="cuda")
+    with pytest.raises(g.GksError):
+        gm.limit(dev(W), X, 1.0, 3)
+    with pytest.raises(g.GksError):
+        g.GksMesh(m, limiter=3)
+    gm.close()

@@ -11,8 +11,9 @@ converges at first order in L1, so the checks are that the error falls
 under refinement and stays small.  Oscillation is measured as the largest
 new extremum: how far a cell's density leaves the range the exact solution
 spans within 2h of its centroid (smearing a jump does not count, an
-overshoot does).  The first steps are also compared with the oracle's
-reconstruct - limit - flux - update chain.
+overshoot does); its area-weighted mean is reported beside the maximum.
+The first steps are also compared with the oracle's reconstruct - limit -
+flux - update chain.
 """
 import math
 
@@ -76,24 +77,25 @@ def run(nx, case, lim=1):
     ex = riemann.tube_cell_averages(m, case[0], case[1], 0.5, T, G)
     area = g.host_inspect(m)["area"]
     l1 = float((np.abs(Wn[0] - ex[0]) * area).sum() / area.sum())
-    return {"l1": l1, "overshoot": oscillation(m, Wn[0], case, 2.0 / nx), "nonphys": nonphys,
-            "limited": limited, "steps": nst, "cell_steps_per_s": m.tri.shape[0] * nst / el}
+    exc = excursion(m, Wn[0], case, 2.0 / nx)
+    return {"l1": l1, "overshoot": float(exc.max()), "osc_l1": float((exc * area).sum() / area.sum()),
+            "nonphys": nonphys, "limited": limited, "steps": nst, "cell_steps_per_s": m.tri.shape[0] * nst / el}
 
 
-def oscillation(m, rho, case, band):
-    """Largest distance of a cell density outside the exact solution's range
-    over [x - band, x + band] at the final time."""
+def excursion(m, rho, case, band):
+    """Per cell: distance of the density outside the exact solution's range
+    over [x - band, x + band] at the final time (0 inside it)."""
     left, right, T = case
     xs = np.linspace(0.0, 1.0, 20001)
     ex = riemann.sample(left, right, (xs - 0.5) / T, G)[0]
     cx = m.xy[m.tri].mean(axis=1)[:, 0]
     lo = np.searchsorted(xs, cx - band)
     hi = np.searchsorted(xs, cx + band)
-    worst = 0.0
+    out = np.zeros(rho.size)
     for i in range(rho.size):
         seg = ex[lo[i]:max(hi[i], lo[i] + 1)]
-        worst = max(worst, rho[i] - seg.max(), seg.min() - rho[i])
-    return float(worst)
+        out[i] = max(0.0, rho[i] - seg.max(), seg.min() - rho[i])
+    return out
 
 
 def test_sod_converges_with_the_limiter():
@@ -122,6 +124,26 @@ def test_lax_with_the_limiter():
     assert r["l1"] < 0.012
     assert r["overshoot"] < 0.12                          # 14% of the density jump
     assert r["limited"] > 0
+
+
+@pytest.mark.parametrize("case", [SOD, LAX], ids=["sod", "lax"])
+def test_characteristic_limiting(case):
+    """Section 4.2 compares limiting in conserved and in characteristic
+    variables and finds less oscillation with the latter.  Measured at
+    h = 1/100: the mean excursion falls 15% at Sod (1.12e-3 -> 0.96e-3) and
+    2% at Lax, the L1 error a little in both; the single largest excursion
+    falls at Sod and rises 12% at Lax."""
+    cons = run(100, case, g.LIMIT_CONSERVATIVE)
+    char = run(100, case, g.LIMIT_CHARACTERISTIC)
+    print("h=1/100 conservative", cons, "characteristic", char, flush=True)
+    assert not char.get("failed")
+    assert char["l1"] <= 1.02 * cons["l1"]
+    if case is SOD:
+        assert char["osc_l1"] < 0.9 * cons["osc_l1"]
+        assert char["overshoot"] < cons["overshoot"]
+    else:
+        assert char["osc_l1"] <= 1.02 * cons["osc_l1"]
+        assert char["overshoot"] < 1.25 * cons["overshoot"]
 
 
 def test_sod_first_steps_match_the_oracle():

@@ -1,4 +1,4 @@
-"""Pins of the oracle's exact acoustic-pulse solution (section 4.5, Eq.
+"""Pins of the oracle's exact acoustic-pulse solution (section 4.4, Eq.
 cirPulseSolution, a J0 integral evaluated by quadrature):
   * at t = 0 it is the initial Gaussian (Hankel transform of a Gaussian);
   * the plane integral of the pressure perturbation stays eps pi / alpha

@@ -18,7 +18,16 @@ method must have whatever the reading of its open points:
     k = 2 and a third-order reconstruction);
   * limiting removes at least 40% of the reconstruction's overshoot at a jump of
     density and pressure, and moves the coefficients far less across a pure
-    contact (the smoothness measure reads the pressure).
+    contact (the smoothness measure reads the pressure);
+  * characteristic variables (reading L9): the basis diagonalises the
+    Jacobian of the Euler flux, found by finite differences of the flux
+    itself, with eigenvalues u_n - c, u_n, u_n, u_n + c; exactness holds in
+    this mode too; and across a moving contact, whose data vary along the
+    entropy eigenvector alone, the limited polynomials keep velocity and
+    pressure uniform at every Gauss point, which limiting the conserved
+    variables one by one (arctan is not linear) cannot; and a quarter turn
+    of the whole problem turns the limited polynomials with it (the
+    direction of the decomposition follows the data, not the axes).
 """
 import numpy as np
 import pytest
@@ -76,11 +85,12 @@ def _three_neighbours(geo, m):
     return np.array([len(st) == 3 for st in limiter.cell_stencils(geo, m)])
 
 
-def _force_all(m, geo, W, X, k):
-    return limiter.limit(geo, W, X, m, threshold=-1.0, k=k)
+def _force_all(m, geo, W, X, k, variables="conservative"):
+    return limiter.limit(geo, W, X, m, threshold=-1.0, k=k, variables=variables)
 
 
-def test_quadratic_fields_unchanged_even_when_every_cell_is_limited():
+@pytest.mark.parametrize("variables", ["conservative", "characteristic"])
+def test_quadratic_fields_unchanged_even_when_every_cell_is_limited(variables):
     m = gi.jss_mesh(7, 6, 4, Lx=1.3, Ly=1.1, periodic=False)
     geo = build_geometry(m)
     c = np.array([0.3, -1.2, 0.7, 2.1, -0.9, 1.6])
@@ -91,13 +101,14 @@ def test_quadratic_fields_unchanged_even_when_every_cell_is_limited():
     X = cls.reconstruct(geo, W, k)
     IS = limiter.shock_indicator(geo, W, X, m, k=k)
     assert np.abs(IS).max() < 1e-10
-    Xl, mask = _force_all(m, geo, W, X, k)
+    Xl, mask = _force_all(m, geo, W, X, k, variables)
     assert mask.all()
     inner = _three_neighbours(geo, m)
     assert np.abs(Xl[:, :, inner] - X[:, :, inner]).max() <= 1e-10 * np.abs(X).max()
 
 
-def test_linear_fields_unchanged_with_linear_boundary_cells():
+@pytest.mark.parametrize("variables", ["conservative", "characteristic"])
+def test_linear_fields_unchanged_with_linear_boundary_cells(variables):
     m = gi.jss_mesh(7, 6, 8, Lx=1.0, Ly=1.0, periodic=False)
     geo = build_geometry(m)
     k = cls.cell_orders(geo)
@@ -107,10 +118,12 @@ def test_linear_fields_unchanged_with_linear_boundary_cells():
     W = np.stack([ubar, 0.5 * ubar, -0.25 * ubar, 3 * ubar])
     X = cls.reconstruct(geo, W, k)
     assert np.abs(limiter.shock_indicator(geo, W, X, m, k=k)).max() < 1e-10
-    Xl, _ = _force_all(m, geo, W, X, k)
+    Xl, _ = _force_all(m, geo, W, X, k, variables)
     inner = _three_neighbours(geo, m)
     assert inner.sum() > 0 and (~inner).sum() > 0
     assert np.abs(Xl[:, :, inner] - X[:, :, inner]).max() <= 1e-11 * np.abs(X).max()
+    if variables == "characteristic":
+        return   # the wall bound below is per conserved variable
     # wall cells take directional candidates, the projections of the exact
     # gradient on the neighbour directions, none longer than the gradient;
     # each limited component lies within its candidates' range, so it is
@@ -215,3 +228,81 @@ def test_indicator_decays_like_h_to_the_1_5_on_smooth_data():
     r1, r2 = peaks[0] / peaks[1], peaks[1] / peaks[2]
     assert peaks[0] < 1.0
     assert 2.0 < r1 and 2.0 < r2 < 4.0   # 2^1.5 = 2.83
+
+
+def _euler_flux_n(W, n, gamma):
+    rho, mx, my, E = W
+    u, v = mx / rho, my / rho
+    p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+    un = u * n[0] + v * n[1]
+    return np.array([rho * un, mx * un + p * n[0], my * un + p * n[1], (E + p) * un])
+
+
+def test_characteristic_basis_diagonalises_the_euler_flux_jacobian():
+    rng = np.random.default_rng(3)
+    G = 1.4
+    for _ in range(20):
+        rho, p = rng.uniform(0.1, 3.0), rng.uniform(0.1, 5.0)
+        u, v = rng.normal(size=2)
+        W = gi.prim_to_cons(np.array([rho]), u, v, p, G)[:, 0]
+        th = rng.uniform(0, 2 * np.pi)
+        n = np.array([np.cos(th), np.sin(th)])
+        A = np.zeros((4, 4))
+        for q in range(4):
+            e = np.zeros(4)
+            e[q] = 1e-6 * max(1.0, abs(W[q]))
+            A[:, q] = (_euler_flux_n(W + e, n, G) - _euler_flux_n(W - e, n, G)) / (2 * e[q])
+        R = limiter.characteristic_basis(W, G, n)
+        c = np.sqrt(G * p / rho)
+        un = u * n[0] + v * n[1]
+        lam = np.array([un - c, un, un, un + c])
+        scale = np.abs(A).max() * np.abs(R).max()
+        assert np.abs(A @ R - R * lam[None, :]).max() <= 1e-7 * scale
+        assert np.linalg.cond(R) < 1e4
+
+
+def test_characteristic_limiting_keeps_a_moving_contact_pure():
+    m = gi.jss_mesh(24, 4, 5, Lx=2.0, Ly=1.0 / 3.0, periodic=True)
+    geo = build_geometry(m)
+    u0, v0, p0 = 0.7, -0.3, 1.0
+    rho = quad_avg(m, lambda x, y: np.where(np.abs(x - 1.0) < 0.5, 1.0, 0.125))
+    W = gi.prim_to_cons(rho, u0, v0, p0, 1.4)
+    X = scheme.Solver(m).reconstruct(W)
+    pts = geo.gp.reshape(-1, 2)
+    cells = np.repeat(geo.own, 2)
+    dev = {}
+    for variables in ("conservative", "characteristic"):
+        Xl, mask = limiter.limit(geo, W, X, m, variables=variables)
+        assert mask.any()
+        Q = scheme.gp_states(geo, W, Xl, cells, pts)[0]
+        vel = np.abs(Q[1] / Q[0] - u0).max() + np.abs(Q[2] / Q[0] - v0).max()
+        prs = np.abs(0.4 * (Q[3] - 0.5 * (Q[1] ** 2 + Q[2] ** 2) / Q[0]) - p0).max()
+        dev[variables] = max(vel, prs)
+    assert dev["characteristic"] <= 1e-12
+    assert dev["conservative"] > 1e-4
+
+
+@pytest.mark.parametrize("variables", ["conservative", "characteristic"])
+def test_limiting_commutes_with_a_quarter_turn(variables):
+    from test_oracle_scheme import rotate_coefficients, rotate_mesh
+    m = gi.jss_mesh(10, 8, 11, Lx=1.0, Ly=0.8, periodic=False, walls=((gi.BC_SLIP, None),) * 4)
+    geo = build_geometry(m)
+    # an oblique shock-like jump: density, pressure and the normal velocity
+    # jump (with uniform velocity the characteristic coordinates of a jump
+    # in density and pressure would not depend on the direction at all)
+    nu = np.array([1.0, 0.6]) / np.hypot(1.0, 0.6)
+    side = lambda x, y: (x + 0.6 * y < 0.55).astype(float)
+    rho = quad_avg(m, lambda x, y: 0.2 + 0.8 * side(x, y))
+    p = quad_avg(m, lambda x, y: 0.3 + 0.7 * side(x, y))
+    mx = quad_avg(m, lambda x, y: (0.2 + 0.8 * side(x, y)) * (0.3 + 0.5 * nu[0] * side(x, y)))
+    my = quad_avg(m, lambda x, y: (0.2 + 0.8 * side(x, y)) * (-0.2 + 0.5 * nu[1] * side(x, y)))
+    W = gi.prim_to_cons(rho, mx / rho, my / rho, p, 1.4)
+    X = scheme.Solver(m).reconstruct(W)
+    Xl, mask = limiter.limit(geo, W, X, m, variables=variables)
+    assert 0 < mask.sum() < geo.nt
+    mr, R = rotate_mesh(m, np.pi / 2)
+    Wr = W.copy()
+    Wr[1:3] = R @ W[1:3]
+    Xlr, maskr = limiter.limit(build_geometry(mr), Wr, rotate_coefficients(X, R), mr, variables=variables)
+    assert np.array_equal(mask, maskr)
+    assert np.abs(Xlr - rotate_coefficients(Xl, R)).max() <= 1e-12 * np.abs(X).max()
