@@ -483,6 +483,14 @@ T* dev_alloc(gks_mesh* m, size_t count) {
     return p;
 }
 
+// List of limited cells and their coefficients: at set-up when gks_step
+// limits, else on the first gks_limit call.
+void ensure_limit_buffers(gks_mesh* m) {
+    if (m->w.lim_list) return;
+    m->w.lim_list = dev_alloc<int32_t>(m, (size_t)m->d.nt);
+    m->w.lim_buf = dev_alloc<double>(m, (size_t)20 * m->d.nt);
+}
+
 // Everything the device needs, built on the host (no HIP calls).
 struct HostSystem {
     HostMesh hm;
@@ -966,7 +974,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     }
     w.ks = dev_alloc<KrylovState>(m, 1);
     w.Xcell = dev_alloc<double>(m, (size_t)20 * nt);
-    if (prm.limiter) w.Xlim = dev_alloc<double>(m, (size_t)20 * nt);
+    if (prm.limiter) ensure_limit_buffers(m);
     w.F = dev_alloc<double>(m, (size_t)4 * nf);
     w.Wn = dev_alloc<double>(m, (size_t)4 * nt);
     w.Wint = dev_alloc<double>(m, (size_t)4 * nt);
@@ -1141,12 +1149,9 @@ void issue_update_graph(gks_mesh* m) {
     Work& w = m->w;
     launch_copyout(m, w.X, w.Xcell);
     launch_zero_i32(m, w.counters, 4);
-    const double* Xf = w.Xcell;
-    if (m->prm.limiter) {
-        launch_limit(m, w.Wint, w.Xcell, w.Xlim, 1.0, m->prm.limiter, w.counters + 2);
-        Xf = w.Xlim;
-    }
-    launch_flux(m, w.Wint, Xf, w.dt_dev, w.F);
+    // the limiter changes the flagged cells of Xcell in place
+    if (m->prm.limiter) launch_limit(m, w.Wint, w.Xcell, nullptr, w.Xcell, 1.0, m->prm.limiter, w.counters + 2);
+    launch_flux(m, w.Wint, w.Xcell, w.dt_dev, w.F);
     launch_update(m, w.Wint, w.F, w.Wn);
 }
 
@@ -1389,8 +1394,9 @@ int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, doubl
         return GKS_EINVAL;
     }
     try {
+        ensure_limit_buffers(m);
         launch_zero_i32(m, m->w.counters, 4);
-        launch_limit(m, W, X, Xout, threshold, variables, m->w.counters + 2);
+        launch_limit(m, W, X, Xout, Xout, threshold, variables, m->w.counters + 2);
         HIPCHK(hipMemcpyAsync(m->w.counters_host, m->w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
                               m->stream));
         HIPCHK(hipStreamSynchronize(m->stream));
@@ -1517,12 +1523,8 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
                 return st;
             }
             launch_copyout(m, w.X, w.Xcell);
-            const double* Xf = w.Xcell;
-            if (m->prm.limiter) {
-                launch_limit(m, W, w.Xcell, w.Xlim, 1.0, m->prm.limiter, w.counters + 2);
-                Xf = w.Xlim;
-            }
-            launch_flux(m, W, Xf, w.dt_dev, w.F);
+            if (m->prm.limiter) launch_limit(m, W, w.Xcell, nullptr, w.Xcell, 1.0, m->prm.limiter, w.counters + 2);
+            launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
             launch_update(m, W, w.F, w.Wn);
         }
         HIPCHK(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));

@@ -144,7 +144,8 @@ struct Work {
     KrylovState* ks = nullptr;    // device
     Status* st_host = nullptr;    // pinned mirror of ks->st
     double* Xcell = nullptr;
-    double* Xlim = nullptr;       // [20][nt] limited coefficients (limiter on)      // [4][5][nt] X in cell order (gks_step)
+    int32_t* lim_list = nullptr;  // [nt] cells the limiter changes (allocated on first use)
+    double* lim_buf = nullptr;    // [20][nt] their limited coefficients, by list position      // [4][5][nt] X in cell order (gks_step)
     double* F = nullptr;          // [4][nf]
     double* Wn = nullptr;         // [4][nt]
     double* Wint = nullptr;       // [4][nt] the step's copy of W (graph path)
@@ -195,7 +196,7 @@ struct LaunchError {
 enum Kc {
     KC_RHS = 0, KC_SPMV, KC_SPMV_RES, KC_ILU_FWD, KC_ILU_BWD, KC_DOTS, KC_AXPY_DOTS, KC_AXPY_NORM,
     KC_FINAL, KC_COMBINE, KC_AXPY, KC_COPYOUT, KC_FLUX, KC_UPDATE, KC_CFL, KC_MISC,
-    KC_SPMV32, KC_ILU_FWD32, KC_ILU_BWD32, KC_EXTRAP, KC_LIMIT, KC_COUNT
+    KC_SPMV32, KC_ILU_FWD32, KC_ILU_BWD32, KC_EXTRAP, KC_LIMIT, KC_LIMIT_APPLY, KC_COUNT
 };
 extern const char* kc_names[NPROF];
 
@@ -246,8 +247,12 @@ void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
 void launch_extrap(gks_mesh* m, int order);
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);
 // DWBAP limiter: Xout = limited X where IS_i >= threshold (count += limited cells)
-void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int variables,
-                  int32_t* count);
+// DWBAP limiter: cells whose indicator reaches threshold get limited
+// coefficients in dst; with Xcopy set, X is first copied there for every
+// cell (dst may then be Xcopy; otherwise dst already holds X, e.g. dst == X
+// is allowed as nothing of X is read after the apply kernel).
+void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, double* dst, double threshold,
+                  int variables, int32_t* count);
 void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out);
 void launch_set_scalar(gks_mesh* m, double* p, double v);

@@ -19,7 +19,7 @@ namespace gks {
 const char* kc_names[NPROF] = {"rhs",       "spmv",       "spmv_resid", "ilu_fwd",  "ilu_bwd",
                                "dots",      "axpy_dots",  "axpy_norm",  "finalize", "combine",
                                "axpy",      "copyout",    "flux",       "update",   "cfl",
-                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "limit", "", "", ""};
+                               "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "limit", "limit_apply", "", ""};
 
 constexpr int TPB = 256;          // threads per block of the streaming kernels
 constexpr int RED_CHUNK = FUSED_DOTS_MAX;   // vectors per block of the dot kernels
@@ -1297,78 +1297,21 @@ struct LimArgs {
     const double* gpd;
     const double* cgeo;
     const double* W;
-    const double* X;
-    double* Xout;
+    const double* X;      // unlimited coefficients [20][nt]
+    double* Xcopy;        // mark: when set, receives X for every cell
     double gamma, threshold;
     int all_quadratic;
     int charvars;         // 1: limit characteristic variables, 0: conserved ones
-    int32_t* count;
+    int32_t* count;       // number of limited cells (list length)
+    int32_t* list;        // [nt] limited cells, in no particular order
+    double* lbuf;         // [20][nt] limited coefficients of list entry k at column k
+    double* dst;          // scatter target [20][nt]
 };
 
-__device__ __forceinline__ double dwbap_dev(const double* u, const double* w, int n) {
-    double s = 0.0;
-    for (int q = 0; q < n; ++q) s += w[q] * atan(u[q]);
-    return tan(s);
-}
-
-// Eigenvectors of the Jacobian of the Euler flux F(W).n at the conserved
-// state W, n the direction of (gx, gy) (the x axis if that is zero):
-// columns of R are the acoustic wave against n, the entropy wave, the shear
-// wave and the acoustic wave along n; L = R^-1 in closed form.
-__device__ void char_basis(const double W[4], double gx, double gy, double gamma, double L[4][4], double R[4][4]) {
-    const double g = hypot(gx, gy);
-    const double nx = g > 0.0 ? gx / g : 1.0, ny = g > 0.0 ? gy / g : 0.0;
-    const double rho = W[0], u = W[1] / rho, v = W[2] / rho;
-    const double q2 = u * u + v * v;
-    const double p = (gamma - 1.0) * (W[3] - 0.5 * rho * q2);
-    const double c = sqrt(gamma * p / rho), ic = 1.0 / c;
-    const double H = (W[3] + p) / rho;
-    const double un = u * nx + v * ny, ut = -u * ny + v * nx;
-    const double b1 = (gamma - 1.0) * ic * ic, b2 = 0.5 * b1 * q2;
-    R[0][0] = 1.0;            R[0][1] = 1.0;      R[0][2] = 0.0; R[0][3] = 1.0;
-    R[1][0] = u - c * nx;     R[1][1] = u;        R[1][2] = -ny; R[1][3] = u + c * nx;
-    R[2][0] = v - c * ny;     R[2][1] = v;        R[2][2] = nx;  R[2][3] = v + c * ny;
-    R[3][0] = H - c * un;     R[3][1] = 0.5 * q2; R[3][2] = ut;  R[3][3] = H + c * un;
-    L[0][0] = 0.5 * (b2 + un * ic); L[0][1] = -0.5 * (b1 * u + nx * ic);
-    L[0][2] = -0.5 * (b1 * v + ny * ic); L[0][3] = 0.5 * b1;
-    L[1][0] = 1.0 - b2; L[1][1] = b1 * u; L[1][2] = b1 * v; L[1][3] = -b1;
-    L[2][0] = -ut; L[2][1] = -ny; L[2][2] = nx; L[2][3] = 0.0;
-    L[3][0] = 0.5 * (b2 - un * ic); L[3][1] = 0.5 * (nx * ic - b1 * u);
-    L[3][2] = 0.5 * (ny * ic - b1 * v); L[3][3] = 0.5 * b1;
-}
-
-// Limit one derivative of the four variables: cand[q][v] is candidate q of
-// variable v; out[v] the limited derivative.  Conserved variables one by
-// one, or characteristic variables L cand mapped back with R.
-__device__ __forceinline__ void limit_vec(const double cand[4][4], const double* w, int n, bool charvars,
-                                          const double L[4][4], const double R[4][4], double out[4]) {
-    double u[4];
-    if (!charvars) {
-        for (int v = 0; v < 4; ++v) {
-            for (int q = 0; q < n; ++q) u[q] = cand[q][v];
-            out[v] = dwbap_dev(u, w, n);
-        }
-        return;
-    }
-    double lim[4];
-    for (int k = 0; k < 4; ++k) {
-        for (int q = 0; q < n; ++q)
-            u[q] = L[k][0] * cand[q][0] + L[k][1] * cand[q][1] + L[k][2] * cand[q][2] + L[k][3] * cand[q][3];
-        lim[k] = dwbap_dev(u, w, n);
-    }
-    for (int v = 0; v < 4; ++v) out[v] = R[v][0] * lim[0] + R[v][1] * lim[1] + R[v][2] * lim[2] + R[v][3] * lim[3];
-}
-
-__global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
-    const int i = xcd_row();
-    if (i >= a.nt) return;
+// Face-neighbour stencil of cell i: interior neighbours, their slots and
+// centroid offsets (r_j - r_i) / h_i.
+__device__ __forceinline__ int lim_stencil(const LimArgs& a, int i, int nb[3], int slot[3], double dc[3][2]) {
     const int nt = a.nt;
-    const double ihi = a.cgeo[i], hi = 1.0 / ihi;
-    // second moments of cell i about its centroid, in units of h_i^2
-    const double mxx = a.cgeo[nt + i], mxy = a.cgeo[2 * nt + i], myy = a.cgeo[3 * nt + i];
-    // stencil: interior neighbours; dc = (r_j - r_i) / h_i
-    int nb[3], slot[3];
-    double dc[3][2];
     int J = 0;
     for (int s = 0; s < 3; ++s) {
         const int j = a.nbc[(int64_t)s * nt + i];
@@ -1379,150 +1322,304 @@ __global__ void __launch_bounds__(TPB) k_limit(LimArgs a) {
         dc[J][1] = a.a0c[((int64_t)s * 5 + 1) * nt + i];
         ++J;
     }
-    const bool boundary = J < 3;
-    const int ki = (boundary && !a.all_quadratic) ? 1 : 2;
-    double Xi[4][5], Wi[4];
+    return J;
+}
+
+// Shock indicator of Eq. ISD1 on the density, for every cell; limited cells
+// are appended to the list.  With Xcopy set, X is copied for every cell.
+__global__ void __launch_bounds__(TPB) k_limit_mark(LimArgs a) {
+    const int i = xcd_row();
+    if (i >= a.nt) return;
+    const int nt = a.nt;
+    if (a.Xcopy) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-        Wi[v] = a.W[(int64_t)v * nt + i];
-#pragma unroll
-        for (int l = 0; l < 5; ++l) Xi[v][l] = a.X[(int64_t)(v * 5 + l) * nt + i];
+        for (int l = 0; l < 20; ++l) a.Xcopy[(int64_t)l * nt + i] = a.X[(int64_t)l * nt + i];
     }
-    bool limit = false;
-    if (J > 0) {
-        // shock indicator on the density
-        const double own = Wi[0] - 0.5 * mxx * Xi[0][2] - mxy * Xi[0][3] - 0.5 * myy * Xi[0][4];
-        double num = 0.0, umax = Wi[0];
-        for (int n = 0; n < J; ++n) {
-            const int j = nb[n];
-            const double ihj = a.cgeo[j];
-            const double dx = -dc[n][0] * hi * ihj, dy = -dc[n][1] * hi * ihj;   // (r_i - r_j) / h_j
-            const double mxj = a.cgeo[nt + j], mxyj = a.cgeo[2 * nt + j], myj = a.cgeo[3 * nt + j];
-            double vj = a.W[j];
-            const double phi[5] = {dx, dy, 0.5 * (dx * dx - mxj), dx * dy - mxyj, 0.5 * (dy * dy - myj)};
-#pragma unroll
-            for (int l = 0; l < 5; ++l) vj += a.X[(int64_t)l * nt + j] * phi[l];
-            num += fabs(own - vj);
-            umax = fmax(umax, a.W[j]);
-        }
-        const double hk = ki == 2 ? hi * sqrt(hi) : hi;   // h_i^((k+1)/2)
-        const double IS = num / (J * hk * umax);
-        limit = IS >= a.threshold;
-    }
-    if (!limit) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-#pragma unroll
-            for (int l = 0; l < 5; ++l) a.Xout[(int64_t)(v * 5 + l) * nt + i] = Xi[v][l];
-        return;
-    }
-    atomicAdd(a.count, 1);
-    // midpoints of the interior faces, relative to r_i, in units of h_i
-    double mid[3][2];
-    int nm = 0;
-    for (int k = 0; k < 3; ++k) {
-        const int cf = a.cface[(int64_t)k * nt + i];
-        const int f = cf >= 0 ? cf : ~cf;
-        const int side = cf >= 0 ? 0 : 1;
-        if ((side == 0 ? a.nbr[f] : a.own[f]) < 0) continue;
-        const int64_t nf = a.nf;
-        mid[nm][0] = 0.5 * (a.gpd[(2 * side) * nf + f] + a.gpd[(4 + 2 * side) * nf + f]);
-        mid[nm][1] = 0.5 * (a.gpd[(2 * side + 1) * nf + f] + a.gpd[(4 + 2 * side + 1) * nf + f]);
-        ++nm;
-    }
-    // weights
-    double p[3], pbar = 0.0;
+    int nb[3], slot[3];
+    double dc[3][2];
+    const int J = lim_stencil(a, i, nb, slot, dc);
+    if (J == 0) return;
+    const int ki = (J < 3 && !a.all_quadratic) ? 1 : 2;
+    const double ihi = a.cgeo[i], hi = 1.0 / ihi;
+    const double mxx = a.cgeo[nt + i], mxy = a.cgeo[2 * nt + i], myy = a.cgeo[3 * nt + i];
+    const double Wi0 = a.W[i];
+    const double own = Wi0 - 0.5 * mxx * a.X[(int64_t)2 * nt + i] - mxy * a.X[(int64_t)3 * nt + i] -
+                       0.5 * myy * a.X[(int64_t)4 * nt + i];
+    double num = 0.0, umax = Wi0;
     for (int n = 0; n < J; ++n) {
         const int j = nb[n];
-        const double r = a.W[j], mu = a.W[(int64_t)nt + j], mv = a.W[(int64_t)2 * nt + j], E = a.W[(int64_t)3 * nt + j];
-        p[n] = (a.gamma - 1.0) * (E - 0.5 * (mu * mu + mv * mv) / r);
-        pbar += p[n];
-    }
-    pbar /= J;
-    double var = 0.0;
-    for (int n = 0; n < J; ++n) var += (p[n] - pbar) * (p[n] - pbar);
-    const double chi = sqrt(var / J) / pbar;
-    const double S = 1.0 / (sqrt(chi + 1e-8) + 0.05);
-    double w[4], wsum = 0.0;
-    for (int q = 0; q <= J; ++q) {
-        const double cx = q == 0 ? 0.0 : dc[q - 1][0], cy = q == 0 ? 0.0 : dc[q - 1][1];
-        double D = 0.0;
-        for (int m = 0; m < nm; ++m) D += hypot(cx - mid[m][0], cy - mid[m][1]);
-        w[q] = pow(D / nm, -S);
-        wsum += w[q];
-    }
-    for (int q = 0; q <= J; ++q) w[q] /= wsum;
-    double Xl[4][5];
+        const double ihj = a.cgeo[j];
+        const double dx = -dc[n][0] * hi * ihj, dy = -dc[n][1] * hi * ihj;   // (r_i - r_j) / h_j
+        const double mxj = a.cgeo[nt + j], mxyj = a.cgeo[2 * nt + j], myj = a.cgeo[3 * nt + j];
+        double vj = a.W[j];
+        const double phi[5] = {dx, dy, 0.5 * (dx * dx - mxj), dx * dy - mxyj, 0.5 * (dy * dy - myj)};
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+        for (int l = 0; l < 5; ++l) vj += a.X[(int64_t)l * nt + j] * phi[l];
+        num += fabs(own - vj);
+        umax = fmax(umax, a.W[j]);
+    }
+    const double hk = ki == 2 ? hi * sqrt(hi) : hi;   // h_i^((k+1)/2)
+    if (num / (J * hk * umax) >= a.threshold) a.list[atomicAdd(a.count, 1)] = i;
+}
+
+// Characteristic decomposition of the Euler equations along unit n at a
+// conserved state: y = L x and x = R y in closed form, L = R^-1, where the
+// columns of R are the acoustic wave against n, the entropy wave, the
+// shear wave and the acoustic wave along n.
+struct CharBasis {
+    double u, v, c, ic, H, nx, ny, un, ut, q2, b1, b2;
+    __device__ void init(const double W[4], double gx, double gy, double gamma) {
+        const double g = hypot(gx, gy);
+        nx = g > 0.0 ? gx / g : 1.0;
+        ny = g > 0.0 ? gy / g : 0.0;
+        const double rho = W[0];
+        u = W[1] / rho;
+        v = W[2] / rho;
+        q2 = u * u + v * v;
+        const double p = (gamma - 1.0) * (W[3] - 0.5 * rho * q2);
+        c = sqrt(gamma * p / rho);
+        ic = 1.0 / c;
+        H = (W[3] + p) / rho;
+        un = u * nx + v * ny;
+        ut = -u * ny + v * nx;
+        b1 = (gamma - 1.0) * ic * ic;
+        b2 = 0.5 * b1 * q2;
+    }
+    __device__ void to_char(const double x[4], double y[4]) const {
+        const double P = b2 * x[0] + b1 * (x[3] - u * x[1] - v * x[2]);
+        const double A = ic * (un * x[0] - nx * x[1] - ny * x[2]);
+        y[0] = 0.5 * (P + A);
+        y[1] = x[0] - P;
+        y[2] = -ut * x[0] - ny * x[1] + nx * x[2];
+        y[3] = 0.5 * (P - A);
+    }
+    __device__ void from_char(const double y[4], double x[4]) const {
+        const double s = y[0] + y[3], d = y[3] - y[0];
+        x[0] = s + y[1];
+        x[1] = u * x[0] + c * nx * d - ny * y[2];
+        x[2] = v * x[0] + c * ny * d + nx * y[2];
+        x[3] = H * s + c * un * d + 0.5 * q2 * y[1] + ut * y[2];
+    }
+};
+
+// Biased average of Eq. DWBAP over the valid candidates (q = 0..3, in order).
+__device__ __forceinline__ double dwbap4(const double u[4], const double w[4], const bool ok[4]) {
+    double s = 0.0;
 #pragma unroll
-        for (int l = 0; l < 5; ++l) Xl[v][l] = Xi[v][l];
-    const bool cv = a.charvars != 0;
-    double Lm[4][4], Rm[4][4];
-    if (cv) char_basis(Wi, Xi[0][0], Xi[0][1], a.gamma, Lm, Rm);
-    double cand[4][4], out[4];
-    if (ki == 2) {
-        double h2[3];
-        for (int n = 0; n < J; ++n) h2[n] = a.cgeo[nb[n]] * a.cgeo[nb[n]];   // 1 / h_j^2
-        for (int l = 0; l < 3; ++l) {
-            for (int v = 0; v < 4; ++v) {
-                cand[0][v] = Xi[v][2 + l] * ihi * ihi;
-                for (int n = 0; n < J; ++n) cand[n + 1][v] = a.X[(int64_t)(v * 5 + 2 + l) * nt + nb[n]] * h2[n];
-            }
-            limit_vec(cand, w, J + 1, cv, Lm, Rm, out);
-            for (int v = 0; v < 4; ++v) Xl[v][2 + l] = out[v] * hi * hi;
+    for (int q = 0; q < 4; ++q)
+        if (ok[q]) s += w[q] * atan(u[q]);
+    return tan(s);
+}
+
+// Limit one derivative of the four variables: cand[q][v] is candidate q of
+// variable v (overwritten), ok[q] whether it exists; out[v] the limited
+// derivative.  Conserved variables one by one, or characteristic variables
+// mapped back.
+__device__ __forceinline__ void limit_vec(double cand[4][4], const double w[4], const bool ok[4], bool charvars,
+                                          const CharBasis& cb, double out[4]) {
+    if (charvars) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            if (!ok[q]) continue;
+            double y[4];
+            cb.to_char(cand[q], y);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) cand[q][k] = y[k];
         }
     }
-    // first derivatives: plane gradients through remainder averages
-    double rem[3][4];
-    for (int n = 0; n < J; ++n) {
-        const int64_t b = (int64_t)slot[n] * 5;
-        const double a3 = a.a0c[(b + 2) * nt + i], a4 = a.a0c[(b + 3) * nt + i], a5 = a.a0c[(b + 4) * nt + i];
+    double lim[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        double u[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) u[q] = cand[q][k];
+        lim[k] = dwbap4(u, w, ok);
+    }
+    if (charvars)
+        cb.from_char(lim, out);
+    else
+#pragma unroll
+        for (int k = 0; k < 4; ++k) out[k] = lim[k];
+}
+
+// The DWBAP limiter on the listed cells (grid-stride over the list): the
+// limited coefficients of entry k go to column k of lbuf.  Neighbours stay
+// in their slots (ok[] marks the interior ones; candidate 1 + s belongs to
+// slot s), so every array index is a compile-time constant.
+__global__ void __launch_bounds__(64) k_limit_apply(LimArgs a) {
+    const int cnt = *a.count;
+    const int nt = a.nt;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+        const int i = a.list[k];
+        const double ihi = a.cgeo[i], hi = 1.0 / ihi;
+        int nb[3];
+        bool ok[4];
+        double dc[3][2];
+        int J = 0;
+        ok[0] = true;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            nb[s] = a.nbc[(int64_t)s * nt + i];
+            ok[s + 1] = nb[s] != i;
+            dc[s][0] = a.a0c[((int64_t)s * 5 + 0) * nt + i];
+            dc[s][1] = a.a0c[((int64_t)s * 5 + 1) * nt + i];
+            J += ok[s + 1];
+        }
+        const int ki = (J < 3 && !a.all_quadratic) ? 1 : 2;
+        // weights of Eqs. DWBAP_w, DWBAP_S; distances in units of h_i to the
+        // midpoints of the interior faces
+        double w[4];
+        {
+            double mid[3][2];
+            bool mok[3];
+            int nm = 0;
+#pragma unroll
+            for (int e = 0; e < 3; ++e) {
+                const int cf = a.cface[(int64_t)e * nt + i];
+                const int f = cf >= 0 ? cf : ~cf;
+                const int side = cf >= 0 ? 0 : 1;
+                mok[e] = (side == 0 ? a.nbr[f] : a.own[f]) >= 0;
+                const int64_t nf = a.nf;
+                mid[e][0] = 0.5 * (a.gpd[(2 * side) * nf + f] + a.gpd[(4 + 2 * side) * nf + f]);
+                mid[e][1] = 0.5 * (a.gpd[(2 * side + 1) * nf + f] + a.gpd[(4 + 2 * side + 1) * nf + f]);
+                nm += mok[e];
+            }
+            double p[3], pbar = 0.0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                p[s] = 0.0;
+                if (!ok[s + 1]) continue;
+                const int j = nb[s];
+                const double r = a.W[j], mu = a.W[(int64_t)nt + j], mv = a.W[(int64_t)2 * nt + j];
+                const double E = a.W[(int64_t)3 * nt + j];
+                p[s] = (a.gamma - 1.0) * (E - 0.5 * (mu * mu + mv * mv) / r);
+                pbar += p[s];
+            }
+            pbar /= J;
+            double var = 0.0;
+#pragma unroll
+            for (int s = 0; s < 3; ++s)
+                if (ok[s + 1]) var += (p[s] - pbar) * (p[s] - pbar);
+            const double chi = sqrt(var / J) / pbar;
+            const double S = 1.0 / (sqrt(chi + 1e-8) + 0.05);
+            double wsum = 0.0;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                w[q] = 0.0;
+                if (!ok[q]) continue;
+                const double cx = q == 0 ? 0.0 : dc[q - 1][0], cy = q == 0 ? 0.0 : dc[q - 1][1];
+                double D = 0.0;
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if (mok[e]) D += hypot(cx - mid[e][0], cy - mid[e][1]);
+                w[q] = pow(D / nm, -S);
+                wsum += w[q];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) w[q] /= wsum;
+        }
+        double Wi[4], Xi[4][5];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            Wi[v] = a.W[(int64_t)v * nt + i];
+#pragma unroll
+            for (int l = 0; l < 5; ++l) Xi[v][l] = a.X[(int64_t)(v * 5 + l) * nt + i];
+        }
+        const bool cv = a.charvars != 0;
+        CharBasis cb;
+        if (cv) cb.init(Wi, Xi[0][0], Xi[0][1], a.gamma);
+        double cand[4][4], out[4];
+        // second derivatives: own and the neighbours' (limited in place)
+        if (ki == 2) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    cand[0][v] = Xi[v][2 + l] * ihi * ihi;
+#pragma unroll
+                    for (int s = 0; s < 3; ++s) {
+                        cand[s + 1][v] = 0.0;
+                        if (!ok[s + 1]) continue;
+                        const double ihj = a.cgeo[nb[s]];
+                        cand[s + 1][v] = a.X[(int64_t)(v * 5 + 2 + l) * nt + nb[s]] * (ihj * ihj);
+                    }
+                }
+                limit_vec(cand, w, ok, cv, cb, out);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Xi[v][2 + l] = out[v] * hi * hi;
+            }
+        }
+        // first derivatives from remainder averages: with three neighbours
+        // the plane through each neighbour pair (weighing the pair's mean
+        // weight); in a wall cell the gradient along each neighbour's
+        // direction alone
+        double rem[3][4];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) rem[s][v] = 0.0;
+            if (!ok[s + 1]) continue;
+            const int64_t b = (int64_t)s * 5;
+            const double a3 = a.a0c[(b + 2) * nt + i], a4 = a.a0c[(b + 3) * nt + i], a5 = a.a0c[(b + 4) * nt + i];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                rem[s][v] = (a.W[(int64_t)v * nt + nb[s]] - Wi[v]) - (Xi[v][2] * a3 + Xi[v][3] * a4 + Xi[v][4] * a5);
+        }
+        const bool pairs = J == 3;
+        double w1[4];
+        w1[0] = w[0];
+#pragma unroll
+        for (int s = 0; s < 3; ++s) w1[s + 1] = pairs ? 0.5 * (w[s + 1] + w[(s + 1) % 3 + 1]) : w[s + 1];
+#pragma unroll
+        for (int l = 0; l < 2; ++l) {
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) cand[s + 1][v] = 0.0;
+                if (!ok[s + 1]) continue;
+                if (!pairs) {
+                    const double dd = dc[s][0] * dc[s][0] + dc[s][1] * dc[s][1];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) cand[s + 1][v] = rem[s][v] * dc[s][l] / dd * ihi;
+                    continue;
+                }
+                const int m2 = (s + 1) % 3;
+                const double a11 = dc[s][0], a12 = dc[s][1], a21 = dc[m2][0], a22 = dc[m2][1];
+                const double det = a11 * a22 - a12 * a21;
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double gcomp;
+                    if (fabs(det) < 1e-12)
+                        gcomp = Xi[v][l];
+                    else if (l == 0)
+                        gcomp = (a22 * rem[s][v] - a12 * rem[m2][v]) / det;
+                    else
+                        gcomp = (a11 * rem[m2][v] - a21 * rem[s][v]) / det;
+                    cand[s + 1][v] = gcomp * ihi;
+                }
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) cand[0][v] = Xi[v][l] * ihi;
+            limit_vec(cand, w1, ok, cv, cb, out);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Xi[v][l] = out[v] * hi;
+        }
+#pragma unroll
         for (int v = 0; v < 4; ++v)
-            rem[n][v] = (a.W[(int64_t)v * nt + nb[n]] - Wi[v]) - (Xl[v][2] * a3 + Xl[v][3] * a4 + Xl[v][4] * a5);
-    }
-    // candidates: with three neighbours the plane through each neighbour
-    // pair (weighing the pair's mean weight); in a wall cell the gradient
-    // along each neighbour's direction alone
-    double w1[4];
-    w1[0] = w[0];
-    double gx[3][4], gy[3][4];
-    for (int n = 0; n < J; ++n) {
-        if (J < 3) {
-            w1[n + 1] = w[n + 1];
-            const double dd = dc[n][0] * dc[n][0] + dc[n][1] * dc[n][1];
-            for (int v = 0; v < 4; ++v) {
-                gx[n][v] = rem[n][v] * dc[n][0] / dd;
-                gy[n][v] = rem[n][v] * dc[n][1] / dd;
-            }
-            continue;
-        }
-        const int m2 = (n + 1) % J;
-        w1[n + 1] = 0.5 * (w[n + 1] + w[m2 + 1]);
-        const double a11 = dc[n][0], a12 = dc[n][1], a21 = dc[m2][0], a22 = dc[m2][1];
-        const double det = a11 * a22 - a12 * a21;
-        for (int v = 0; v < 4; ++v) {
-            if (fabs(det) < 1e-12) {
-                gx[n][v] = Xi[v][0];
-                gy[n][v] = Xi[v][1];
-            } else {
-                gx[n][v] = (a22 * rem[n][v] - a12 * rem[m2][v]) / det;
-                gy[n][v] = (a11 * rem[m2][v] - a21 * rem[n][v]) / det;
-            }
-        }
-    }
-    for (int l = 0; l < 2; ++l) {
-        for (int v = 0; v < 4; ++v) {
-            cand[0][v] = Xi[v][l] * ihi;
-            for (int n = 0; n < J; ++n) cand[n + 1][v] = (l == 0 ? gx[n][v] : gy[n][v]) * ihi;
-        }
-        limit_vec(cand, w1, J + 1, cv, Lm, Rm, out);
-        for (int v = 0; v < 4; ++v) Xl[v][l] = out[v] * hi;
-    }
 #pragma unroll
-    for (int v = 0; v < 4; ++v)
+            for (int l = 0; l < 5; ++l) a.lbuf[(int64_t)(v * 5 + l) * nt + k] = Xi[v][l];
+    }
+}
+
+// Limited coefficients of the listed cells into their places in dst.
+__global__ void __launch_bounds__(TPB) k_limit_scatter(LimArgs a) {
+    const int cnt = *a.count;
+    const int nt = a.nt;
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
+        const int i = a.list[k];
 #pragma unroll
-        for (int l = 0; l < 5; ++l) a.Xout[(int64_t)(v * 5 + l) * nt + i] = Xl[v][l];
+        for (int l = 0; l < 20; ++l) a.dst[(int64_t)l * nt + i] = a.lbuf[(int64_t)l * nt + k];
+    }
 }
 
 static inline void check_launch(int kc) {
@@ -1849,8 +1946,8 @@ void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn) {
                                        m->d.cface, m->d.area, W, F, Wn, m->prm.gamma, m->w.counters + 1));
 }
 
-void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold, int variables,
-                  int32_t* count) {
+void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, double* dst, double threshold,
+                  int variables, int32_t* count) {
     LimArgs a;
     a.nt = m->d.nt;
     a.nf = m->d.nf;
@@ -1863,17 +1960,26 @@ void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xout, d
     a.cgeo = m->d.cgeo;
     a.W = W;
     a.X = X;
-    a.Xout = Xout;
+    a.Xcopy = Xcopy;
     a.gamma = m->prm.gamma;
     a.threshold = threshold;
     a.all_quadratic = m->prm.all_quadratic;
     a.charvars = variables == GKS_LIMIT_CHARACTERISTIC;
     a.count = count;
-    // bytes of the common case (cell not limited): own W, X and moments, its
-    // neighbour slots and offsets; per neighbour its density polynomial and
-    // geometry; X written
-    const double by = (double)a.nt * (4 * 8.0 + 20 * 8.0 + 32.0 + 12.0 + 6 * 8.0 + 3 * (8.0 + 5 * 8.0 + 4 * 8.0) + 20 * 8.0);
-    PROFB(KC_LIMIT, by, hipLaunchKernelGGL(k_limit, dim3(nblocks(a.nt)), dim3(TPB), 0, m->stream, a));
+    a.list = m->w.lim_list;
+    a.lbuf = m->w.lim_buf;
+    a.dst = dst;
+    // unique bytes per cell (a neighbour's data is the same array element as
+    // that cell's own): density average and its five coefficients, h and the
+    // moments, neighbour slots and offsets; plus the copy of X if asked
+    const double by = (double)a.nt * (8.0 + 40.0 + 32.0 + 12.0 + 48.0 + (Xcopy ? 320.0 : 0.0));
+    PROFB(KC_LIMIT, by, hipLaunchKernelGGL(k_limit_mark, dim3(nblocks(a.nt)), dim3(TPB), 0, m->stream, a));
+    // the limited cells are few and their work is arithmetic: a fixed grid
+    // of one-wave blocks strides over the list
+    const int nb = std::max(1, std::min(2048, nblocks(a.nt, 64)));
+    PROF(KC_LIMIT_APPLY, hipLaunchKernelGGL(k_limit_apply, dim3(nb), dim3(64), 0, m->stream, a));
+    PROF(KC_LIMIT_APPLY, hipLaunchKernelGGL(k_limit_scatter, dim3(std::min(256, nblocks(a.nt))), dim3(TPB), 0,
+                                            m->stream, a));
 }
 
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out) {

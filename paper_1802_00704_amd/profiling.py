@@ -34,7 +34,8 @@ CLASS_OF = [
     (r"k_sum_partials", "finalize"), (r"k_gmres_ctl", "misc"), (r"k_mask_cols", "misc"),
     (r"k_copyout", "copyout"), (r"k_rhs", "rhs"), (r"k_flux", "flux"), (r"k_update", "update"),
     (r"k_cfl", "cfl"), (r"k_copyout", "copyout"), (r"k_copyin", "misc"), (r"k_copy", "copy"), (r"k_extrap", "extrap"),
-    (r"k_limit", "limit"), (r"k_es_fwd", "ilu_fwd32"), (r"k_es_bwd", "ilu_bwd32"),
+    (r"k_limit_mark", "limit"), (r"k_limit_apply", "limit_apply"), (r"k_limit_scatter", "limit_apply"),
+    (r"k_es_fwd", "ilu_fwd32"), (r"k_es_bwd", "ilu_bwd32"),
 ]
 
 
