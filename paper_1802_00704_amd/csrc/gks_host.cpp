@@ -503,6 +503,9 @@ struct HostSystem {
     // the split form (K_L blocks in L's slots, E = D - K_D per row).
     bool tri_free = false;
     std::vector<double> KLval, Ev;
+    // split form, rows scaled by their pivot inverse: Dinv_i K_ik (k < i),
+    // Dinv_i K_ij (j > i), Dinv_i E_i
+    std::vector<double> KLs, KUs, Gs;
     std::vector<int32_t> Kcol, nbc, iperm, Lcol, Ucol;
     std::vector<int32_t> own, nbr, cface, bck;
     std::vector<double> fgeo, gpd, cgeo, bcs;
@@ -817,6 +820,29 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
                 }
         S.tri_free = !tri;
     }
+    if (S.tri_free) {
+        // without fill U = K_U, so the split form's blocks are K_L, K_U, E
+        // scaled from the left by the row's pivot inverse
+        S.KLs.assign((size_t)LW * 25 * n, 0.0);
+        S.KUs.assign((size_t)LW * 25 * n, 0.0);
+        S.Gs.assign((size_t)25 * n, 0.0);
+        auto scale = [&](const std::vector<double>& src, std::vector<double>& dst, int slots, int i) {
+            for (int s2 = 0; s2 < slots; ++s2)
+                for (int r = 0; r < 5; ++r)
+                    for (int c = 0; c < 5; ++c) {
+                        double t = 0.0;
+                        for (int q = 0; q < 5; ++q)
+                            t += Dv[(size_t)(5 * r + q) * n + i] * src[((size_t)s2 * 25 + 5 * q + c) * n + i];
+                        dst[((size_t)s2 * 25 + 5 * r + c) * n + i] = t;
+                    }
+        };
+#pragma omp parallel for schedule(static)
+        for (int i = 0; i < n; ++i) {
+            scale(S.KLval, S.KLs, LW, i);
+            scale(Uval, S.KUs, LW, i);
+            scale(S.Ev, S.Gs, 1, i);
+        }
+    }
     pt.mark("BILU(0)");
     // ---- face / cell arrays in device layout
     std::vector<int32_t>& own = S.own;
@@ -931,15 +957,16 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
                 for (int s2 = 0; s2 < KW; ++s2) d.lev_Kb[l] += S.Kcol[(size_t)s2 * n + i] != n ? 1.0 : 0.0;
         if (prm.precision == GKS_MIXED) {
             d.split = S.tri_free;
-            // split form: K_L in L's slots; general form: L itself
-            d.Lval32 = dev_upload(m, pack_sliced<float>(d.split ? S.KLval : S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr));
-            d.Uval32 = dev_upload(m, pack_sliced<float>(S.Uval, S.Ucol, n, S.lev_ptr, Us, nullptr));
+            // split form: Dinv K_L and Dinv K_U in L's and U's slots; general
+            // form: the factors L and U themselves
+            d.Lval32 = dev_upload(m, pack_sliced<float>(d.split ? S.KLs : S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr));
+            d.Uval32 = dev_upload(m, pack_sliced<float>(d.split ? S.KUs : S.Uval, S.Ucol, n, S.lev_ptr, Us, nullptr));
         }
     }
     d.Dinv = dev_upload(m, pack_blocks<double>(S.Dv, 1, n, np));
     if (prm.precision == GKS_MIXED) {
         if (d.split)
-            d.E32 = dev_upload(m, pack_blocks<float>(S.Ev, 1, n, np));
+            d.E32 = dev_upload(m, pack_blocks<float>(S.Gs, 1, n, np));   // Dinv E
         else
             d.Kval32 = dev_upload(m, pack_blocks<float>(S.Kval, KW, n, np));
         d.Dinv32 = dev_upload(m, pack_blocks<float>(S.Dv, 1, n, np));

@@ -112,10 +112,10 @@ struct DevMesh {
     double* Uval = nullptr;       // sliced [chunk][25 * 64] strict upper factor blocks
     SlicedIdx Li{}, Ui{};         // their column indices and slice tables
     double* Dinv = nullptr;       // [25][np] inverted pivot blocks
-    float* Lval32 = nullptr;      // sliced FP32: L, or K_L in the split form
-    float* Uval32 = nullptr;      // sliced FP32: U (= K_U in the split form)
+    float* Lval32 = nullptr;      // sliced FP32: L, or Dinv K_L in the split form
+    float* Uval32 = nullptr;      // sliced FP32: U, or Dinv K_U (U = K_U) in the split form
     float* Dinv32 = nullptr;
-    float* E32 = nullptr;         // split form: [25][np] D - K_D
+    float* E32 = nullptr;         // split form: [25][np] Dinv (D - K_D)
     bool split = false;           // mixed inner sweeps in the split form (cell graph without 3-cycles)
     std::vector<int32_t> lev_ptr; // host: rows of level l are [lev_ptr[l], lev_ptr[l+1])
     std::vector<int32_t> Lsbase, Usbase;  // host: first slice of each level

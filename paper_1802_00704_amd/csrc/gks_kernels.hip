@@ -530,10 +530,13 @@ __global__ void __launch_bounds__(TPB) k_mx_bwd(int np, int r0, int r1, int sbas
 // strict block triangles of K.  The Richardson sweep z <- z + M^-1 (b - K z)
 // is then  (D + K_L) w = b + E z + K_L D^-1 K_U z,  (D + K_U) z' = D w,
 // E = D - K_D, and the previous backward solve gives D^-1 K_U z = w_prev - z
-// (Eisenstat's observation), so no product with all of K is needed:
-//   forward  w_i = Dinv_i (b_i + E_i z_i - sum_{k<i} K_ik t_k),
+// (Eisenstat's observation), so no product with all of K is needed.  The
+// blocks are stored scaled from the left by the row's pivot inverse
+// (L'_ik = Dinv_i K_ik, U'_ij = Dinv_i K_ij, G_i = Dinv_i E_i) and the first
+// sweep keeps b'_i = Dinv_i b_i, so later sweeps never touch Dinv:
+//   forward  w_i = b'_i + G_i z_i - sum_{k<i} L'_ik t_k,
 //            t_i = w_i - w_prev_i + z_i           (first sweep: z = 0, t = w)
-//   backward z'_i = w_i - Dinv_i sum_{j>i} K_ij z'_j
+//   backward z'_i = w_i - sum_{j>i} U'_ij z'_j
 // The last level has no upper neighbours (z'_i = w_i, set by the forward
 // kernel); the backward kernel of level 0 can also run the next sweep's
 // forward for its rows, which have no lower neighbours (BF).
@@ -550,9 +553,20 @@ __device__ __forceinline__ void block_mul(float (&out)[CB], const float (&blk)[2
         }
 }
 
+// acc += blk x (x FP32)
+template <typename ACC>
+__device__ __forceinline__ void block_add(ACC (&acc)[CB], const float (&blk)[25], const float (&x)[CB]) {
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+#pragma unroll
+            for (int q = 0; q < NB; ++q) acc[c * NB + r] += (ACC)blk[r * NB + q] * (ACC)x[c * NB + q];
+}
+
 template <bool FIRST, bool LAST, typename ACC>
 __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, SlicedIdx Li,
-                                                const float* __restrict__ KLv, const float* __restrict__ E,
+                                                const float* __restrict__ KLv, const float* __restrict__ G,
                                                 const float* __restrict__ Dinv, const double* __restrict__ v,
                                                 const double* __restrict__ vscale, float* __restrict__ b,
                                                 float* __restrict__ t, float* __restrict__ w,
@@ -566,15 +580,21 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
     float zi[CB];
     if (FIRST) {
         const double* vi = v + (int64_t)i * CB;
+        ACC x[CB];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double sc = vscale[c];
 #pragma unroll
-            for (int r = 0; r < NB; ++r) {
-                const float x = (float)(sc * vi[c * NB + r]);
-                bi[c * NB + r] = x;
-                acc[c * NB + r] = (ACC)x;
-            }
+            for (int r = 0; r < NB; ++r) x[c * NB + r] = (ACC)(float)(sc * vi[c * NB + r]);
+        }
+        float db[25];
+        load_block(Dinv, np, 0, i, db);
+        float bs[CB];
+        block_mul(bs, db, x);
+#pragma unroll
+        for (int q = 0; q < CB; ++q) {
+            bi[q] = bs[q];
+            acc[q] = (ACC)bs[q];
         }
     } else {
         const float* zp = z + (int64_t)i * CB;
@@ -583,20 +603,14 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
             zi[q] = zp[q];
             acc[q] = (ACC)bi[q];
         }
-        float eb[25];
-        load_block(E, np, 0, i, eb);
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int q = 0; q < NB; ++q) acc[c * NB + r] += (ACC)eb[r * NB + q] * (ACC)zi[c * NB + q];
+        float gb[25];
+        load_block(G, np, 0, i, gb);
+        block_add(acc, gb, zi);
     }
     slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), FIRST ? w : t);
-    float db[25];
-    load_block(Dinv, np, 0, i, db);
     float wi[CB];
-    block_mul(wi, db, acc);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) wi[q] = (float)acc[q];
     float* wp = w + (int64_t)i * CB;
     if (!FIRST && !LAST) {
         float* tp = t + (int64_t)i * CB;
@@ -614,53 +628,44 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
 
 template <bool BF, typename ACC>
 __global__ void __launch_bounds__(TPB) k_es_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
-                                                const float* __restrict__ KUv, const float* __restrict__ E,
-                                                const float* __restrict__ Dinv, const float* __restrict__ b,
-                                                float* __restrict__ t, float* __restrict__ w,
-                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
+                                                const float* __restrict__ KUv, const float* __restrict__ G,
+                                                const float* __restrict__ b, float* __restrict__ t,
+                                                float* __restrict__ w, float* __restrict__ z,
+                                                const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     const int rl = xcd_row();
     const int i = r0 + rl;
     if (i >= r1) return;
-    ACC acc[CB];
-#pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = 0;
-    slice_sub(acc, KUv, Ui.col, slice_ref(Ui, sbase, rl), z);   // acc = -sum K_ij z'_j
-    float db[25];
-    load_block(Dinv, np, 0, i, db);
-    float u[CB];
-    block_mul(u, db, acc);
     float* wp = w + (int64_t)i * CB;
-    float wi[CB], zn[CB];
+    float wi[CB];
+    ACC acc[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) {
         wi[q] = wp[q];
-        zn[q] = wi[q] + u[q];
+        acc[q] = (ACC)wi[q];
     }
+    slice_sub(acc, KUv, Ui.col, slice_ref(Ui, sbase, rl), z);   // acc = w_i - sum U'_ij z'_j
+    float zn[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) zn[q] = (float)acc[q];
     float* zp = z + (int64_t)i * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) zp[q] = zn[q];
     if (BF) {
         // next sweep, forward, for a row without lower neighbours
         const float* bi = b + (int64_t)i * CB;
-        float eb[25];
-        load_block(E, np, 0, i, eb);
+        float gb[25];
+        load_block(G, np, 0, i, gb);
         ACC a2[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) a2[q] = (ACC)bi[q];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r)
-#pragma unroll
-                for (int q = 0; q < NB; ++q) a2[c * NB + r] += (ACC)eb[r * NB + q] * (ACC)zn[c * NB + q];
-        float w2[CB];
-        block_mul(w2, db, a2);
+        block_add(a2, gb, zn);
         float* tp = t + (int64_t)i * CB;
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
-            tp[q] = w2[q] - wi[q] + zn[q];
-            wp[q] = w2[q];
+            const float w2 = (float)a2[q];
+            tp[q] = w2 - wi[q] + zn[q];
+            wp[q] = w2;
         }
     }
 }
@@ -1768,8 +1773,10 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         if (r1 <= r0) return;
         const int rows = r1 - r0;
         const bool last = l == nl - 1;
-        // blocks: K_L, Dinv (+ E); vectors: b (v when first), w, t, z
-        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + 2 * VF : 100.0 + 3 * VF)) +
+        // blocks: Dinv K_L, and Dinv (first sweep) or Dinv E; vectors: v and
+        // b' written (first) or b', z read, w written; w_prev, t (middle
+        // levels), z (last level)
+        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + 2 * VF : 3 * VF)) +
                           rows * VF * ((last ? 1 : 0) + (!first && !last ? 2 : 0));
         const dim3 g(nblocks(rows)), bl(TPB);
         if (first && last)
@@ -1789,15 +1796,16 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) return;
         const int rows = r1 - r0;
-        // blocks: K_U, Dinv (+ E); vectors: w, z (+ b, t, w)
-        const double by = D.lev_Ub[l] * 104.0 + rows * (100.0 + 2 * VF) + (bf ? rows * (100.0 + 3 * VF) : 0.0);
+        // blocks: Dinv K_U (+ Dinv E); vectors: w read, z written (+ b' read,
+        // t and w written)
+        const double by = D.lev_Ub[l] * 104.0 + rows * 2 * VF + (bf ? rows * (100.0 + 3 * VF) : 0.0);
         const dim3 g(nblocks(rows)), bl(TPB);
         if (bf)
             PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, D.Dinv32, b, t, w, z, gate));
+                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, b, t, w, z, gate));
         else
             PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, D.Dinv32, b, t, w, z, gate));
+                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, b, t, w, z, gate));
     };
     for (int sw = 0; sw < q; ++sw) {
         const bool first = sw == 0;
