@@ -564,6 +564,47 @@ __device__ __forceinline__ void block_add(ACC (&acc)[CB], const float (&blk)[25]
             for (int q = 0; q < NB; ++q) acc[c * NB + r] += (ACC)blk[r * NB + q] * (ACC)x[c * NB + q];
 }
 
+// Row-major [.][CB] vectors of a wave's rows [i0, i0 + nr) pass through the
+// wave's LDS area: lanes copy 16-byte chunks lane-contiguously to or from
+// global memory, and each lane reads or writes its own row in LDS.  Every
+// lane of the wave must take part (rows past nr are neither read nor
+// written in global memory).
+template <typename T>
+__device__ __forceinline__ void rows_load(const T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
+                                          T (&v)[CB]) {
+    constexpr int K = CB * (int)sizeof(T) / 16;   // 16-byte chunks per row
+    const float4* src = reinterpret_cast<const float4*>(a + i0 * CB);
+    const int nc = nr * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = k * 64 + lane;
+        if (c < nc) st[c] = src[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const T* my = reinterpret_cast<const T*>(st + lane * K);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) v[q] = my[q];
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ void rows_store(T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
+                                           const T (&v)[CB]) {
+    constexpr int K = CB * (int)sizeof(T) / 16;
+    T* my = reinterpret_cast<T*>(st + lane * K);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) my[q] = v[q];
+    __builtin_amdgcn_wave_barrier();
+    float4* dst = reinterpret_cast<float4*>(a + i0 * CB);
+    const int nc = nr * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = k * 64 + lane;
+        if (c < nc) dst[c] = st[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 template <bool FIRST, bool LAST, typename ACC>
 __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, SlicedIdx Li,
                                                 const float* __restrict__ KLv, const float* __restrict__ G,
@@ -572,14 +613,21 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
                                                 float* __restrict__ t, float* __restrict__ w,
                                                 float* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
+    constexpr int SK = FIRST ? 2 * CB / 4 : CB / 4;   // 16-byte chunks per staged row (FP64 v first)
+    __shared__ float4 stage[TPB / 64][64 * SK];
     const int rl = xcd_row();
-    const int i = r0 + rl;
-    if (i >= r1) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)r0 + rl - lane;       // first row of the wave
+    if (i0 >= r1) return;                              // the whole wave is past the level
+    const int nr = (int)min((int64_t)64, (int64_t)r1 - i0);
+    const bool valid = lane < nr;
+    const int i = (int)i0 + lane;
+    float4* st = stage[threadIdx.x >> 6];
     ACC acc[CB];
-    float* bi = b + (int64_t)i * CB;
     float zi[CB];
     if (FIRST) {
-        const double* vi = v + (int64_t)i * CB;
+        double vi[CB];
+        rows_load(v, i0, nr, st, lane, vi);
         ACC x[CB];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -587,43 +635,42 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
 #pragma unroll
             for (int r = 0; r < NB; ++r) x[c * NB + r] = (ACC)(float)(sc * vi[c * NB + r]);
         }
-        float db[25];
-        load_block(Dinv, np, 0, i, db);
         float bs[CB];
-        block_mul(bs, db, x);
 #pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            bi[q] = bs[q];
-            acc[q] = (ACC)bs[q];
+        for (int q = 0; q < CB; ++q) bs[q] = 0.0f;
+        if (valid) {
+            float db[25];
+            load_block(Dinv, np, 0, i, db);
+            block_mul(bs, db, x);
         }
+        rows_store(b, i0, nr, st, lane, bs);
+#pragma unroll
+        for (int q = 0; q < CB; ++q) acc[q] = (ACC)bs[q];
     } else {
-        const float* zp = z + (int64_t)i * CB;
+        float bl[CB];
+        rows_load(z, i0, nr, st, lane, zi);
+        rows_load(b, i0, nr, st, lane, bl);
 #pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            zi[q] = zp[q];
-            acc[q] = (ACC)bi[q];
+        for (int q = 0; q < CB; ++q) acc[q] = (ACC)bl[q];
+        if (valid) {
+            float gb[25];
+            load_block(G, np, 0, i, gb);
+            block_add(acc, gb, zi);
         }
-        float gb[25];
-        load_block(G, np, 0, i, gb);
-        block_add(acc, gb, zi);
     }
-    slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), FIRST ? w : t);
+    if (valid) slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), FIRST ? w : t);
     float wi[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) wi[q] = (float)acc[q];
-    float* wp = w + (int64_t)i * CB;
     if (!FIRST && !LAST) {
-        float* tp = t + (int64_t)i * CB;
+        float wprev[CB], ti[CB];
+        rows_load(w, i0, nr, st, lane, wprev);
 #pragma unroll
-        for (int q = 0; q < CB; ++q) tp[q] = wi[q] - wp[q] + zi[q];
+        for (int q = 0; q < CB; ++q) ti[q] = wi[q] - wprev[q] + zi[q];
+        rows_store(t, i0, nr, st, lane, ti);
     }
-#pragma unroll
-    for (int q = 0; q < CB; ++q) wp[q] = wi[q];
-    if (LAST) {
-        float* zp = z + (int64_t)i * CB;
-#pragma unroll
-        for (int q = 0; q < CB; ++q) zp[q] = wi[q];
-    }
+    rows_store(w, i0, nr, st, lane, wi);
+    if (LAST) rows_store(z, i0, nr, st, lane, wi);
 }
 
 template <bool BF, typename ACC>
@@ -633,40 +680,45 @@ __global__ void __launch_bounds__(TPB) k_es_bwd(int np, int r0, int r1, int sbas
                                                 float* __restrict__ w, float* __restrict__ z,
                                                 const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
+    __shared__ float4 stage[TPB / 64][64 * CB / 4];
     const int rl = xcd_row();
-    const int i = r0 + rl;
-    if (i >= r1) return;
-    float* wp = w + (int64_t)i * CB;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)r0 + rl - lane;
+    if (i0 >= r1) return;
+    const int nr = (int)min((int64_t)64, (int64_t)r1 - i0);
+    const bool valid = lane < nr;
+    const int i = (int)i0 + lane;
+    float4* st = stage[threadIdx.x >> 6];
     float wi[CB];
+    rows_load(w, i0, nr, st, lane, wi);
     ACC acc[CB];
 #pragma unroll
-    for (int q = 0; q < CB; ++q) {
-        wi[q] = wp[q];
-        acc[q] = (ACC)wi[q];
-    }
-    slice_sub(acc, KUv, Ui.col, slice_ref(Ui, sbase, rl), z);   // acc = w_i - sum U'_ij z'_j
+    for (int q = 0; q < CB; ++q) acc[q] = (ACC)wi[q];
+    if (valid) slice_sub(acc, KUv, Ui.col, slice_ref(Ui, sbase, rl), z);   // acc = w_i - sum U'_ij z'_j
     float zn[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) zn[q] = (float)acc[q];
-    float* zp = z + (int64_t)i * CB;
-#pragma unroll
-    for (int q = 0; q < CB; ++q) zp[q] = zn[q];
+    rows_store(z, i0, nr, st, lane, zn);
     if (BF) {
         // next sweep, forward, for a row without lower neighbours
-        const float* bi = b + (int64_t)i * CB;
-        float gb[25];
-        load_block(G, np, 0, i, gb);
+        float bi[CB];
+        rows_load(b, i0, nr, st, lane, bi);
         ACC a2[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) a2[q] = (ACC)bi[q];
-        block_add(a2, gb, zn);
-        float* tp = t + (int64_t)i * CB;
+        if (valid) {
+            float gb[25];
+            load_block(G, np, 0, i, gb);
+            block_add(a2, gb, zn);
+        }
+        float w2[CB], ti[CB];
 #pragma unroll
         for (int q = 0; q < CB; ++q) {
-            const float w2 = (float)a2[q];
-            tp[q] = w2 - wi[q] + zn[q];
-            wp[q] = w2;
+            w2[q] = (float)a2[q];
+            ti[q] = w2[q] - wi[q] + zn[q];
         }
+        rows_store(t, i0, nr, st, lane, ti);
+        rows_store(w, i0, nr, st, lane, w2);
     }
 }
 
