@@ -33,6 +33,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "cell-steps/s at 1M tris, mixed vs FP64 at resid 1e-10; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6      # MI355X FP64 vector peak
 FP64_VALU_PEAK_TFLOPS = 78.6
 
 
@@ -160,6 +161,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
 
 
 TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "gks_solver_hbm_traffic_shock_vortex_1m.txt")
+FP64_SUMMARY = os.path.join(ROOT, "profiles", "gks_fp64_flops_shock_vortex_1m.txt")
 
 
 def measured_traffic(kernel_class: str):
@@ -173,6 +175,33 @@ def measured_traffic(kernel_class: str):
     if sha != kernel_sources_sha256():
         return None
     return table.get(kernel_class)
+
+
+def measured_flops(kernel_class: str):
+    """FP64 FLOPs per launch of a kernel class from the committed counter
+    summary, or None when the kernels changed since the counters were taken."""
+    try:
+        from paper_1802_00704_amd.profiling import kernel_sources_sha256, read_summary
+        sha, table = read_summary(FP64_SUMMARY, column=2, ncols=8)
+    except (OSError, ImportError):
+        return None
+    if sha != kernel_sources_sha256():
+        return None
+    return table.get(kernel_class)
+
+
+def flux_fp64(prof: dict):
+    """FP64 VALU roofline of the flux kernel: counted FLOPs per launch over
+    the live average launch duration."""
+    d = prof.get("flux") if prof else None
+    fl = measured_flops("flux")
+    if not d or d["ms"] <= 0 or not fl:
+        return None
+    us = d["ms"] * 1e3 / max(1, d["launches"])
+    achieved = fl / (us * 1e-6) / 1e12
+    return {"bound": "fp64_valu", "kernel": "flux", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "avg_launch_us": round(us, 2),
+            "flop_per_launch": fl}
 
 
 def roofline(prof: dict, elapsed_s: float):
@@ -296,6 +325,7 @@ def main():
                    else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from the last three solutions",
                    "cells": m.nt},
         "roofline": roofline(r["profile"], r["profiled_elapsed_s"]),
+        "flux_fp64": flux_fp64(r["profile"]),
         "cpu_baseline": cpu,
         "forms": {f: {k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")}
                   for f in forms},

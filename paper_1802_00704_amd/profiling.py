@@ -11,6 +11,14 @@ the same counter reads for the library's plain copy kernel ``k_copy``, whose
 bytes are known exactly (8 bytes read and 8 written per element of its
 grid).  The output also carries a SHA-256 of the kernel sources, so a reader
 can tell whether the figures still describe the current kernels.
+
+    python -m paper_1802_00704_amd.profiling --fp64 <csv_dir>
+
+does the same for one counter run of SQ_INSTS_VALU_FLOPS_FP64,
+SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 and SQ_INSTS_VALU: per kernel class,
+FP64 FLOPs per launch.  The FLOPS counter adds 2 per FMA and 1 per other
+FP64 instruction of a wave; times 64 lanes it gives the FLOPs of full
+waves (an upper bound where lanes are inactive).
 """
 from __future__ import annotations
 
@@ -90,7 +98,43 @@ def traffic(fetch_dir: str, write_dir: str) -> dict:
     return {"calibration": {"fetch": cf, "write": cw}, "classes": out}
 
 
+FP64_COUNTERS = ("SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64",
+                 "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64", "SQ_INSTS_VALU")
+
+
+def fp64(csv_dir: str) -> dict:
+    """{class: {counter: mean value per launch, "launches": n}}"""
+    out = collections.OrderedDict()
+    for counter in FP64_COUNTERS:
+        acc = collections.defaultdict(list)
+        for n, _, v in _load(csv_dir, counter):
+            cls = kernel_class(n)
+            if cls:
+                acc[cls].append(v)
+        for cls, vals in acc.items():
+            out.setdefault(cls, {})[counter] = sum(vals) / len(vals)
+            out[cls]["launches"] = len(vals)
+    return out
+
+
+def main_fp64(csv_dir: str) -> int:
+    t = fp64(csv_dir)
+    print("kernel_sources_sha256 %s" % kernel_sources_sha256())
+    print("%-12s %8s %16s %13s %13s %13s %11s %13s" % ("class", "launches", "fp64_flop/launch", "fma_f64",
+                                                        "add_f64", "mul_f64", "trans_f64", "valu_insts"))
+    for cls, d in t.items():
+        if d.get("SQ_INSTS_VALU_FLOPS_FP64", 0.0) <= 0.0:
+            continue
+        print("%-12s %8d %16.0f %13.0f %13.0f %13.0f %11.0f %13.0f" % (
+            cls, d["launches"], 64.0 * d["SQ_INSTS_VALU_FLOPS_FP64"], d.get("SQ_INSTS_VALU_FMA_F64", 0.0),
+            d.get("SQ_INSTS_VALU_ADD_F64", 0.0), d.get("SQ_INSTS_VALU_MUL_F64", 0.0),
+            d.get("SQ_INSTS_VALU_TRANS_F64", 0.0), d.get("SQ_INSTS_VALU", 0.0)))
+    return 0
+
+
 def main(argv):
+    if len(argv) == 3 and argv[1] == "--fp64":
+        return main_fp64(argv[2])
     if len(argv) != 3:
         print(__doc__)
         return 2
@@ -104,16 +148,18 @@ def main(argv):
     return 0
 
 
-def read_summary(path: str) -> tuple[str, dict]:
-    """(sha256, {class: traffic bytes per launch}) from a committed summary."""
+def read_summary(path: str, column: int = 4, ncols: int = 5) -> tuple[str, dict]:
+    """(sha256, {class: value}) from a committed summary: the traffic bytes
+    per launch (defaults), or with column=2, ncols=8 the FP64 FLOPs per
+    launch of the --fp64 table."""
     sha, table = "", {}
     for line in open(path):
         parts = line.split()
         if len(parts) == 2 and parts[0] == "kernel_sources_sha256":
             sha = parts[1]
-        elif len(parts) == 5 and not line.startswith("#") and parts[0] != "class":
+        elif len(parts) == ncols and not line.startswith("#") and parts[0] != "class":
             try:
-                table[parts[0]] = float(parts[4])
+                table[parts[0]] = float(parts[column])
             except ValueError:
                 pass
     return sha, table
