@@ -139,6 +139,47 @@ __global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__
     if (partial) block_sumsq4(sq, partial);
 }
 
+// Row-major [.][CB] vectors of a wave's rows [i0, i0 + nr) pass through the
+// wave's LDS area: lanes copy 16-byte chunks lane-contiguously to or from
+// global memory, and each lane reads or writes its own row in LDS.  Every
+// lane of the wave must take part (rows past nr are neither read nor
+// written in global memory).
+template <typename T>
+__device__ __forceinline__ void rows_load(const T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
+                                          T (&v)[CB]) {
+    constexpr int K = CB * (int)sizeof(T) / 16;   // 16-byte chunks per row
+    const float4* src = reinterpret_cast<const float4*>(a + i0 * CB);
+    const int nc = nr * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = k * 64 + lane;
+        if (c < nc) st[c] = src[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+    const T* my = reinterpret_cast<const T*>(st + lane * K);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) v[q] = my[q];
+    __builtin_amdgcn_wave_barrier();
+}
+
+template <typename T>
+__device__ __forceinline__ void rows_store(T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
+                                           const T (&v)[CB]) {
+    constexpr int K = CB * (int)sizeof(T) / 16;
+    T* my = reinterpret_cast<T*>(st + lane * K);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) my[q] = v[q];
+    __builtin_amdgcn_wave_barrier();
+    float4* dst = reinterpret_cast<float4*>(a + i0 * CB);
+    const int nc = nr * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = k * 64 + lane;
+        if (c < nc) dst[c] = st[c];
+    }
+    __builtin_amdgcn_wave_barrier();
+}
+
 // ------------------------------------------------------------------ SpMV
 // y = K (s .* x)   or   y = b - K x   (RESID), block-ELL, thread per row.
 // In RESID mode xscale (when not null) scales b instead: y = s .* b - K x.
@@ -151,16 +192,19 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict
                                               const double* __restrict__ b, double* __restrict__ y,
     const int32_t* __restrict__ gate, double* __restrict__ partial = nullptr) {
     if (gate && *gate == 0) return;
+    __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
     const int i = xcd_row();
-    const bool valid = i < n;
-    if (!valid && !(RESID && partial)) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)i - lane;                  // first row of the wave
+    const int nr = (int)max((int64_t)0, min((int64_t)64, (int64_t)n - i0));
+    if (nr == 0 && !(RESID && partial)) return;            // the whole wave is past the rows
+    const bool valid = lane < nr;
+    float4* st = stage[threadIdx.x >> 6];
     double sq[NC] = {0.0, 0.0, 0.0, 0.0};
+    double acc[CB];
+#pragma unroll
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
     if (valid) {
-        double acc[NC][NB];
-#pragma unroll
-        for (int c = 0; c < NC; ++c)
-#pragma unroll
-            for (int r = 0; r < NB; ++r) acc[c][r] = 0.0;
 #pragma unroll
         for (int s = 0; s < KW; ++s) {
             const int j = col[(int64_t)s * n + i];
@@ -175,31 +219,32 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict
 #pragma unroll
                 for (int r = 0; r < NB; ++r)
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) acc[c][r] += (double)blk[r * NB + q] * xv[c * NB + q];
-        }
-        double* yi = y + (int64_t)i * CB;
-        if (RESID) {
-            const double* bi = b + (int64_t)i * CB;
-#pragma unroll
-            for (int c = 0; c < NC; ++c) {
-                const double sc = xscale ? xscale[c] : 1.0;
-#pragma unroll
-                for (int r = 0; r < NB; ++r) {
-                    const double v = sc * bi[c * NB + r] - acc[c][r];
-                    yi[c * NB + r] = v;
-                    sq[c] += v * v;
-                }
-            }
-        } else {
-            double sc[NC];
-#pragma unroll
-            for (int c = 0; c < NC; ++c) sc[c] = xscale ? xscale[c] : 1.0;
-#pragma unroll
-            for (int c = 0; c < NC; ++c)
-#pragma unroll
-                for (int r = 0; r < NB; ++r) yi[c * NB + r] = sc[c] * acc[c][r];
+                    for (int q = 0; q < NB; ++q) acc[c * NB + r] += (double)blk[r * NB + q] * xv[c * NB + q];
         }
     }
+    double out[CB];
+    if (RESID) {
+        double bi[CB];
+        rows_load(b, i0, nr, st, lane, bi);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double sc = xscale ? xscale[c] : 1.0;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const double v = sc * bi[c * NB + r] - acc[c * NB + r];
+                out[c * NB + r] = v;
+                if (valid) sq[c] += v * v;
+            }
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double sc = xscale ? xscale[c] : 1.0;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) out[c * NB + r] = sc * acc[c * NB + r];
+        }
+    }
+    if (nr > 0) rows_store(y, i0, nr, st, lane, out);
     if (RESID && partial) block_sumsq4(sq, partial);
 }
 
@@ -229,7 +274,9 @@ __device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int
 }
 
 // y = K x (FP64 K) and, in the same pass, the first Gram-Schmidt products
-// V_j . y for j < nvd <= RED_CHUNK (block partials to dpart).
+// V_j . y for j < nvd <= RED_CHUNK (block partials to dpart).  y leaves
+// through the wave's LDS area, and the products run over the wave's
+// contiguous rows in 16-byte pairs, so every V_j read is lane-contiguous.
 template <typename XT>
 __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* __restrict__ val,
                                                    const int32_t* __restrict__ col, const XT* __restrict__ x,
@@ -237,16 +284,21 @@ __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* 
                                                    int64_t vstride, int nvd, double* __restrict__ dpart,
                                                    const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
+    __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
     const int i = xcd_row();
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)i - lane;
+    const int nr = (int)max((int64_t)0, min((int64_t)64, (int64_t)n - i0));
+    float4* st = stage[threadIdx.x >> 6];
     double d[RED_CHUNK][NC];
 #pragma unroll
     for (int j = 0; j < RED_CHUNK; ++j)
 #pragma unroll
         for (int c = 0; c < NC; ++c) d[j][c] = 0.0;
-    if (i < n) {
-        double acc[CB];
+    double acc[CB];
 #pragma unroll
-        for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    for (int q = 0; q < CB; ++q) acc[q] = 0.0;
+    if (lane < nr) {
 #pragma unroll
         for (int s = 0; s < KW; ++s) {
             const int j = col[(int64_t)s * n + i];
@@ -263,17 +315,26 @@ __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* 
 #pragma unroll
                     for (int q = 0; q < NB; ++q) acc[c * NB + r] += blk[r * NB + q] * xv[c * NB + q];
         }
-        double* yi = y + (int64_t)i * CB;
+    }
+    if (nr > 0) {
+        rows_store(y, i0, nr, st, lane, acc);   // the staged y stays in LDS
+        const double2* ys = reinterpret_cast<const double2*>(st);
+        const int npair = nr * (CB / 2);
 #pragma unroll
-        for (int q = 0; q < CB; ++q) yi[q] = acc[q];
+        for (int k = 0; k < CB / 2; ++k) {
+            const int c = k * 64 + lane;   // pair c: elements 2c, 2c + 1 of the wave's rows
+            if (c >= npair) continue;
+            const int e = (2 * c) % CB;
+            const int c0 = e / NB, c1 = (e + 1) / NB;
+            const double2 yv = ys[c];
 #pragma unroll
-        for (int j = 0; j < RED_CHUNK; ++j) {
-            if (j < nvd) {
-                const double* vi = V + (int64_t)j * vstride + (int64_t)i * CB;
+            for (int j = 0; j < RED_CHUNK; ++j) {
+                if (j < nvd) {
+                    const double2 vv = reinterpret_cast<const double2*>(V + (int64_t)j * vstride + i0 * CB)[c];
 #pragma unroll
-                for (int c = 0; c < NC; ++c)
-#pragma unroll
-                    for (int l = 0; l < NB; ++l) d[j][c] += vi[c * NB + l] * acc[c * NB + l];
+                    for (int cc = 0; cc < NC; ++cc)
+                        d[j][cc] += (cc == c0 ? vv.x * yv.x : 0.0) + (cc == c1 ? vv.y * yv.y : 0.0);
+                }
             }
         }
     }
@@ -383,21 +444,23 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, Slic
                                                  const double* __restrict__ v, const double* __restrict__ vscale,
                                                  double* __restrict__ y, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
+    __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
     const int rl = xcd_row();
-    const int i = r0 + rl;
-    if (i >= r1) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)r0 + rl - lane;            // first row of the wave
+    if (i0 >= r1) return;                                   // the whole wave is past the level
+    const int nr = (int)min((int64_t)64, (int64_t)r1 - i0);
+    float4* st = stage[threadIdx.x >> 6];
     double acc[CB];
-    const double* vi = v + (int64_t)i * CB;
+    rows_load(v, i0, nr, st, lane, acc);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
         const double sc = vscale ? vscale[c] : 1.0;
 #pragma unroll
-        for (int r = 0; r < NB; ++r) acc[c * NB + r] = sc * vi[c * NB + r];
+        for (int r = 0; r < NB; ++r) acc[c * NB + r] *= sc;
     }
-    slice_sub(acc, Lv, Li.col, slice_ref(Li, sbase, rl), y);
-    double* yi = y + (int64_t)i * CB;
-#pragma unroll
-    for (int q = 0; q < CB; ++q) yi[q] = acc[q];
+    if (lane < nr) slice_sub(acc, Lv, Li.col, slice_ref(Li, sbase, rl), y);
+    rows_store(y, i0, nr, st, lane, acc);
 }
 
 __global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
@@ -405,26 +468,34 @@ __global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sba
                                                  const double* __restrict__ y, double* __restrict__ z,
                                                  const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
+    __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];
     const int rl = xcd_row();
-    const int i = r0 + rl;
-    if (i >= r1) return;
+    const int lane = threadIdx.x & 63;
+    const int64_t i0 = (int64_t)r0 + rl - lane;
+    if (i0 >= r1) return;
+    const int nr = (int)min((int64_t)64, (int64_t)r1 - i0);
+    float4* st = stage[threadIdx.x >> 6];
+    const int i = (int)i0 + lane;
     double acc[CB];
-    const double* yi = y + (int64_t)i * CB;
+    rows_load(y, i0, nr, st, lane, acc);
+    double zi[CB];
 #pragma unroll
-    for (int q = 0; q < CB; ++q) acc[q] = yi[q];
-    slice_sub(acc, Uv, Ui.col, slice_ref(Ui, sbase, rl), z);
-    double d[25];
-    load_block(Dinv, np, 0, i, d);
-    double* zi = z + (int64_t)i * CB;
+    for (int q = 0; q < CB; ++q) zi[q] = 0.0;
+    if (lane < nr) {
+        slice_sub(acc, Uv, Ui.col, slice_ref(Ui, sbase, rl), z);
+        double d[25];
+        load_block(Dinv, np, 0, i, d);
 #pragma unroll
-    for (int c = 0; c < NC; ++c)
+        for (int c = 0; c < NC; ++c)
 #pragma unroll
-        for (int r = 0; r < NB; ++r) {
-            double t = 0.0;
+            for (int r = 0; r < NB; ++r) {
+                double t = 0.0;
 #pragma unroll
-            for (int q = 0; q < NB; ++q) t += d[r * NB + q] * acc[c * NB + q];
-            zi[c * NB + r] = t;
-        }
+                for (int q = 0; q < NB; ++q) t += d[r * NB + q] * acc[c * NB + q];
+                zi[c * NB + r] = t;
+            }
+    }
+    rows_store(z, i0, nr, st, lane, zi);
 }
 
 // ------------------------------------------------------------------ mixed-precision inner sweeps
@@ -562,47 +633,6 @@ __device__ __forceinline__ void block_add(ACC (&acc)[CB], const float (&blk)[25]
         for (int r = 0; r < NB; ++r)
 #pragma unroll
             for (int q = 0; q < NB; ++q) acc[c * NB + r] += (ACC)blk[r * NB + q] * (ACC)x[c * NB + q];
-}
-
-// Row-major [.][CB] vectors of a wave's rows [i0, i0 + nr) pass through the
-// wave's LDS area: lanes copy 16-byte chunks lane-contiguously to or from
-// global memory, and each lane reads or writes its own row in LDS.  Every
-// lane of the wave must take part (rows past nr are neither read nor
-// written in global memory).
-template <typename T>
-__device__ __forceinline__ void rows_load(const T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
-                                          T (&v)[CB]) {
-    constexpr int K = CB * (int)sizeof(T) / 16;   // 16-byte chunks per row
-    const float4* src = reinterpret_cast<const float4*>(a + i0 * CB);
-    const int nc = nr * K;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int c = k * 64 + lane;
-        if (c < nc) st[c] = src[c];
-    }
-    __builtin_amdgcn_wave_barrier();
-    const T* my = reinterpret_cast<const T*>(st + lane * K);
-#pragma unroll
-    for (int q = 0; q < CB; ++q) v[q] = my[q];
-    __builtin_amdgcn_wave_barrier();
-}
-
-template <typename T>
-__device__ __forceinline__ void rows_store(T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
-                                           const T (&v)[CB]) {
-    constexpr int K = CB * (int)sizeof(T) / 16;
-    T* my = reinterpret_cast<T*>(st + lane * K);
-#pragma unroll
-    for (int q = 0; q < CB; ++q) my[q] = v[q];
-    __builtin_amdgcn_wave_barrier();
-    float4* dst = reinterpret_cast<float4*>(a + i0 * CB);
-    const int nc = nr * K;
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int c = k * 64 + lane;
-        if (c < nc) dst[c] = st[c];
-    }
-    __builtin_amdgcn_wave_barrier();
 }
 
 template <bool FIRST, bool LAST, typename ACC>
