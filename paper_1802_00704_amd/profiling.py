@@ -31,7 +31,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ("csrc/gks_kernels.hip", "csrc/gks_flux_device.h", "csrc/gks_internal.h")
+KERNEL_SOURCES = ("csrc/gks_kernels.hip", "csrc/gks_flux_device.h", "csrc/gks_char_basis.h", "csrc/gks_internal.h")
 
 # rocprof kernel symbol (without arguments) -> event-profiler class name
 CLASS_OF = [

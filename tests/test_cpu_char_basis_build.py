@@ -1,0 +1,56 @@
+"""The limiter kernel's closed-form characteristic basis compiled for the CPU
+(with address and undefined-behaviour sanitizers) against the oracle's
+right eigenvectors and their numerical inverse, on seeded states and
+directions, including a zero direction (the x axis is taken)."""
+import os
+import shutil
+import subprocess
+
+import numpy as np
+import pytest
+
+import gks_inputs as gi
+from oracle import limiter
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "cpu_build", "char_basis_cpu.cpp")
+EXE = os.path.join(HERE, "cpu_build", "_char_basis_cpu")
+CLANG = "/opt/rocm/llvm/bin/clang++"
+
+
+@pytest.fixture(scope="module")
+def exe():
+    if not os.path.exists(CLANG):
+        pytest.skip("clang++ of ROCm not available")
+    dep = os.path.join(HERE, "..", "paper_1802_00704_amd", "csrc", "gks_char_basis.h")
+    if not os.path.exists(EXE) or os.path.getmtime(EXE) < max(os.path.getmtime(SRC), os.path.getmtime(dep)):
+        san = "-fsanitize=" + "address,undefined"
+        cmd = [CLANG, "-x", "c++", "-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
+               san, "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", SRC, "-o", EXE + ".tmp"]
+        subprocess.run(cmd, check=True)
+        shutil.move(EXE + ".tmp", EXE)
+    return EXE
+
+
+def test_closed_form_basis_matches_oracle(exe):
+    rng = np.random.default_rng(5)
+    G = 1.4
+    n = 200
+    rows, refs = [], []
+    for k in range(n):
+        rho, p = rng.uniform(0.1, 3.0), rng.uniform(0.1, 5.0)
+        u, v = rng.normal(size=2)
+        W = gi.prim_to_cons(np.array([rho]), u, v, p, G)[:, 0]
+        g = np.zeros(2) if k % 17 == 0 else rng.normal(size=2) * 10 ** rng.uniform(-3, 3)
+        x = rng.normal(size=4)
+        nvec = np.array([1.0, 0.0]) if not g.any() else g / np.hypot(*g)
+        R = limiter.characteristic_basis(W, G, nvec)
+        refs.append((np.linalg.solve(R, x), R @ x, np.linalg.cond(R)))
+        rows.append(np.concatenate([W, g, x]))
+    payload = np.array([n], dtype="<i4").tobytes() + np.array([G], dtype="<f8").tobytes() + \
+        np.array(rows, dtype="<f8").tobytes()
+    out = np.frombuffer(subprocess.run([exe], input=payload, capture_output=True, check=True).stdout,
+                        dtype="<f8").reshape(n, 8)
+    for k, (Lx, Rx, cond) in enumerate(refs):
+        assert np.abs(out[k, :4] - Lx).max() <= 1e-12 * cond * np.abs(Lx).max(), k
+        assert np.abs(out[k, 4:] - Rx).max() <= 1e-13 * np.abs(Rx).max(), k

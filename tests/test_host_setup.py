@@ -171,6 +171,12 @@ def test_invalid_meshes_are_rejected():
         g.host_inspect(nonmanifold)
     with pytest.raises(g.GksError):
         g.host_inspect(m, restart=0)
+    # two triangles: each cell's gradient along the shared edge is bound only
+    # to the other's, so the CLS matrix is singular (the oracle's direct
+    # solver fails too)
+    with pytest.raises(g.GksError) as e:
+        g.host_inspect(gi.jss_mesh(1, 1, 1, Lx=1.0, Ly=1.0, periodic=False))
+    assert e.value.code == _lib.GKS_EINVAL and "singular" in str(e.value)
 
 
 def _factor_blocks(hs):
