@@ -224,6 +224,49 @@ def test_full_size_reconstruct_residual(adv512):
     assert res.max() <= 1e-10 * 1.01
 
 
+@pytest.fixture(scope="module")
+def sv1m():
+    """The benchmark's workload: shock-vortex on 1000 x 500 walled squares
+    (1,000,000 triangles; inflow, outflow and slip boundaries)."""
+    m = sv_mesh(1000, 500, 3)
+    return m, gi.shock_vortex_ic(m)
+
+
+def test_bench_size_flux_sampled(sv1m):
+    """1,000,000 cells: seeded coefficients, all faces on the GPU, a seeded
+    sample of faces (every boundary face among them) on the oracle."""
+    m, W = sv1m
+    from oracle.mesh import build_geometry
+    geo = build_geometry(m)
+    X = gi.random_coefficients(m.nt, seed=12, scale=0.002)
+    dt = 1e-4
+    F = g.GksMesh(m, nonphys_fallback=1).flux(dev(W), dev(X), dt).cpu().numpy()
+    rng = np.random.default_rng(4)
+    faces = np.union1d(rng.choice(geo.nf, 3000, replace=False), np.nonzero(geo.nbr < 0)[0])
+    F_ref = scheme.face_fluxes(geo, W, X, dt, scheme.Params(fallback=True), m.bc_table, faces=faces)
+    assert relinf(F[:, faces], F_ref) <= 1e-13
+
+
+def test_bench_size_mixed_reconstruct_residual(sv1m):
+    """1,000,000 cells, the benchmark's mixed form at tolerance 1e-10: the
+    true relative residual of the GPU coefficients in the oracle's own
+    normal equations, and a whole step reporting converged columns."""
+    m, W = sv1m
+    from oracle.mesh import build_geometry
+    geo = build_geometry(m)
+    K, pairs = ocls.assemble(geo)
+    R = ocls.rhs(geo, pairs, W)
+    gm = g.GksMesh(m, tol=1e-10, precision=g.GKS_MIXED, nonphys_fallback=1)
+    X, info = gm.reconstruct(dev(W))
+    res = ocls.residual(K, R, X.cpu().numpy())
+    assert res.max() <= 1e-10 * 1.01
+    Wt = dev(W)
+    _, info = gm.step(Wt)
+    assert max(info["rel_resid"]) <= 1e-10
+    assert torch.isfinite(Wt).all()
+    gm.close()
+
+
 @pytest.mark.parametrize("case", ["advection", "shock_vortex"])
 def test_mixed_precision_step_parity(case):
     """FP32 inner sweeps inside FP64 flexible GMRES: W within 1e-9 of the
