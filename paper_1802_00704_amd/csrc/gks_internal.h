@@ -173,10 +173,15 @@ struct gks_mesh {
     bool capturing = false;       // a stream capture is in progress (no profiling events)
     bool own_stream = false;      // the handle created m->stream itself
     // captured step graphs (see gks_step): A = solve with a fixed iteration
-    // budget, B = copy-out, flux, update; rebuilt when the budget changes
+    // budget, B = copy-out, flux, update; rebuilt when the budget changes;
+    // C[k] = Arnoldi step k of a cycle still running after A, with the gated
+    // end of cycle (captured on first need)
     hipGraphExec_t gA = nullptr, gB = nullptr;
+    std::vector<hipGraphExec_t> gC;
     int gA_budget = 0;            // Arnoldi steps captured in gA
     int budget = 0;               // steps wanted in gA for the next step
+    int need_hist[8] = {0};       // first-cycle lengths of the last steps
+    int need_n = 0;               // entries of need_hist filled
     int hist = 0;                 // solutions held in X, Xp, Xpp (extrapolated guess)
     int64_t graph_steps = 0;      // steps run through the graphs
     int capture_failures = 0;     // captures that failed (3 turn graphs off)
