@@ -189,6 +189,17 @@ def test_zero_rhs_columns_and_errors():
     with pytest.raises(g.NonPhysical):
         gm.step(Wt)
     assert torch.equal(Wt, before)
+    # with the Gauss-point fallback on, a step far beyond the CFL limit
+    # makes updated cells non-physical: an error, W unchanged (graph and
+    # eager paths)
+    for graphs in (1, 0):
+        gmf = g.GksMesh(m, nonphys_fallback=1, graphs=graphs)
+        Wt = dev(gi.density_advection_ic(m))
+        before = Wt.clone()
+        with pytest.raises(g.NonPhysical):
+            gmf.step(Wt, 5.0)
+        assert torch.equal(Wt, before)
+        gmf.close()
 
 
 @pytest.fixture(scope="module")
