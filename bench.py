@@ -58,6 +58,13 @@ def workload(name: str):
         desc = ("acoustic pressure pulse (amplitude 0.01, half width 0.04), periodic JSS 708x708 on [0,1]^2, "
                 "1,002,528 triangles, CFL 0.5, CLS tol 1e-10")
         return m, W, desc, {}
+    if name == "cavity_256":
+        walls = ((gi.BC_NOSLIP, (0.0, 0.0, 0.0, 0.0)),) * 3 + ((gi.BC_NOSLIP, (0.0, 1.0, 0.0, 0.0)),)
+        m = gi.jss_mesh(256, 256, 4, Lx=1.0, Ly=1.0, periodic=False, stretch=1.5, walls=walls)
+        W = gi.cavity_ic(m)
+        desc = ("lid-driven cavity (lid u = 1, Ma 0.15, Re 1000: mu 1e-3, viscous collision time), JSS 256x256 "
+                "tanh-clustered (1.5) on [0,1]^2, 131,072 triangles, CFL 0.5, CLS tol 1e-10")
+        return m, W, desc, {"mu": 1e-3}
     raise SystemExit("unknown workload %r" % name)
 
 
@@ -82,6 +89,12 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
         W = gi.acoustic_pulse_ic(m)
         sample = "acoustic pulse JSS 71x71 (10,082 triangles), same family at 10x coarser h"
         prm = scheme.Params()
+    elif name == "cavity_256":
+        walls = ((gi.BC_NOSLIP, (0.0, 0.0, 0.0, 0.0)),) * 3 + ((gi.BC_NOSLIP, (0.0, 1.0, 0.0, 0.0)),)
+        m = gi.jss_mesh(64, 64, 4, Lx=1.0, Ly=1.0, periodic=False, stretch=1.5, walls=walls)
+        W = gi.cavity_ic(m)
+        sample = "lid-driven cavity JSS 64x64 tanh-clustered (8,192 triangles), same family at 4x coarser h"
+        prm = scheme.Params(mu=1e-3)
     else:
         m = gi.jss_mesh(64, 64, 2)
         W = gi.density_advection_ic(m)
@@ -106,11 +119,13 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
             "sample": "%s, %d steps in %.1f s" % (sample, steps, el)}
 
 
-def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, graphs: int = 1, limiter: int = 0):
+def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, graphs: int = 1, limiter: int = 0,
+             extra: dict | None = None):
     import torch
     import paper_1802_00704_amd as g
     t0 = time.perf_counter()
-    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1, graphs=graphs, limiter=limiter)
+    gm = g.GksMesh(m, tol=1e-10, precision=precision, nonphys_fallback=1, graphs=graphs, limiter=limiter,
+                   **(extra or {}))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
     W = torch.tensor(W0, dtype=torch.float64, device="cuda")
@@ -244,7 +259,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="shock_vortex_1m",
-                    choices=["shock_vortex_1m", "advection_512", "acoustic_pulse_1m"])
+                    choices=["shock_vortex_1m", "advection_512", "acoustic_pulse_1m", "cavity_256"])
     ap.add_argument("--forms", default="mixed,fp64")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
@@ -263,12 +278,12 @@ def main():
         sys.exit(2)
     import torch
     import paper_1802_00704_amd as g
-    m, W0, desc, _ = workload(args.workload)
+    m, W0, desc, extra = workload(args.workload)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
     res = {}
     for f in forms:
         prec = g.GKS_MIXED if f == "mixed" else g.GKS_FP64
-        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile, args.graphs)
+        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile, args.graphs, extra=extra)
         print("# %s: %.4g cell-steps/s, %.3f ms/step, %.1f Krylov iterations/step" %
               (f, res[f]["value"], res[f]["ms_per_step"], res[f]["krylov_iters_per_step"]), file=sys.stderr,
               flush=True)
@@ -281,7 +296,7 @@ def main():
         lim = {}
         for name, variables in (("conservative", g.LIMIT_CONSERVATIVE), ("characteristic", g.LIMIT_CHARACTERISTIC)):
             rl = run_form(m, W0, g.GKS_MIXED, args.steps, args.warmup, not args.no_profile, args.graphs,
-                          limiter=variables)
+                          limiter=variables, extra=extra)
             pl = rl["profile"].get("limit") if rl["profile"] else None
             pa = rl["profile"].get("limit_apply") if rl["profile"] else None
             leg = {"ms_per_step": rl["ms_per_step"], "value": rl["value"],

@@ -1761,6 +1761,12 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
 // handle has it (see k_es_fwd/k_es_bwd), else the general fused sweeps
 // (k_mx_fwd/k_mx_bwd).  Bytes: stored blocks (100 B FP32, 4 B index) of each
 // level plus per row its own vectors (80 B FP32, 160 B FP64 v).
+// Block size of a level's sweep launch: TPB threads once the level has rows
+// for two such blocks per CU, else one-wave blocks, so that the waves of a
+// small level spread over every CU (the sweeps have no block-wide
+// reductions; their LDS areas are per wave).
+static inline int sweep_tpb(int64_t rows) { return rows >= 2 * 256 * (int64_t)TPB ? TPB : 64; }
+
 static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
     using ACC = double;
     const DevMesh& D = m->d;
@@ -1779,11 +1785,11 @@ static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale
             const double lb = D.lev_Lb[l] * 104.0;
             if (first)
                 PROFB(KC_ILU_FWD32, lb + rows * (VB + 2 * VF),
-                      hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np,
+                      hipLaunchKernelGGL((k_mx_fwd<true, ACC>), dim3(nblocks(rows, sweep_tpb(rows))), dim3(sweep_tpb(rows)), 0, m->stream, D.n, D.np,
                                          r0, r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
             else
                 PROFB(KC_ILU_FWD32, lb + D.lev_Kb[l] * 104.0 + rows * 3 * VF,
-                      hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.n, D.np,
+                      hipLaunchKernelGGL((k_mx_fwd<false, ACC>), dim3(nblocks(rows, sweep_tpb(rows))), dim3(sweep_tpb(rows)), 0, m->stream, D.n, D.np,
                                          r0, r1, D.Lsbase[l], D.Kval32, D.Kcol, D.Li, D.Lval32, v, vscale, b, z, y, gate));
         }
         for (int l = nl - 1; l >= 0; --l) {
@@ -1793,11 +1799,11 @@ static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale
             const double ub = D.lev_Ub[l] * 104.0;
             if (first)
                 PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 2 * VF),
-                      hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0,
+                      hipLaunchKernelGGL((k_mx_bwd<true, ACC>), dim3(nblocks(rows, sweep_tpb(rows))), dim3(sweep_tpb(rows)), 0, m->stream, D.np, r0,
                                          r1, D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
             else
                 PROFB(KC_ILU_BWD32, ub + rows * (100.0 + 4 * VF),
-                      hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows)), dim3(TPB), 0, m->stream, D.np, r0,
+                      hipLaunchKernelGGL((k_mx_bwd<false, ACC>), dim3(nblocks(rows, sweep_tpb(rows))), dim3(sweep_tpb(rows)), 0, m->stream, D.np, r0,
                                          r1, D.Usbase[l], D.Ui, D.Uval32, D.Dinv32, y, d, z, gate));
         }
     }
@@ -1823,7 +1829,8 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         // levels), z (last level)
         const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + 2 * VF : 3 * VF)) +
                           rows * VF * ((last ? 1 : 0) + (!first && !last ? 2 : 0));
-        const dim3 g(nblocks(rows)), bl(TPB);
+        const int tb = sweep_tpb(rows);
+        const dim3 g(nblocks(rows, tb)), bl(tb);
         if (first && last)
             PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<true, true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
                                                      D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
@@ -1844,7 +1851,8 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         // blocks: Dinv K_U (+ Dinv E); vectors: w read, z written (+ b' read,
         // t and w written)
         const double by = D.lev_Ub[l] * 104.0 + rows * 2 * VF + (bf ? rows * (100.0 + 3 * VF) : 0.0);
-        const dim3 g(nblocks(rows)), bl(TPB);
+        const int tb = sweep_tpb(rows);
+        const dim3 g(nblocks(rows, tb)), bl(tb);
         if (bf)
             PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
                                                      D.Usbase[l], D.Ui, D.Uval32, D.E32, b, t, w, z, gate));
@@ -1878,14 +1886,14 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         PROFB(KC_ILU_FWD, D.lev_Lb[l] * 204.0 + (r1 - r0) * 2.0 * VB,
-              hipLaunchKernelGGL(k_ilu_fwd, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream, r0, r1, D.Lsbase[l], D.Li,
+              hipLaunchKernelGGL(k_ilu_fwd, dim3(nblocks(r1 - r0, sweep_tpb(r1 - r0))), dim3(sweep_tpb(r1 - r0)), 0, m->stream, r0, r1, D.Lsbase[l], D.Li,
                                  D.Lval, in, in_scale, tmp, gate));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         PROFB(KC_ILU_BWD, D.lev_Ub[l] * 204.0 + (r1 - r0) * (200.0 + 2.0 * VB),
-              hipLaunchKernelGGL(k_ilu_bwd, dim3(nblocks(r1 - r0)), dim3(TPB), 0, m->stream, D.np, r0, r1, D.Usbase[l],
+              hipLaunchKernelGGL(k_ilu_bwd, dim3(nblocks(r1 - r0, sweep_tpb(r1 - r0))), dim3(sweep_tpb(r1 - r0)), 0, m->stream, D.np, r0, r1, D.Usbase[l],
                                  D.Ui, D.Uval, D.Dinv, tmp, out, gate));
     }
 }
