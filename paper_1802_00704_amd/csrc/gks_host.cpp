@@ -1100,8 +1100,7 @@ void end_cycle(gks_mesh* m, int nvec, bool graph) {
     const int32_t* nvec_dev = graph ? &ks->st.k : nullptr;
     launch_ctl(m, 3, graph);
     if (m->prm.precision == GKS_MIXED) {
-        launch_combine_f32(m, w.Z, vs, nvec, &ks->y[0][0], w.ones, w.t1, nvec_dev, gate);
-        launch_acc(m, w.X, w.t1, gate);
+        launch_combine_f32(m, w.Z, vs, nvec, &ks->y[0][0], w.ones, w.X, nvec_dev, gate, true);   // X += Z y
     } else {
         launch_combine(m, w.V, vs, nvec, &ks->y[0][0], &ks->scale[0][0], w.t1, nvec_dev, gate);
         launch_ilu(m, w.t1, nullptr, w.t2, w.t3, gate);

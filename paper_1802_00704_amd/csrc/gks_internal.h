@@ -236,8 +236,10 @@ void launch_axpy_dots(gks_mesh* m, const double* V, int64_t vstride, int nvec, c
 // nvec_dev: when non-null the number of vectors is min(nvec, *nvec_dev)
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);
+// accum: out += the combination instead of out = it
 void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, const double* y, const double* scale,
-                        double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);
+                        double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr,
+                        bool accum = false);
 void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate = nullptr);
 // mode 0: norms of the right-hand side; 1: start of a cycle (true residual);
 // 2: Arnoldi step (skipped once st.run is 0); 3: triangular solve for y.

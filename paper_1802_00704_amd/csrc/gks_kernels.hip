@@ -847,7 +847,9 @@ __global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ 
 }
 
 // out = sum_j y_j[c] scale_j[c] V_j
-template <typename VT>
+// out = sum_j y_j scale_j V_j, or out += that sum (ACCUM: the mixed form's
+// X += Z y in one pass)
+template <typename VT, bool ACCUM = false>
 __global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V, int64_t vstride, int nvec,
                                                  const double* __restrict__ y, const double* __restrict__ scale,
                                                  double* __restrict__ out, const int32_t* __restrict__ nvec_dev,
@@ -875,7 +877,12 @@ __global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V
         for (int e = 0; e < E; ++e) acc[e] += y[j * NC + col[e]] * scale[j * NC + col[e]] * (double)v[e];
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) out[off + e] = acc[e];
+    for (int e = 0; e < E; ++e) {
+        if (ACCUM)
+            out[off + e] += acc[e];
+        else
+            out[off + e] = acc[e];
+    }
 }
 
 // X += z
@@ -1932,10 +1939,17 @@ void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, con
 }
 
 void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, const double* y, const double* scale,
-                        double* out, const int32_t* nvec_dev, const int32_t* gate) {
+                        double* out, const int32_t* nvec_dev, const int32_t* gate, bool accum) {
     const int n = m->d.n;
-    PROFB(KC_COMBINE, (double)n * (nvec * VB / 2 + VB), hipLaunchKernelGGL(k_combine<float>, dim3(nblocks((int64_t)n * Grp<float>::T)), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
-                                        y, scale, out, nvec_dev, gate));
+    const dim3 g(nblocks((int64_t)n * Grp<float>::T)), b(TPB);
+    // bytes: the FP32 basis vectors read, out written (and read when accumulating)
+    const double by = (double)n * (nvec * VB / 2 + (accum ? 2 : 1) * VB);
+    if (accum)
+        PROFB(KC_COMBINE, by, hipLaunchKernelGGL((k_combine<float, true>), g, b, 0, m->stream, n, V, vstride, nvec, y,
+                                                 scale, out, nvec_dev, gate));
+    else
+        PROFB(KC_COMBINE, by, hipLaunchKernelGGL((k_combine<float, false>), g, b, 0, m->stream, n, V, vstride, nvec, y,
+                                                 scale, out, nvec_dev, gate));
 }
 
 void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate) {
