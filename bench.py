@@ -235,6 +235,35 @@ def roofline(prof: dict, elapsed_s: float):
             "time_share": shares, "kernel_time_fraction_of_steps": round(tot * 1e-3 / elapsed_s, 4)}
 
 
+SAME_WORK_CLASSES = ("rhs", "cfl", "update", "copyout", "extrap", "spmv_resid", "ilu_fwd32", "ilu_bwd32",
+                     "ilu_fwd", "ilu_bwd")
+
+
+def kernel_table(prof: dict) -> dict:
+    """Every kernel class that moves memory: live average launch duration,
+    algorithmic GB/s and its fraction of the HBM peak, share of kernel time,
+    and, while the kernel sources match the committed counter summary, the
+    counted HBM traffic per launch and the GB/s it implies."""
+    if not prof:
+        return {}
+    tot = sum(v["ms"] for v in prof.values())
+    out = {}
+    for k, d in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]):
+        if d["ms"] <= 0 or d["bytes"] <= 0 or k in ("flux", "limit_apply"):
+            continue
+        gbs = d["bytes"] / (d["ms"] * 1e-3) / 1e9
+        us = d["ms"] * 1e3 / max(1, d["launches"])
+        row = {"launches": d["launches"], "avg_launch_us": round(us, 2), "achieved_GBs": round(gbs, 1),
+               "frac": round(gbs / HBM_PEAK_GBS, 4), "time_share": round(d["ms"] / tot, 4)}
+        # the counter summary averages each class over both forms' launches;
+        # only classes whose launches do the same work in either form use it
+        tr = measured_traffic(k) if k in SAME_WORK_CLASSES else None
+        if tr:
+            row["traffic_GBs"] = round(tr / (us * 1e-6) / 1e9, 1)
+        out[k] = row
+    return out
+
+
 def serving_leg(n_requests: int, slots: int) -> dict:
     """The first n_requests of the seeded serving stream (Poisson arrivals at
     40/s; advection or shock-vortex, 2e3-2e5 triangles log-uniform, 50-500
@@ -342,7 +371,8 @@ def main():
         "roofline": roofline(r["profile"], r["profiled_elapsed_s"]),
         "flux_fp64": flux_fp64(r["profile"]),
         "cpu_baseline": cpu,
-        "forms": {f: {k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")}
+        "forms": {f: dict({k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")},
+                          hbm_kernels=kernel_table(res[f]["profile"]))
                   for f in forms},
         "latency_ms": {"step_p50": r["step_ms_p50"], "step_p99": r["step_ms_p99"],
                        "serving_step_p50": serving["step_ms_p50"] if serving else None,

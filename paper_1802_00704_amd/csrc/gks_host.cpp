@@ -9,11 +9,13 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
-#include <type_traits>
+#include <functional>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <numeric>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "gks_internal.h"
@@ -49,6 +51,41 @@ struct Fail {
         if (e_ != hipSuccess)                                                             \
             throw Fail{GKS_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)};      \
     } while (0)
+
+// ------------------------------------------------------------------ set-up arrays
+// The large host arrays of the set-up (matrix, factors and their device
+// layouts: several KB per cell) are allocated without initialisation and
+// first written by OpenMP loops, so that their page faults spread over the
+// threads instead of one serial zero fill each.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+    template <class U>
+    void construct(U* p) noexcept {
+        ::new ((void*)p) U;
+    }
+    template <class U, class... A>
+    void construct(U* p, A&&... a) {
+        ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using hvec = std::vector<T, NoInitAlloc<T>>;
+
+// v = n copies of x, written in parallel
+template <class T>
+void par_fill(hvec<T>& v, size_t n, const T& x) {
+    v.clear();
+    v.resize(n);
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < (int64_t)n; ++i) v[i] = x;
+}
 
 // ------------------------------------------------------------------ 5x5 blocks
 using Blk = std::array<double, 25>;
@@ -325,9 +362,9 @@ Blk atb(const double A[6][5], const double B[6][5], double s) {
 }
 
 struct Assembly {
-    std::vector<Blk> diag;                    // [nt]
-    std::vector<std::array<Blk, 3>> off;      // [nt][slot] block K_{i, nb[i][slot]}
-    std::vector<std::array<std::array<double, 5>, 3>> a0;  // [nt][slot]
+    hvec<Blk> diag;                           // [nt]
+    hvec<std::array<Blk, 3>> off;             // [nt][slot] block K_{i, nb[i][slot]}
+    hvec<std::array<std::array<double, 5>, 3>> a0;  // [nt][slot]
 };
 
 // Row i of the normal equations gathers the rows of the pairs (i, j) (cell i
@@ -454,34 +491,93 @@ std::vector<int> rcm_order(const HostMesh& hm) {
 // handle's set-up or tear-down cannot disturb another handle's capture.
 std::mutex g_dev_mu;
 
-template <typename T>
-T* dev_upload(gks_mesh* m, const std::vector<T>& h) {
-    T* p = nullptr;
-    const size_t bytes = std::max<size_t>(1, h.size()) * sizeof(T);
+// Device memory of a handle.  Allocation is serialised; the copy or clear
+// that follows runs on the handle's own stream outside the lock.
+void* dev_malloc(gks_mesh* m, size_t bytes) {
+    void* p = nullptr;
     std::lock_guard<std::mutex> lk(g_dev_mu);
-    hipError_t e = hipMalloc((void**)&p, bytes);
+    hipError_t e = hipMalloc(&p, bytes);
     if (e != hipSuccess) throw Fail{GKS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
     m->allocs.push_back(p);
     m->dev_bytes += (int64_t)bytes;
-    if (!h.empty()) {
-        HIPCHK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, m->stream));
-        HIPCHK(hipStreamSynchronize(m->stream));
-    }
     return p;
 }
 
 template <typename T>
 T* dev_alloc(gks_mesh* m, size_t count) {
-    T* p = nullptr;
     const size_t bytes = std::max<size_t>(1, count) * sizeof(T);
-    std::lock_guard<std::mutex> lk(g_dev_mu);
-    hipError_t e = hipMalloc((void**)&p, bytes);
-    if (e != hipSuccess) throw Fail{GKS_ENOMEM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
-    m->allocs.push_back(p);
-    m->dev_bytes += (int64_t)bytes;
+    T* p = (T*)dev_malloc(m, bytes);
     HIPCHK(hipMemsetAsync(p, 0, bytes, m->stream));   // set-up only, never captured
     return p;
 }
+
+// Host arrays bound for the device, sent in one transfer into one
+// allocation; each array starts on a 256-byte boundary.  The device pointers
+// are written by send(), which returns once the copy is complete.
+struct Staging {
+    struct Item {
+        const void* src;
+        size_t bytes;
+        std::function<void(char*)> bind;
+    };
+    std::vector<Item> items;
+    std::vector<std::shared_ptr<void>> held;   // arrays built only to be sent
+
+    template <class Vec, class P>
+    void add(const Vec& v, P* dst) {
+        using T = typename Vec::value_type;
+        static_assert(std::is_same<std::remove_cv_t<std::remove_pointer_t<P>>, T>::value, "element type");
+        items.push_back({v.data(), v.size() * sizeof(T), [dst](char* a) { *dst = reinterpret_cast<P>(a); }});
+    }
+    template <class Vec, class P>
+    void add_owned(Vec&& v, P* dst) {
+        auto h = std::make_shared<std::decay_t<Vec>>(std::move(v));
+        held.push_back(h);
+        add(*h, dst);
+    }
+    void send(gks_mesh* m) {
+        std::vector<size_t> off(items.size());
+        size_t tot = 0;
+        for (size_t k = 0; k < items.size(); ++k) {
+            off[k] = tot;
+            tot += (items[k].bytes + 255) / 256 * 256;
+        }
+        tot = std::max<size_t>(tot, 256);
+        char* dev = (char*)dev_malloc(m, tot);
+        hvec<char> host(tot);
+        // copy in 4 MiB pieces spread over the threads
+        constexpr size_t PIECE = (size_t)4 << 20;
+        std::vector<std::pair<size_t, size_t>> pieces;   // (item, offset in it)
+        for (size_t k = 0; k < items.size(); ++k)
+            for (size_t o = 0; o < items[k].bytes; o += PIECE) pieces.push_back({k, o});
+#pragma omp parallel for schedule(dynamic)
+        for (int64_t q = 0; q < (int64_t)pieces.size(); ++q) {
+            const Item& it = items[pieces[q].first];
+            const size_t o = pieces[q].second;
+            std::memcpy(host.data() + off[pieces[q].first] + o, (const char*)it.src + o, std::min(PIECE, it.bytes - o));
+        }
+        HIPCHK(hipMemcpyAsync(dev, host.data(), tot, hipMemcpyHostToDevice, m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+        for (size_t k = 0; k < items.size(); ++k) items[k].bind(dev + off[k]);
+    }
+};
+
+// Work arrays of a handle carved from one allocation (256-byte aligned
+// pieces), cleared to zero on the handle's stream by commit().
+struct Arena {
+    std::vector<std::pair<size_t, std::function<void(char*)>>> items;   // offset, binder
+    size_t tot = 0;
+    template <class T>
+    void add(T** dst, size_t count) {
+        items.push_back({tot, [dst](char* a) { *dst = reinterpret_cast<T*>(a); }});
+        tot += (std::max<size_t>(1, count) * sizeof(T) + 255) / 256 * 256;
+    }
+    void commit(gks_mesh* m) {
+        char* dev = (char*)dev_malloc(m, std::max<size_t>(tot, 256));
+        HIPCHK(hipMemsetAsync(dev, 0, std::max<size_t>(tot, 256), m->stream));   // set-up only, never captured
+        for (auto& it : items) it.second(dev + it.first);
+    }
+};
 
 // List of limited cells and their coefficients: at set-up when gks_step
 // limits, else on the first gks_limit call.
@@ -497,15 +593,15 @@ struct HostSystem {
     std::vector<int> perm;                        // solver order -> cell
     std::vector<int32_t> lev_ptr;
     int n_levels = 0, n_colors = 0, rcm_bw = 0, nfb = 0;
-    std::vector<double> Kval, a0c, Lval, Uval, Dv;
+    hvec<double> Kval, a0c, Lval, Uval, Dv;
     // When the cell graph has no 3-cycles BILU(0) has no off-diagonal fill:
     // U = K_U and L = K_L D^-1 exactly, and the mixed-form inner sweeps use
     // the split form (K_L blocks in L's slots, E = D - K_D per row).
     bool tri_free = false;
-    std::vector<double> KLval, Ev;
+    hvec<double> KLval, Ev;
     // split form, rows scaled by their pivot inverse: Dinv_i K_ik (k < i),
     // Dinv_i K_ij (j > i), Dinv_i E_i
-    std::vector<double> KLs, KUs, Gs;
+    hvec<double> KLs, KUs, Gs;
     std::vector<int32_t> Kcol, nbc, iperm, Lcol, Ucol;
     std::vector<int32_t> own, nbr, cface, bck;
     std::vector<double> fgeo, gpd, cgeo, bcs;
@@ -513,9 +609,10 @@ struct HostSystem {
 
 // Entry-major [slots*25][n] -> vector-packed device layout (gks_internal.h).
 template <typename T>
-std::vector<T> pack_blocks(const std::vector<double>& src, int slots, int n, int np) {
+hvec<T> pack_blocks(const hvec<double>& src, int slots, int n, int np) {
     constexpr int V = 16 / sizeof(T);
-    std::vector<T> dst((size_t)slots * 25 * np, T(0));
+    hvec<T> dst;
+    par_fill(dst, (size_t)slots * 25 * np, T(0));
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i)
         for (int s = 0; s < slots; ++s) {
@@ -566,11 +663,12 @@ SliceLayout slice_layout(const std::vector<int32_t>& col, int slots, int n, cons
 // Blocks of an ELL factor in the sliced layout (element type T) and, when
 // col_out is given, the column indices per chunk.
 template <typename T>
-std::vector<T> pack_sliced(const std::vector<double>& val, const std::vector<int32_t>& col, int n,
+hvec<T> pack_sliced(const hvec<double>& val, const std::vector<int32_t>& col, int n,
                            const std::vector<int32_t>& lev_ptr, const SliceLayout& L, std::vector<int32_t>* col_out) {
     constexpr int V = 16 / sizeof(T);
     const size_t nch = std::max<int32_t>(1, L.chunks);
-    std::vector<T> dst(nch * 25 * 64, T(0));
+    hvec<T> dst;
+    par_fill(dst, nch * 25 * 64, T(0));
     if (col_out) col_out->assign(nch * 64, n);
     const int nl = (int)lev_ptr.size() - 1;
     for (int l = 0; l < nl; ++l) {
@@ -682,13 +780,13 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     pt.mark("ordering");
     // matrix in solver order: slot 0 diagonal, then neighbours, padded with the dummy row
     const int n = nt;
-    std::vector<double>& Kval = S.Kval;
-    Kval.assign((size_t)KW * 25 * n, 0.0);
+    hvec<double>& Kval = S.Kval;
+    par_fill(Kval, (size_t)KW * 25 * n, 0.0);
     std::vector<int32_t>& Kcol = S.Kcol;
     Kcol.assign((size_t)KW * n, n);
     S.iperm.assign(iperm.begin(), iperm.end());
     S.nbc.assign((size_t)3 * n, 0);
-    S.a0c.assign((size_t)3 * 5 * n, 0.0);
+    par_fill(S.a0c, (size_t)3 * 5 * n, 0.0);
     for (int o = 0; o < n; ++o)
         for (int s2 = 0; s2 < 3; ++s2) {
             const int j = hm.nb[o][s2];
@@ -713,7 +811,7 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     // BILU(0) in solver order: row-wise IKJ elimination restricted to the
     // pattern.  Rows of one level only read rows of earlier levels, so each
     // level is factored in parallel.
-    std::vector<Blk> rv((size_t)KW * n);
+    hvec<Blk> rv((size_t)KW * n);   // entries [0, rnz[i]) of each row are written below
     std::vector<int> rc((size_t)KW * n), rnz(n);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
@@ -733,7 +831,8 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
             }
         rnz[i] = nz;
     }
-    std::vector<Blk> dinv(n);
+    pt.mark("BILU rows");
+    hvec<Blk> dinv(n);
     int singular = -1;
     for (size_t l = 0; l + 1 < S.lev_ptr.size(); ++l) {
 #pragma omp parallel for schedule(static)
@@ -768,18 +867,23 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         }
         if (singular >= 0) throw Fail{GKS_EINVAL, "singular pivot block in the CLS matrix"};
     }
-    std::vector<double>& Lval = S.Lval;
-    std::vector<double>& Uval = S.Uval;
-    std::vector<double>& Dv = S.Dv;
+    pt.mark("BILU elimination");
+    hvec<double>& Lval = S.Lval;
+    hvec<double>& Uval = S.Uval;
+    hvec<double>& Dv = S.Dv;
     std::vector<int32_t>& Lcol = S.Lcol;
     std::vector<int32_t>& Ucol = S.Ucol;
-    Lval.assign((size_t)LW * 25 * n, 0.0);
-    Uval.assign((size_t)LW * 25 * n, 0.0);
-    Dv.assign((size_t)25 * n, 0.0);
+    // the split form's blocks serve the mixed form only
+    const bool want_split = prm.precision == GKS_MIXED;
+    par_fill(Lval, (size_t)LW * 25 * n, 0.0);
+    par_fill(Uval, (size_t)LW * 25 * n, 0.0);
+    par_fill(Dv, (size_t)25 * n, 0.0);
     Lcol.assign((size_t)LW * n, n);
     Ucol.assign((size_t)LW * n, n);
-    S.KLval.assign((size_t)LW * 25 * n, 0.0);
-    S.Ev.assign((size_t)25 * n, 0.0);
+    if (want_split) {
+        par_fill(S.KLval, (size_t)LW * 25 * n, 0.0);
+        par_fill(S.Ev, (size_t)25 * n, 0.0);
+    }
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < n; ++i) {
         const int* ci = &rc[(size_t)KW * i];
@@ -790,7 +894,7 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
             if (c < i) {
                 Lcol[(size_t)nl * n + i] = c;
                 for (int e = 0; e < 25; ++e) Lval[((size_t)nl * 25 + e) * n + i] = vi[a][e];
-                for (int s2 = 0; s2 < KW; ++s2)
+                for (int s2 = 0; s2 < KW && want_split; ++s2)
                     if (Kcol[(size_t)s2 * n + i] == c)
                         for (int e = 0; e < 25; ++e)
                             S.KLval[((size_t)nl * 25 + e) * n + i] = Kval[((size_t)s2 * 25 + e) * n + i];
@@ -801,11 +905,13 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
                 ++nu;
             } else {
                 // E = D - K_D: the pivot block after elimination minus the diagonal of K
-                for (int e = 0; e < 25; ++e) S.Ev[(size_t)e * n + i] = vi[a][e] - Kval[(size_t)e * n + i];
+                if (want_split)
+                    for (int e = 0; e < 25; ++e) S.Ev[(size_t)e * n + i] = vi[a][e] - Kval[(size_t)e * n + i];
             }
         }
         for (int e = 0; e < 25; ++e) Dv[(size_t)e * n + i] = dinv[i][e];
     }
+    pt.mark("factor arrays");
     {
         // 3-cycles of the cell graph (three mutually adjacent cells)
         bool tri = false;
@@ -820,13 +926,14 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
                 }
         S.tri_free = !tri;
     }
-    if (S.tri_free) {
+    if (S.tri_free && want_split) {
         // without fill U = K_U, so the split form's blocks are K_L, K_U, E
-        // scaled from the left by the row's pivot inverse
-        S.KLs.assign((size_t)LW * 25 * n, 0.0);
-        S.KUs.assign((size_t)LW * 25 * n, 0.0);
-        S.Gs.assign((size_t)25 * n, 0.0);
-        auto scale = [&](const std::vector<double>& src, std::vector<double>& dst, int slots, int i) {
+        // scaled from the left by the row's pivot inverse (every entry is
+        // written below)
+        S.KLs.resize((size_t)LW * 25 * n);
+        S.KUs.resize((size_t)LW * 25 * n);
+        S.Gs.resize((size_t)25 * n);
+        auto scale = [&](const hvec<double>& src, hvec<double>& dst, int slots, int i) {
             for (int s2 = 0; s2 < slots; ++s2)
                 for (int r = 0; r < 5; ++r)
                     for (int c = 0; c < 5; ++c) {
@@ -843,7 +950,7 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
             scale(S.Ev, S.Gs, 1, i);
         }
     }
-    pt.mark("BILU(0)");
+    pt.mark("split-form blocks");
     // ---- face / cell arrays in device layout
     std::vector<int32_t>& own = S.own;
     std::vector<int32_t>& nbr = S.nbr;
@@ -898,12 +1005,14 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
         if (k == GKS_BC_INFLOW && !(bcs[4 * (size_t)(r + 1)] > 0 && bcs[4 * (size_t)(r + 1) + 3] > 0))
             throw Fail{GKS_EINVAL, "inflow state must have positive density and pressure"};
     }
+    pt.mark("face and cell arrays");
 }
 
 void setup(gks_mesh* m, const gks_mesh_desc* de) {
     const gks_params& prm = m->prm;
     HostSystem S;
     build_system(de, prm, S);
+    PhaseTimer pt;
     const HostMesh& hm = S.hm;
     const int nt = hm.nt, nf = hm.nf, n = nt;
     m->rcm_bw = S.rcm_bw;
@@ -918,104 +1027,116 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     d.nfb = S.nfb;
     d.lev_ptr = S.lev_ptr;
     d.n_bc = de->n_bc;
-    d.own = dev_upload(m, S.own);
-    d.nbr = dev_upload(m, S.nbr);
-    d.fgeo = dev_upload(m, S.fgeo);
-    d.gpd = dev_upload(m, S.gpd);
-    d.area = dev_upload(m, hm.area);
-    d.cgeo = dev_upload(m, S.cgeo);
-    d.cface = dev_upload(m, S.cface);
-    d.bc_kind = dev_upload(m, S.bck);
-    d.bc_state = dev_upload(m, S.bcs);
-    d.iperm = dev_upload(m, S.iperm);
-    d.nbc = dev_upload(m, S.nbc);
-    d.a0c = dev_upload(m, S.a0c);
+    // Every array the device reads is gathered into one host buffer and
+    // sent in one transfer: the handle's stream shares a hardware queue with
+    // other handles' streams, so each separate transfer would wait behind
+    // their queued kernels.
+    Staging up;
+    up.add(S.own, &d.own);
+    up.add(S.nbr, &d.nbr);
+    up.add(S.fgeo, &d.fgeo);
+    up.add(S.gpd, &d.gpd);
+    up.add(hm.area, &d.area);
+    up.add(S.cgeo, &d.cgeo);
+    up.add(S.cface, &d.cface);
+    up.add(S.bck, &d.bc_kind);
+    up.add(S.bcs, &d.bc_state);
+    up.add(S.iperm, &d.iperm);
+    up.add(S.nbc, &d.nbc);
+    up.add(S.a0c, &d.a0c);
     d.np = (n + 3) / 4 * 4;
     const int np = d.np;
-    d.Kval = dev_upload(m, pack_blocks<double>(S.Kval, KW, n, np));
-    d.Kcol = dev_upload(m, S.Kcol);
+    up.add_owned(pack_blocks<double>(S.Kval, KW, n, np), &d.Kval);
+    up.add(S.Kcol, &d.Kcol);
+    const SliceLayout Ls = slice_layout(S.Lcol, LW, n, S.lev_ptr);
+    const SliceLayout Us = slice_layout(S.Ucol, LW, n, S.lev_ptr);
     {
-        const SliceLayout Ls = slice_layout(S.Lcol, LW, n, S.lev_ptr);
-        const SliceLayout Us = slice_layout(S.Ucol, LW, n, S.lev_ptr);
         std::vector<int32_t> lcol, ucol;
-        d.Lval = dev_upload(m, pack_sliced<double>(S.Lval, S.Lcol, n, S.lev_ptr, Ls, &lcol));
-        d.Uval = dev_upload(m, pack_sliced<double>(S.Uval, S.Ucol, n, S.lev_ptr, Us, &ucol));
-        d.Li.col = dev_upload(m, lcol);
-        d.Li.off = dev_upload(m, Ls.off);
-        d.Li.w = dev_upload(m, Ls.w);
-        d.Ui.col = dev_upload(m, ucol);
-        d.Ui.off = dev_upload(m, Us.off);
-        d.Ui.w = dev_upload(m, Us.w);
-        d.Lsbase = Ls.sbase;
-        d.Usbase = Us.sbase;
-        d.lev_Lb = Ls.lev_blocks;
-        d.lev_Ub = Us.lev_blocks;
+        up.add_owned(pack_sliced<double>(S.Lval, S.Lcol, n, S.lev_ptr, Ls, &lcol), &d.Lval);
+        up.add_owned(pack_sliced<double>(S.Uval, S.Ucol, n, S.lev_ptr, Us, &ucol), &d.Uval);
+        up.add_owned(std::move(lcol), &d.Li.col);
+        up.add_owned(std::move(ucol), &d.Ui.col);
+    }
+    up.add(Ls.off, &d.Li.off);
+    up.add(Ls.w, &d.Li.w);
+    up.add(Us.off, &d.Ui.off);
+    up.add(Us.w, &d.Ui.w);
+    d.Lsbase = Ls.sbase;
+    d.Usbase = Us.sbase;
+    d.lev_Lb = Ls.lev_blocks;
+    d.lev_Ub = Us.lev_blocks;
+    {
         const int nl = (int)S.lev_ptr.size() - 1;
         d.lev_Kb.assign(nl, 0.0);
         for (int l = 0; l < nl; ++l)
             for (int i = S.lev_ptr[l]; i < S.lev_ptr[l + 1]; ++i)
                 for (int s2 = 0; s2 < KW; ++s2) d.lev_Kb[l] += S.Kcol[(size_t)s2 * n + i] != n ? 1.0 : 0.0;
-        if (prm.precision == GKS_MIXED) {
-            d.split = S.tri_free;
-            // split form: Dinv K_L and Dinv K_U in L's and U's slots; general
-            // form: the factors L and U themselves
-            d.Lval32 = dev_upload(m, pack_sliced<float>(d.split ? S.KLs : S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr));
-            d.Uval32 = dev_upload(m, pack_sliced<float>(d.split ? S.KUs : S.Uval, S.Ucol, n, S.lev_ptr, Us, nullptr));
-        }
     }
-    d.Dinv = dev_upload(m, pack_blocks<double>(S.Dv, 1, n, np));
+    if (prm.precision == GKS_MIXED) {
+        d.split = S.tri_free;
+        // split form: Dinv K_L and Dinv K_U in L's and U's slots; general
+        // form: the factors L and U themselves
+        up.add_owned(pack_sliced<float>(d.split ? S.KLs : S.Lval, S.Lcol, n, S.lev_ptr, Ls, nullptr), &d.Lval32);
+        up.add_owned(pack_sliced<float>(d.split ? S.KUs : S.Uval, S.Ucol, n, S.lev_ptr, Us, nullptr), &d.Uval32);
+    }
+    up.add_owned(pack_blocks<double>(S.Dv, 1, n, np), &d.Dinv);
     if (prm.precision == GKS_MIXED) {
         if (d.split)
-            d.E32 = dev_upload(m, pack_blocks<float>(S.Gs, 1, n, np));   // Dinv E
+            up.add_owned(pack_blocks<float>(S.Gs, 1, n, np), &d.E32);   // Dinv E
         else
-            d.Kval32 = dev_upload(m, pack_blocks<float>(S.Kval, KW, n, np));
-        d.Dinv32 = dev_upload(m, pack_blocks<float>(S.Dv, 1, n, np));
+            up.add_owned(pack_blocks<float>(S.Kval, KW, n, np), &d.Kval32);
+        up.add_owned(pack_blocks<float>(S.Dv, 1, n, np), &d.Dinv32);
     }
-
-    // ---- work space
+    up.add_owned(std::vector<double>((size_t)(MAXM + 1) * NC, 1.0), &m->w.ones);
+    pt.mark("pack device layouts");
+    up.send(m);
+    pt.mark("upload");
+    // ---- work space: one zeroed allocation
     Work& w = m->w;
     const size_t vec = (size_t)(n + 1) * CB;
     const int mres = prm.restart;
-    w.X = dev_alloc<double>(m, vec);
-    w.R = dev_alloc<double>(m, vec);
-    w.V = dev_alloc<double>(m, vec * (mres + 1));
+    Arena ws;
+    ws.add(&w.X, vec);
+    ws.add(&w.R, vec);
+    ws.add(&w.V, vec * (mres + 1));
     if (prm.precision == GKS_MIXED) {
-        w.Z = dev_alloc<float>(m, vec * mres);
-        w.yf = dev_alloc<float>(m, vec);
-        w.df = dev_alloc<float>(m, vec);
-        w.bf = dev_alloc<float>(m, vec);
+        ws.add(&w.Z, vec * mres);
+        ws.add(&w.yf, vec);
+        ws.add(&w.df, vec);
+        ws.add(&w.bf, vec);
     }
-    w.Xp = dev_alloc<float>(m, vec);
-    w.Xpp = dev_alloc<float>(m, vec);
-    w.w = dev_alloc<double>(m, vec);
-    w.t1 = dev_alloc<double>(m, vec);
-    w.t2 = dev_alloc<double>(m, vec);
-    w.t3 = dev_alloc<double>(m, vec);
+    ws.add(&w.Xp, vec);
+    ws.add(&w.Xpp, vec);
+    ws.add(&w.w, vec);
+    ws.add(&w.t1, vec);
+    ws.add(&w.t2, vec);
+    ws.add(&w.t3, vec);
     w.nblk_red = std::max(1, std::min(1024, (n + 255) / 256));
-    w.partial = dev_alloc<double>(m, (size_t)w.nblk_red * (MAXM + 1) * NC);
-    w.npart = dev_alloc<double>(m, (size_t)NC * (((size_t)n * 10 + 255) / 256 + 1));
-    w.dpart = dev_alloc<double>(m, (size_t)FUSED_DOTS_MAX * NC * (std::max<size_t>((n + 255) / 256, 2048) + 1));
-    {
-        std::vector<double> ones((size_t)(MAXM + 1) * NC, 1.0);
-        w.ones = dev_upload(m, ones);
-    }
-    w.ks = dev_alloc<KrylovState>(m, 1);
-    w.Xcell = dev_alloc<double>(m, (size_t)20 * nt);
+    ws.add(&w.partial, (size_t)w.nblk_red * (MAXM + 1) * NC);
+    ws.add(&w.npart, (size_t)NC * (((size_t)n * 10 + 255) / 256 + 1));
+    ws.add(&w.dpart, (size_t)FUSED_DOTS_MAX * NC * (std::max<size_t>((n + 255) / 256, 2048) + 1));
+    ws.add(&w.ks, 1);
+    ws.add(&w.Xcell, (size_t)20 * nt);
+    ws.add(&w.F, (size_t)4 * nf);
+    ws.add(&w.Wn, (size_t)4 * nt);
+    ws.add(&w.Wint, (size_t)4 * nt);
+    ws.add(&w.dt_dev, 1);
+    ws.add(&w.dtpart, 1024);
+    ws.add(&w.counters, 4);
+    ws.commit(m);
     if (prm.limiter) ensure_limit_buffers(m);
-    w.F = dev_alloc<double>(m, (size_t)4 * nf);
-    w.Wn = dev_alloc<double>(m, (size_t)4 * nt);
-    w.Wint = dev_alloc<double>(m, (size_t)4 * nt);
-    w.dt_dev = dev_alloc<double>(m, 1);
-    w.dtpart = dev_alloc<double>(m, 1024);
-    w.counters = (int32_t*)dev_alloc<double>(m, 2);
     {
+        // pinned status words, read back by the host: one allocation
+        constexpr size_t o_cnt = (sizeof(Status) + 63) / 64 * 64, o_scal = o_cnt + 64;
+        char* hp = nullptr;
         std::lock_guard<std::mutex> lk(g_dev_mu);
-        HIPCHK(hipHostMalloc((void**)&w.st_host, sizeof(Status), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&w.counters_host, 4 * sizeof(int32_t), hipHostMallocDefault));
-        HIPCHK(hipHostMalloc((void**)&w.scal_host, 4 * sizeof(double), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&hp, o_scal + 4 * sizeof(double), hipHostMallocDefault));
+        w.st_host = (Status*)hp;
+        w.counters_host = (int32_t*)(hp + o_cnt);
+        w.scal_host = (double*)(hp + o_scal);
     }
-    HIPCHK(hipMemcpyAsync(&w.ks->tol, &prm.tol, sizeof(double), hipMemcpyHostToDevice, m->stream));
-    HIPCHK(hipStreamSynchronize(m->stream));
+    launch_set_scalar(m, &w.ks->tol, prm.tol);
+    pt.mark("work space");
 }
 
 // ------------------------------------------------------------------ GMRES driver (FP64)
@@ -1762,9 +1883,7 @@ void gks_destroy(gks_mesh* m) {
         if (c) (void)hipGraphExecDestroy(c);
     for (void* p : m->allocs) (void)hipFree(p);
     if (m->own_stream && m->stream) (void)hipStreamDestroy(m->stream);
-    if (m->w.st_host) (void)hipHostFree(m->w.st_host);
-    if (m->w.counters_host) (void)hipHostFree(m->w.counters_host);
-    if (m->w.scal_host) (void)hipHostFree(m->w.scal_host);
+    if (m->w.st_host) (void)hipHostFree(m->w.st_host);   // the status words share this allocation
     delete m;
 }
 
