@@ -556,6 +556,10 @@ struct Staging {
             const size_t o = pieces[q].second;
             std::memcpy(host.data() + off[pieces[q].first] + o, (const char*)it.src + o, std::min(PIECE, it.bytes - o));
         }
+        for (size_t k = 0; k < items.size(); ++k) {   // alignment gaps as zeros
+            const size_t end = k + 1 < items.size() ? off[k + 1] : tot;
+            std::memset(host.data() + off[k] + items[k].bytes, 0, end - off[k] - items[k].bytes);
+        }
         HIPCHK(hipMemcpyAsync(dev, host.data(), tot, hipMemcpyHostToDevice, m->stream));
         HIPCHK(hipStreamSynchronize(m->stream));
         for (size_t k = 0; k < items.size(); ++k) items[k].bind(dev + off[k]);
