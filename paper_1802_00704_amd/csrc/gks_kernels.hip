@@ -700,8 +700,12 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
         for (int q = 0; q < CB; ++q) ti[q] = wi[q] - wprev[q] + zi[q];
         rows_store(t, i0, nr, st, lane, ti);
     }
-    rows_store(w, i0, nr, st, lane, wi);
-    if (LAST) rows_store(z, i0, nr, st, lane, wi);
+    // rows of the last level have no upper neighbours: z = w, and no later
+    // pass reads their w
+    if (LAST)
+        rows_store(z, i0, nr, st, lane, wi);
+    else
+        rows_store(w, i0, nr, st, lane, wi);
 }
 
 template <bool BF, typename ACC>
@@ -731,25 +735,11 @@ __global__ void __launch_bounds__(TPB) k_es_bwd(int np, int r0, int r1, int sbas
     for (int q = 0; q < CB; ++q) zn[q] = (float)acc[q];
     rows_store(z, i0, nr, st, lane, zn);
     if (BF) {
-        // next sweep, forward, for a row without lower neighbours
-        float bi[CB];
-        rows_load(b, i0, nr, st, lane, bi);
-        ACC a2[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) a2[q] = (ACC)bi[q];
-        if (valid) {
-            float gb[25];
-            load_block(G, np, 0, i, gb);
-            block_add(a2, gb, zn);
-        }
-        float w2[CB], ti[CB];
-#pragma unroll
-        for (int q = 0; q < CB; ++q) {
-            w2[q] = (float)a2[q];
-            ti[q] = w2[q] - wi[q] + zn[q];
-        }
-        rows_store(t, i0, nr, st, lane, ti);
-        rows_store(w, i0, nr, st, lane, w2);
+        // The next sweep's forward pass for these rows, which have no lower
+        // neighbours: no elimination touched their pivots, so E = D - K_D is
+        // zero and the pass leaves w = b' unchanged and gives t = w - w_prev
+        // + z = z.  Only t is written.
+        rows_store(t, i0, nr, st, lane, zn);
     }
 }
 
@@ -1831,11 +1821,11 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         if (r1 <= r0) return;
         const int rows = r1 - r0;
         const bool last = l == nl - 1;
-        // blocks: Dinv K_L, and Dinv (first sweep) or Dinv E; vectors: v and
-        // b' written (first) or b', z read, w written; w_prev, t (middle
-        // levels), z (last level)
-        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + 2 * VF : 3 * VF)) +
-                          rows * VF * ((last ? 1 : 0) + (!first && !last ? 2 : 0));
+        // blocks: Dinv K_L, and Dinv (first sweep) or Dinv E; vectors: v read
+        // and b' written (first) or b', z read; then w written (z on the last
+        // level); w_prev read and t written on the middle levels
+        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + VF : 2 * VF) + VF) +
+                          rows * VF * (!first && !last ? 2 : 0);
         const int tb = sweep_tpb(rows);
         const dim3 g(nblocks(rows, tb)), bl(tb);
         if (first && last)
@@ -1855,9 +1845,8 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) return;
         const int rows = r1 - r0;
-        // blocks: Dinv K_U (+ Dinv E); vectors: w read, z written (+ b' read,
-        // t and w written)
-        const double by = D.lev_Ub[l] * 104.0 + rows * 2 * VF + (bf ? rows * (100.0 + 3 * VF) : 0.0);
+        // blocks: Dinv K_U; vectors: w read, z written (+ t written)
+        const double by = D.lev_Ub[l] * 104.0 + rows * 2 * VF + (bf ? rows * VF : 0.0);
         const int tb = sweep_tpb(rows);
         const dim3 g(nblocks(rows, tb)), bl(tb);
         if (bf)
