@@ -556,6 +556,7 @@ struct Staging {
             const size_t o = pieces[q].second;
             std::memcpy(host.data() + off[pieces[q].first] + o, (const char*)it.src + o, std::min(PIECE, it.bytes - o));
         }
+        held.clear();   // everything is in the staging buffer now
         for (size_t k = 0; k < items.size(); ++k) {   // alignment gaps as zeros
             const size_t end = k + 1 < items.size() ? off[k + 1] : tot;
             std::memset(host.data() + off[k] + items[k].bytes, 0, end - off[k] - items[k].bytes);
@@ -1052,6 +1053,27 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     const int np = d.np;
     up.add_owned(pack_blocks<double>(S.Kval, KW, n, np), &d.Kval);
     up.add(S.Kcol, &d.Kcol);
+    if (S.n_colors > 0) {
+        // SpMV wave order: chunk k of every colour in turn (rows of a colour
+        // are in RCM order, so chunk k covers about the same part of the mesh
+        // in each colour); chunks of about 4096 rows of the largest colour
+        const int nw = (n + 63) / 64;
+        const int nl = (int)S.lev_ptr.size() - 1;
+        std::vector<int> wa(nl + 1);
+        for (int l = 0; l <= nl; ++l) wa[l] = (S.lev_ptr[l] + 63) / 64;   // waves whose first row is in level l
+        int wmax = 1;
+        for (int l = 0; l < nl; ++l) wmax = std::max(wmax, wa[l + 1] - wa[l]);
+        const int K = std::max(1, (wmax + 63) / 64);
+        std::vector<int32_t> order;
+        order.reserve(nw);
+        for (int k = 0; k < K; ++k)
+            for (int l = 0; l < nl; ++l) {
+                const int64_t cnt = wa[l + 1] - wa[l];
+                for (int64_t g = wa[l] + cnt * k / K; g < wa[l] + cnt * (k + 1) / K; ++g) order.push_back((int32_t)g);
+            }
+        if ((int)order.size() != nw) throw Fail{GKS_EHIP, "internal: SpMV wave order does not cover the rows"};
+        up.add_owned(std::move(order), &d.worder);
+    }
     const SliceLayout Ls = slice_layout(S.Lcol, LW, n, S.lev_ptr);
     const SliceLayout Us = slice_layout(S.Ucol, LW, n, S.lev_ptr);
     {

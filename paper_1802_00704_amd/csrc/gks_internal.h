@@ -107,6 +107,9 @@ struct DevMesh {
     double* a0c = nullptr;        // [3][5][nt] CLS row-0 coefficients per neighbour slot (cell order)
     double* Kval = nullptr;       // [KW][25][n]
     int32_t* Kcol = nullptr;      // [KW][n] (n = dummy)
+    int32_t* worder = nullptr;    // [ceil(n / 64)] order in which the SpMV kernels take the 64-row
+                                  // groups (multicolour: a spatial chunk of every colour in turn);
+                                  // null: natural order
     float* Kval32 = nullptr;
     double* Lval = nullptr;       // sliced [chunk][25 * 64] strict lower factor blocks
     double* Uval = nullptr;       // sliced [chunk][25 * 64] strict upper factor blocks

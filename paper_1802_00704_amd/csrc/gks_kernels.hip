@@ -42,6 +42,21 @@ __device__ __forceinline__ int xcd_block() {
 }
 __device__ __forceinline__ int xcd_row() { return xcd_block() * blockDim.x + threadIdx.x; }
 
+// Row of a thread in the SpMV kernels.  With a wave order, the launch's
+// waves take the 64-row groups in that order: in multicolour order it
+// cycles through the colours chunk by chunk, so the rows that one XCD works
+// on at a time cover one part of the mesh in every colour and the neighbour
+// rows they gather (all in other colours) meet again in that XCD's L2.
+// Waves past the table get rows past n (no work).
+__device__ __forceinline__ int spmv_row(const int32_t* __restrict__ worder, int n) {
+    const int r = xcd_row();
+    if (!worder) return r;
+    const int nw = (n + 63) >> 6;
+    const int g = r >> 6;   // wave-uniform
+    const int w = g < nw ? __builtin_amdgcn_readfirstlane(worder[g]) : nw;
+    return w * 64 + (r & 63);
+}
+
 
 // ------------------------------------------------------------------ block loads
 // Matrix storage ("vector-packed"): for slot s of row i, entries e < 24 of the
@@ -189,12 +204,13 @@ __device__ __forceinline__ void rows_store(T* __restrict__ a, int64_t i0, int nr
 // sums of y^2 (no early return then: every thread reaches the reduction).
 template <typename T, typename XT, bool RESID>
 __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ worder,
                                               const XT* __restrict__ x, const double* __restrict__ xscale,
                                               const double* __restrict__ b, double* __restrict__ y,
     const int32_t* __restrict__ gate, double* __restrict__ partial = nullptr) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
-    const int i = xcd_row();
+    const int i = spmv_row(worder, n);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)i - lane;                  // first row of the wave
     const int nr = (int)max((int64_t)0, min((int64_t)64, (int64_t)n - i0));
@@ -280,13 +296,14 @@ __device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int
 // contiguous rows in 16-byte pairs, so every V_j read is lane-contiguous.
 template <typename XT>
 __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* __restrict__ val,
-                                                   const int32_t* __restrict__ col, const XT* __restrict__ x,
+                                                   const int32_t* __restrict__ col, const int32_t* __restrict__ worder,
+                                                   const XT* __restrict__ x,
                                                    double* __restrict__ y, const double* __restrict__ V,
                                                    int64_t vstride, int nvd, double* __restrict__ dpart,
                                                    const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
-    const int i = xcd_row();
+    const int i = spmv_row(worder, n);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)i - lane;
     const int nr = (int)max((int64_t)0, min((int64_t)64, (int64_t)n - i0));
@@ -1699,13 +1716,13 @@ void launch_rhs(gks_mesh* m, const double* W, double* sq_out) {
 void launch_spmv64(gks_mesh* m, const double* x, const double* xscale, double* y, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_SPMV, spmv_bytes(n, 8, false), hipLaunchKernelGGL((k_spmv<double, double, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, xscale, nullptr, y, gate));
+                                         m->d.Kval, m->d.Kcol, m->d.worder, x, xscale, nullptr, y, gate));
 }
 
 void launch_spmv64_f32x(gks_mesh* m, const float* x, double* y, const int32_t* gate) {
     const int n = m->d.n;
     PROFB(KC_SPMV, n * (KW * 25.0 * 8 + KW * 4.0 + VB / 2 + VB), hipLaunchKernelGGL((k_spmv<double, float, false>), dim3(nblocks(n)), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, nullptr, nullptr, y, gate));
+                                         m->d.Kval, m->d.Kcol, m->d.worder, x, nullptr, nullptr, y, gate));
 }
 
 // y = K x with the products V_j . y (j < nvd <= RED_CHUNK) reduced to
@@ -1717,7 +1734,7 @@ static void spmv_dots(gks_mesh* m, const XT* x, double* y, const double* V, int6
     const int nb = nblocks(n);
     const double by = n * (KW * 25.0 * 8 + KW * 4.0 + (double)sizeof(XT) * CB + VB + nvd * VB);
     PROFB(KC_SPMV, by, hipLaunchKernelGGL(k_spmv_dots<XT>, dim3(nb), dim3(TPB), 0, m->stream, n, m->d.np, m->d.Kval,
-                                          m->d.Kcol, x, y, V, vstride, nvd, m->w.dpart, gate));
+                                          m->d.Kcol, m->d.worder, x, y, V, vstride, nvd, m->w.dpart, gate));
     PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(nvd * NC), dim3(TPB), 0, m->stream, nvd * NC, nb, m->w.dpart,
                                       scale, out, gate));
 }
@@ -1747,7 +1764,7 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
     const int nb = nblocks(n);
     double* part = sq_out ? m->w.npart : nullptr;
     PROFB(KC_SPMV_RES, spmv_bytes(n, 8, true), hipLaunchKernelGGL((k_spmv<double, double, true>), dim3(nb), dim3(TPB), 0, m->stream, n, m->d.np,
-                                         m->d.Kval, m->d.Kcol, x, nullptr, b, y, gate, part));
+                                         m->d.Kval, m->d.Kcol, m->d.worder, x, nullptr, b, y, gate, part));
     if (sq_out)
         PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(NC), dim3(TPB), 0, m->stream, NC, nb, part, nullptr, sq_out,
                                           gate));
