@@ -455,6 +455,26 @@ __device__ __forceinline__ void slice_sub(ACC (&acc)[CB], const T* __restrict__ 
     }
 }
 
+// As slice_sub, with x_j read from xlo for columns j < split, else from x.
+template <typename T, typename XT, typename ACC>
+__device__ __forceinline__ void slice_sub_split(ACC (&acc)[CB], const T* __restrict__ val,
+                                                const int32_t* __restrict__ col, const SliceRef& sr,
+                                                const XT* __restrict__ xlo, const XT* __restrict__ x, int split) {
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        if (s >= sr.w) break;
+        const int64_t ch = sr.ch0 + s;
+        const int j = col[ch * 64 + sr.lane];
+        const XT* xj = (j < split ? xlo : x) + (int64_t)j * CB;
+        XT xv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) xv[q] = xj[q];
+        T blk[25];
+        load_block(val + ch * 25 * 64, 64, 0, sr.lane, blk);
+        block_sub(acc, blk, xv);
+    }
+}
+
 // forward  y_i = s .* v_i - sum_{k<i} L_ik y_k            (unit lower factor)
 // backward z_i = Dinv_i (y_i - sum_{j>i} U_ij z_j)
 // over the rows [r0, r1) of one dependency level.
@@ -654,7 +674,7 @@ __device__ __forceinline__ void block_add(ACC (&acc)[CB], const float (&blk)[25]
 }
 
 template <bool FIRST, bool LAST, typename ACC>
-__global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, SlicedIdx Li,
+__global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li,
                                                 const float* __restrict__ KLv, const float* __restrict__ G,
                                                 const float* __restrict__ Dinv, const double* __restrict__ v,
                                                 const double* __restrict__ vscale, float* __restrict__ b,
@@ -706,7 +726,14 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
             block_add(acc, gb, zi);
         }
     }
-    if (valid) slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), FIRST ? w : t);
+    // lower neighbours: w in the first sweep; later, z for rows of level 0
+    // (rows [0, zrows): their t equals z) and t for the others
+    if (valid) {
+        if (FIRST)
+            slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), w);
+        else
+            slice_sub_split(acc, KLv, Li.col, slice_ref(Li, sbase, rl), (const float*)z, (const float*)t, zrows);
+    }
     float wi[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) wi[q] = (float)acc[q];
@@ -725,12 +752,10 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
         rows_store(w, i0, nr, st, lane, wi);
 }
 
-template <bool BF, typename ACC>
-__global__ void __launch_bounds__(TPB) k_es_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
-                                                const float* __restrict__ KUv, const float* __restrict__ G,
-                                                const float* __restrict__ b, float* __restrict__ t,
-                                                float* __restrict__ w, float* __restrict__ z,
-                                                const int32_t* __restrict__ gate) {
+template <typename ACC>
+__global__ void __launch_bounds__(TPB) k_es_bwd(int r0, int r1, int sbase, SlicedIdx Ui,
+                                                const float* __restrict__ KUv, const float* __restrict__ w,
+                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * CB / 4];
     const int rl = xcd_row();
@@ -751,13 +776,6 @@ __global__ void __launch_bounds__(TPB) k_es_bwd(int np, int r0, int r1, int sbas
 #pragma unroll
     for (int q = 0; q < CB; ++q) zn[q] = (float)acc[q];
     rows_store(z, i0, nr, st, lane, zn);
-    if (BF) {
-        // The next sweep's forward pass for these rows, which have no lower
-        // neighbours: no elimination touched their pivots, so E = D - K_D is
-        // zero and the pass leaves w = b' unchanged and gives t = w - w_prev
-        // + z = z.  Only t is written.
-        rows_store(t, i0, nr, st, lane, zn);
-    }
 }
 
 // ------------------------------------------------------------------ reductions
@@ -1847,38 +1865,35 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         const dim3 g(nblocks(rows, tb)), bl(tb);
         if (first && last)
             PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<true, true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+                                                     D.Lsbase[l], lp[1], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
         else if (first)
             PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<true, false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+                                                     D.Lsbase[l], lp[1], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
         else if (last)
             PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<false, true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+                                                     D.Lsbase[l], lp[1], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
         else
             PROFB(KC_ILU_FWD32, by, hipLaunchKernelGGL((k_es_fwd<false, false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Lsbase[l], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
+                                                     D.Lsbase[l], lp[1], D.Li, D.Lval32, D.E32, D.Dinv32, v, vscale, b, t, w, z, gate));
     };
-    auto bwd = [&](int l, bool bf) {
+    auto bwd = [&](int l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) return;
         const int rows = r1 - r0;
-        // blocks: Dinv K_U; vectors: w read, z written (+ t written)
-        const double by = D.lev_Ub[l] * 104.0 + rows * 2 * VF + (bf ? rows * VF : 0.0);
+        // blocks: Dinv K_U; vectors: w read, z written
+        const double by = D.lev_Ub[l] * 104.0 + rows * 2 * VF;
         const int tb = sweep_tpb(rows);
         const dim3 g(nblocks(rows, tb)), bl(tb);
-        if (bf)
-            PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<true, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, b, t, w, z, gate));
-        else
-            PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<false, ACC>), g, bl, 0, m->stream, D.np, r0, r1,
-                                                     D.Usbase[l], D.Ui, D.Uval32, D.E32, b, t, w, z, gate));
+        PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<ACC>), g, bl, 0, m->stream, r0, r1, D.Usbase[l], D.Ui,
+                                                 D.Uval32, w, z, gate));
     };
     for (int sw = 0; sw < q; ++sw) {
         const bool first = sw == 0;
-        // level 0's forward of a later sweep ran in the previous sweep's BF launch
+        // Level 0's forward pass of a later sweep changes nothing: its rows
+        // have no lower neighbours, so E = D - K_D = 0 there, w stays b' and
+        // t = w - w_prev + z is z, which the next levels gather directly.
         for (int l = (first || nl < 2) ? 0 : 1; l < nl; ++l) fwd(l, first);
-        for (int l = nl - 2; l >= 1; --l) bwd(l, false);
-        if (nl >= 2) bwd(0, sw + 1 < q);
+        for (int l = nl - 2; l >= 0; --l) bwd(l);
     }
 }
 
