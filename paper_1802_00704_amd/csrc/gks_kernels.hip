@@ -475,10 +475,42 @@ __device__ __forceinline__ void slice_sub_split(ACC (&acc)[CB], const T* __restr
     }
 }
 
+// As slice_sub, with x_j = xs .* xlo_j (per-column scale xs, none if null)
+// for columns j < split, else x_j.
+template <typename T, typename ACC>
+__device__ __forceinline__ void slice_sub_lo(ACC (&acc)[CB], const T* __restrict__ val,
+                                             const int32_t* __restrict__ col, const SliceRef& sr,
+                                             const double* __restrict__ xlo, const double* __restrict__ xs,
+                                             const double* __restrict__ x, int split) {
+#pragma unroll
+    for (int s = 0; s < LW; ++s) {
+        if (s >= sr.w) break;
+        const int64_t ch = sr.ch0 + s;
+        const int j = col[ch * 64 + sr.lane];
+        const bool lo = j < split;
+        const double* xj = (lo ? xlo : x) + (int64_t)j * CB;
+        double xv[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) xv[q] = xj[q];
+        if (lo && xs) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NB; ++r) xv[c * NB + r] *= xs[c];
+        }
+        T blk[25];
+        load_block(val + ch * 25 * 64, 64, 0, sr.lane, blk);
+        block_sub(acc, blk, xv);
+    }
+}
+
 // forward  y_i = s .* v_i - sum_{k<i} L_ik y_k            (unit lower factor)
 // backward z_i = Dinv_i (y_i - sum_{j>i} U_ij z_j)
-// over the rows [r0, r1) of one dependency level.
-__global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, SlicedIdx Li, const double* __restrict__ Lv,
+// over the rows [r0, r1) of one dependency level.  Rows of level 0 (rows
+// [0, zrows)) have no lower neighbours, so their y is s .* v: the forward
+// pass skips them and reads s .* v where it gathers them, and their backward
+// pass reads v with the scale.
+__global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, int zrows, SlicedIdx Li, const double* __restrict__ Lv,
                                                  const double* __restrict__ v, const double* __restrict__ vscale,
                                                  double* __restrict__ y, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
@@ -497,14 +529,14 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, Slic
 #pragma unroll
         for (int r = 0; r < NB; ++r) acc[c * NB + r] *= sc;
     }
-    if (lane < nr) slice_sub(acc, Lv, Li.col, slice_ref(Li, sbase, rl), y);
+    if (lane < nr) slice_sub_lo(acc, Lv, Li.col, slice_ref(Li, sbase, rl), v, vscale, (const double*)y, zrows);
     rows_store(y, i0, nr, st, lane, acc);
 }
 
 __global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
                                                  const double* __restrict__ Uv, const double* __restrict__ Dinv,
-                                                 const double* __restrict__ y, double* __restrict__ z,
-                                                 const int32_t* __restrict__ gate) {
+                                                 const double* __restrict__ y, const double* __restrict__ yscale,
+                                                 double* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];
     const int rl = xcd_row();
@@ -516,6 +548,14 @@ __global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sba
     const int i = (int)i0 + lane;
     double acc[CB];
     rows_load(y, i0, nr, st, lane, acc);
+    if (yscale) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            const double sc = yscale[c];
+#pragma unroll
+            for (int r = 0; r < NB; ++r) acc[c * NB + r] *= sc;
+        }
+    }
     double zi[CB];
 #pragma unroll
     for (int q = 0; q < CB; ++q) zi[q] = 0.0;
@@ -1910,19 +1950,24 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
     const DevMesh& D = m->d;
     const auto& lp = D.lev_ptr;
     const int nl = (int)lp.size() - 1;
-    for (int l = 0; l < nl; ++l) {
+    // level 0 (no lower neighbours: y = s .* v) has no forward launch
+    // when later levels read it from v
+    const int l0 = nl >= 2 ? 1 : 0;
+    const int zrows = l0 ? lp[1] : 0;
+    for (int l = l0; l < nl; ++l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         PROFB(KC_ILU_FWD, D.lev_Lb[l] * 204.0 + (r1 - r0) * 2.0 * VB,
-              hipLaunchKernelGGL(k_ilu_fwd, dim3(nblocks(r1 - r0, sweep_tpb(r1 - r0))), dim3(sweep_tpb(r1 - r0)), 0, m->stream, r0, r1, D.Lsbase[l], D.Li,
-                                 D.Lval, in, in_scale, tmp, gate));
+              hipLaunchKernelGGL(k_ilu_fwd, dim3(nblocks(r1 - r0, sweep_tpb(r1 - r0))), dim3(sweep_tpb(r1 - r0)), 0, m->stream, r0, r1, D.Lsbase[l],
+                                 zrows, D.Li, D.Lval, in, in_scale, tmp, gate));
     }
     for (int l = nl - 1; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
+        const bool from_v = l == 0 && l0 == 1;
         PROFB(KC_ILU_BWD, D.lev_Ub[l] * 204.0 + (r1 - r0) * (200.0 + 2.0 * VB),
               hipLaunchKernelGGL(k_ilu_bwd, dim3(nblocks(r1 - r0, sweep_tpb(r1 - r0))), dim3(sweep_tpb(r1 - r0)), 0, m->stream, D.np, r0, r1, D.Usbase[l],
-                                 D.Ui, D.Uval, D.Dinv, tmp, out, gate));
+                                 D.Ui, D.Uval, D.Dinv, from_v ? in : tmp, from_v ? in_scale : nullptr, out, gate));
     }
 }
 
