@@ -509,10 +509,14 @@ __device__ __forceinline__ void slice_sub_lo(ACC (&acc)[CB], const T* __restrict
 // over the rows [r0, r1) of one dependency level.  Rows of level 0 (rows
 // [0, zrows)) have no lower neighbours, so their y is s .* v: the forward
 // pass skips them and reads s .* v where it gathers them, and their backward
-// pass reads v with the scale.
-__global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, int zrows, SlicedIdx Li, const double* __restrict__ Lv,
+// pass reads v with the scale.  Rows of the last level have no upper
+// neighbours: its forward pass (LAST) writes z_i = Dinv_i y_i directly.
+template <bool LAST>
+__global__ void __launch_bounds__(TPB) k_ilu_fwd(int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li,
+                                                 const double* __restrict__ Lv, const double* __restrict__ Dinv,
                                                  const double* __restrict__ v, const double* __restrict__ vscale,
-                                                 double* __restrict__ y, const int32_t* __restrict__ gate) {
+                                                 double* __restrict__ y, double* __restrict__ z,
+                                                 const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
     const int rl = xcd_row();
@@ -530,7 +534,27 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int r0, int r1, int sbase, int 
         for (int r = 0; r < NB; ++r) acc[c * NB + r] *= sc;
     }
     if (lane < nr) slice_sub_lo(acc, Lv, Li.col, slice_ref(Li, sbase, rl), v, vscale, (const double*)y, zrows);
-    rows_store(y, i0, nr, st, lane, acc);
+    if (LAST) {
+        double zi[CB];
+#pragma unroll
+        for (int q = 0; q < CB; ++q) zi[q] = 0.0;
+        if (lane < nr) {
+            double d[25];
+            load_block(Dinv, np, 0, (int)i0 + lane, d);
+#pragma unroll
+            for (int c = 0; c < NC; ++c)
+#pragma unroll
+                for (int r = 0; r < NB; ++r) {
+                    double t = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NB; ++q) t += d[r * NB + q] * acc[c * NB + q];
+                    zi[c * NB + r] = t;
+                }
+        }
+        rows_store(z, i0, nr, st, lane, zi);
+    } else {
+        rows_store(y, i0, nr, st, lane, acc);
+    }
 }
 
 __global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
@@ -1954,14 +1978,22 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
     // when later levels read it from v
     const int l0 = nl >= 2 ? 1 : 0;
     const int zrows = l0 ? lp[1] : 0;
+    // the last level's forward pass also applies its pivot inverse (no upper
+    // neighbours), so its backward pass has no launch
     for (int l = l0; l < nl; ++l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
-        PROFB(KC_ILU_FWD, D.lev_Lb[l] * 204.0 + (r1 - r0) * 2.0 * VB,
-              hipLaunchKernelGGL(k_ilu_fwd, dim3(nblocks(r1 - r0, sweep_tpb(r1 - r0))), dim3(sweep_tpb(r1 - r0)), 0, m->stream, r0, r1, D.Lsbase[l],
-                                 zrows, D.Li, D.Lval, in, in_scale, tmp, gate));
+        const dim3 g(nblocks(r1 - r0, sweep_tpb(r1 - r0))), b(sweep_tpb(r1 - r0));
+        if (l == nl - 1)
+            PROFB(KC_ILU_FWD, D.lev_Lb[l] * 204.0 + (r1 - r0) * (200.0 + 2.0 * VB),
+                  hipLaunchKernelGGL(k_ilu_fwd<true>, g, b, 0, m->stream, D.np, r0, r1, D.Lsbase[l], zrows, D.Li, D.Lval,
+                                     D.Dinv, in, in_scale, tmp, out, gate));
+        else
+            PROFB(KC_ILU_FWD, D.lev_Lb[l] * 204.0 + (r1 - r0) * 2.0 * VB,
+                  hipLaunchKernelGGL(k_ilu_fwd<false>, g, b, 0, m->stream, D.np, r0, r1, D.Lsbase[l], zrows, D.Li, D.Lval,
+                                     D.Dinv, in, in_scale, tmp, out, gate));
     }
-    for (int l = nl - 1; l >= 0; --l) {
+    for (int l = nl - 2; l >= 0; --l) {
         const int r0 = lp[l], r1 = lp[l + 1];
         if (r1 <= r0) continue;
         const bool from_v = l == 0 && l0 == 1;
