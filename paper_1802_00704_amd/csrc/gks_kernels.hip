@@ -26,8 +26,10 @@ constexpr int TPB = 256;          // threads per block of the streaming kernels
 constexpr int RED_CHUNK = FUSED_DOTS_MAX;   // vectors per block of the dot kernels
 
 static inline int nblocks(int64_t n, int tpb = TPB) { return (int)((n + tpb - 1) / tpb); }
-// grid of the Gram-Schmidt update (grid-stride beyond): 8 blocks per CU
-constexpr int AXPY_BLOCKS = 2048;
+// grid of the Gram-Schmidt update (grid-stride beyond): about 8 blocks per
+// CU, a multiple of 5 (k_axpy_dots needs a grid of a multiple of 10 threads)
+// and of the 8 XCDs
+constexpr int AXPY_BLOCKS = 2040;
 
 // The hardware hands consecutive workgroups of a grid to the 8 XCDs in turn,
 // and each XCD has its own L2.  Row kernels gather neighbour blocks, so they
@@ -361,23 +363,29 @@ __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* 
 
 // out = w - sum_j h_j[c] scale_j[c] V_j and, in the same pass, the second
 // Gram-Schmidt products V_j . out for j < nvec <= RED_CHUNK (block partials
-// to dpart).  Grid-stride over 16-byte groups as k_axpy; out may alias w.
+// to dpart).  Grid-stride over 16-byte groups (pair p of a 20-double row);
+// the launch makes the grid a multiple of 10 threads, so each thread keeps
+// one pair position, hence fixed columns c0, c1 and fixed coefficients.
+// out may alias w.
 __global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
                                                    const double* __restrict__ h, const double* __restrict__ scale,
                                                    const double* w, double* out, double* __restrict__ dpart,
                                                    const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    double d[RED_CHUNK][NC];
-#pragma unroll
-    for (int j = 0; j < RED_CHUNK; ++j)
-#pragma unroll
-        for (int c = 0; c < NC; ++c) d[j][c] = 0.0;
     const int64_t npair = (int64_t)n * 10;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npair; t += (int64_t)gridDim.x * blockDim.x) {
-        const int64_t i = t / 10;
-        const int p = (int)(t - i * 10);
-        const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
-        const int64_t off = i * CB + 2 * p;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int p = (int)(t0 % 10);
+    const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
+    double hs0[RED_CHUNK], hs1[RED_CHUNK], d0[RED_CHUNK], d1[RED_CHUNK];
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j) {
+        hs0[j] = j < nvec ? h[j * NC + c0] * scale[j * NC + c0] : 0.0;
+        hs1[j] = j < nvec ? h[j * NC + c1] * scale[j * NC + c1] : 0.0;
+        d0[j] = 0.0;
+        d1[j] = 0.0;
+    }
+    for (int64_t t = t0; t < npair; t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t off = (t / 10) * CB + 2 * p;
         const double2 w2 = *reinterpret_cast<const double2*>(w + off);
         double a0 = w2.x, a1 = w2.y;
         double2 vv[RED_CHUNK];
@@ -385,19 +393,24 @@ __global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restri
         for (int j = 0; j < RED_CHUNK; ++j) {
             if (j < nvec) {
                 vv[j] = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
-                a0 -= h[j * NC + c0] * scale[j * NC + c0] * vv[j].x;
-                a1 -= h[j * NC + c1] * scale[j * NC + c1] * vv[j].y;
+                a0 -= hs0[j] * vv[j].x;
+                a1 -= hs1[j] * vv[j].y;
             }
         }
         *reinterpret_cast<double2*>(out + off) = make_double2(a0, a1);
 #pragma unroll
         for (int j = 0; j < RED_CHUNK; ++j) {
             if (j < nvec) {
-#pragma unroll
-                for (int c = 0; c < NC; ++c) d[j][c] += (c == c0 ? vv[j].x * a0 : 0.0) + (c == c1 ? vv[j].y * a1 : 0.0);
+                d0[j] += vv[j].x * a0;
+                d1[j] += vv[j].y * a1;
             }
         }
     }
+    double d[RED_CHUNK][NC];
+#pragma unroll
+    for (int j = 0; j < RED_CHUNK; ++j)
+#pragma unroll
+        for (int c = 0; c < NC; ++c) d[j][c] = (c == c0 ? d0[j] : 0.0) + (c == c1 ? d1[j] : 0.0);
     block_dots(d, nvec, dpart);
 }
 
@@ -1834,7 +1847,8 @@ void launch_spmv64_f32x_dots(gks_mesh* m, const float* x, double* y, const doubl
 void launch_axpy_dots(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
                       const double* w, double* out, double* dots_out, const int32_t* gate) {
     const int n = m->d.n;
-    const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));
+    // a multiple of 5 blocks of 256 threads: the grid is a multiple of 10 threads
+    const int nb = (std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10)) + 4) / 5 * 5;
     PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy_dots, dim3(nb), dim3(TPB), 0, m->stream, n, V, vstride,
                                                                    nvec, h, scale, w, out, m->w.dpart, gate));
     PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(nvec * NC), dim3(TPB), 0, m->stream, nvec * NC, nb, m->w.dpart,
