@@ -295,7 +295,7 @@ def main():
     ap.add_argument("--graphs", type=int, default=1, choices=[0, 1],
                     help="1: steps replay captured HIP graphs; 0: eager launches (counter runs use 0 so that "
                          "every traced launch does work)")
-    ap.add_argument("--serving-requests", type=int, default=60,
+    ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving stream to run after the throughput legs (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
     ap.add_argument("--no-limiter-leg", action="store_true",
