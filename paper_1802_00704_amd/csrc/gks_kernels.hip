@@ -724,8 +724,11 @@ __global__ void __launch_bounds__(TPB) k_mx_bwd(int np, int r0, int r1, int sbas
 //            t_i = w_i - w_prev_i + z_i           (first sweep: z = 0, t = w)
 //   backward z'_i = w_i - sum_{j>i} U'_ij z'_j
 // The last level has no upper neighbours (z'_i = w_i, set by the forward
-// kernel); the backward kernel of level 0 can also run the next sweep's
-// forward for its rows, which have no lower neighbours (BF).
+// kernel).  Level 0 has no lower neighbours, so its pivots are untouched by
+// the elimination: G = 0 there, w = b' in every sweep and t = z after the
+// first.  Level 0 therefore has a forward pass only in the first sweep, which
+// stores b' alone; later levels gather b' (first sweep) or z (later sweeps)
+// for level-0 neighbours, and level 0's backward pass reads b' as its w.
 template <typename ACC>
 __device__ __forceinline__ void block_mul(float (&out)[CB], const float (&blk)[25], const ACC (&x)[CB]) {
 #pragma unroll
@@ -803,11 +806,12 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
             block_add(acc, gb, zi);
         }
     }
-    // lower neighbours: w in the first sweep; later, z for rows of level 0
-    // (rows [0, zrows): their t equals z) and t for the others
+    // lower neighbours: for rows of level 0 (rows [0, zrows)) b' in the
+    // first sweep (their w) and z later (their t); for the others w in the
+    // first sweep and t later
     if (valid) {
         if (FIRST)
-            slice_sub(acc, KLv, Li.col, slice_ref(Li, sbase, rl), w);
+            slice_sub_split(acc, KLv, Li.col, slice_ref(Li, sbase, rl), (const float*)b, (const float*)w, zrows);
         else
             slice_sub_split(acc, KLv, Li.col, slice_ref(Li, sbase, rl), (const float*)z, (const float*)t, zrows);
     }
@@ -822,10 +826,10 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
         rows_store(t, i0, nr, st, lane, ti);
     }
     // rows of the last level have no upper neighbours: z = w, and no later
-    // pass reads their w
+    // pass reads their w; level 0's w is b', already stored
     if (LAST)
         rows_store(z, i0, nr, st, lane, wi);
-    else
+    else if (!(FIRST && r1 <= zrows))
         rows_store(w, i0, nr, st, lane, wi);
 }
 
@@ -1937,7 +1941,9 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         // blocks: Dinv K_L, and Dinv (first sweep) or Dinv E; vectors: v read
         // and b' written (first) or b', z read; then w written (z on the last
         // level); w_prev read and t written on the middle levels
-        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + VF : 2 * VF) + VF) +
+        // (the first sweep's level 0 writes b' alone: its w is b')
+        const bool wout = last || !(first && l == 0);
+        const double by = D.lev_Lb[l] * 104.0 + rows * (100.0 + (first ? VB + VF : 2 * VF) + (wout ? VF : 0.0)) +
                           rows * VF * (!first && !last ? 2 : 0);
         const int tb = sweep_tpb(rows);
         const dim3 g(nblocks(rows, tb)), bl(tb);
@@ -1963,7 +1969,7 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
         const int tb = sweep_tpb(rows);
         const dim3 g(nblocks(rows, tb)), bl(tb);
         PROFB(KC_ILU_BWD32, by, hipLaunchKernelGGL((k_es_bwd<ACC>), g, bl, 0, m->stream, r0, r1, D.Usbase[l], D.Ui,
-                                                 D.Uval32, w, z, gate));
+                                                 D.Uval32, l == 0 ? b : w, z, gate));
     };
     for (int sw = 0; sw < q; ++sw) {
         const bool first = sw == 0;
