@@ -264,6 +264,9 @@ typedef struct {
     int32_t* ucol;     /* [3][nt] strict upper factor                        */
     double*  uval;     /* [3][25][nt]                                        */
     double*  dinv;     /* [25][nt] inverted pivot blocks                     */
+    int32_t* spmv_order;   /* [n_spmv_waves] order in which the SpMV kernels take the
+                              64-row groups of solver rows (multicolour order), or NULL */
+    int32_t  n_spmv_waves; /* ceil(nt / 64) with a multicolour order, else 0    */
 } gks_host_system;
 
 int  gks_host_inspect(const gks_mesh_desc* desc, const gks_params* prm, gks_host_system* out);

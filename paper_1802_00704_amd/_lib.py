@@ -77,7 +77,7 @@ class HostSystem(C.Structure):
             ("own", C.c_int32), ("nbr", C.c_int32), ("area", C.c_double), ("h", C.c_double),
             ("perm", C.c_int32), ("lev_ptr", C.c_int32), ("kcol", C.c_int32), ("kval", C.c_double),
             ("lcol", C.c_int32), ("lval", C.c_double), ("ucol", C.c_int32), ("uval", C.c_double),
-            ("dinv", C.c_double))]
+            ("dinv", C.c_double), ("spmv_order", C.c_int32))] + [("n_spmv_waves", C.c_int32)]
 
 
 _lib = None
@@ -194,7 +194,8 @@ def host_inspect(mesh, params: Params | None = None, **kw) -> dict:
                "kcol": arr(hs.kcol, 4 * nt).reshape(4, nt), "kval": arr(hs.kval, 100 * nt).reshape(4, 25, nt),
                "lcol": arr(hs.lcol, 3 * nt).reshape(3, nt), "lval": arr(hs.lval, 75 * nt).reshape(3, 25, nt),
                "ucol": arr(hs.ucol, 3 * nt).reshape(3, nt), "uval": arr(hs.uval, 75 * nt).reshape(3, 25, nt),
-               "dinv": arr(hs.dinv, 25 * nt).reshape(25, nt)}
+               "dinv": arr(hs.dinv, 25 * nt).reshape(25, nt),
+               "spmv_order": arr(hs.spmv_order, hs.n_spmv_waves) if hs.n_spmv_waves else None}
     finally:
         lib().gks_host_free(C.byref(hs))
     return out

@@ -608,6 +608,7 @@ struct HostSystem {
     // Dinv_i K_ij (j > i), Dinv_i E_i
     hvec<double> KLs, KUs, Gs;
     std::vector<int32_t> Kcol, nbc, iperm, Lcol, Ucol;
+    std::vector<int32_t> worder;                  // SpMV order of the 64-row groups (multicolour only)
     std::vector<int32_t> own, nbr, cface, bck;
     std::vector<double> fgeo, gpd, cgeo, bcs;
 };
@@ -782,6 +783,25 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
     for (int l = 0; l < nkeys; ++l) S.lev_ptr[l + 1] += S.lev_ptr[l];
     S.n_levels = nkeys;
 
+    if (S.n_colors > 0) {
+        // SpMV wave order: chunk k of every colour in turn (rows of a colour
+        // are in RCM order, so chunk k covers about the same part of the mesh
+        // in each colour); chunks of about 4096 rows of the largest colour
+        const int nw = (nt + 63) / 64;
+        const int nl = nkeys;
+        std::vector<int> wa(nl + 1);
+        for (int l = 0; l <= nl; ++l) wa[l] = (S.lev_ptr[l] + 63) / 64;   // waves whose first row is in level l
+        int wmax = 1;
+        for (int l = 0; l < nl; ++l) wmax = std::max(wmax, wa[l + 1] - wa[l]);
+        const int K = std::max(1, (wmax + 63) / 64);
+        S.worder.reserve(nw);
+        for (int k = 0; k < K; ++k)
+            for (int l = 0; l < nl; ++l) {
+                const int64_t cnt = wa[l + 1] - wa[l];
+                for (int64_t g = wa[l] + cnt * k / K; g < wa[l] + cnt * (k + 1) / K; ++g) S.worder.push_back((int32_t)g);
+            }
+        if ((int)S.worder.size() != nw) throw Fail{GKS_EINVAL, "internal: SpMV wave order does not cover the rows"};
+    }
     pt.mark("ordering");
     // matrix in solver order: slot 0 diagonal, then neighbours, padded with the dummy row
     const int n = nt;
@@ -1053,27 +1073,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     const int np = d.np;
     up.add_owned(pack_blocks<double>(S.Kval, KW, n, np), &d.Kval);
     up.add(S.Kcol, &d.Kcol);
-    if (S.n_colors > 0) {
-        // SpMV wave order: chunk k of every colour in turn (rows of a colour
-        // are in RCM order, so chunk k covers about the same part of the mesh
-        // in each colour); chunks of about 4096 rows of the largest colour
-        const int nw = (n + 63) / 64;
-        const int nl = (int)S.lev_ptr.size() - 1;
-        std::vector<int> wa(nl + 1);
-        for (int l = 0; l <= nl; ++l) wa[l] = (S.lev_ptr[l] + 63) / 64;   // waves whose first row is in level l
-        int wmax = 1;
-        for (int l = 0; l < nl; ++l) wmax = std::max(wmax, wa[l + 1] - wa[l]);
-        const int K = std::max(1, (wmax + 63) / 64);
-        std::vector<int32_t> order;
-        order.reserve(nw);
-        for (int k = 0; k < K; ++k)
-            for (int l = 0; l < nl; ++l) {
-                const int64_t cnt = wa[l + 1] - wa[l];
-                for (int64_t g = wa[l] + cnt * k / K; g < wa[l] + cnt * (k + 1) / K; ++g) order.push_back((int32_t)g);
-            }
-        if ((int)order.size() != nw) throw Fail{GKS_EHIP, "internal: SpMV wave order does not cover the rows"};
-        up.add_owned(std::move(order), &d.worder);
-    }
+    if (!S.worder.empty()) up.add(S.worder, &d.worder);
     const SliceLayout Ls = slice_layout(S.Lcol, LW, n, S.lev_ptr);
     const SliceLayout Us = slice_layout(S.Ucol, LW, n, S.lev_ptr);
     {
@@ -1868,6 +1868,8 @@ int gks_host_inspect(const gks_mesh_desc* desc, const gks_params* prm, gks_host_
         out->ucol = dup(S.Ucol);
         out->uval = dup(S.Uval);
         out->dinv = dup(S.Dv);
+        out->n_spmv_waves = (int32_t)S.worder.size();
+        out->spmv_order = S.worder.empty() ? nullptr : dup(S.worder);
         (void)nf;
     } catch (const Fail& f) {
         g_create_err = f.msg;
@@ -1884,7 +1886,7 @@ int gks_host_inspect(const gks_mesh_desc* desc, const gks_params* prm, gks_host_
 void gks_host_free(gks_host_system* s) {
     if (!s) return;
     void* ptrs[] = {s->own, s->nbr, s->area, s->h, s->perm, s->lev_ptr, s->kcol, s->kval,
-                    s->lcol, s->lval, s->ucol, s->uval, s->dinv};
+                    s->lcol, s->lval, s->ucol, s->uval, s->dinv, s->spmv_order};
     for (void* q : ptrs) std::free(q);
     std::memset(s, 0, sizeof(*s));
 }

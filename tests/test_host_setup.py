@@ -6,6 +6,8 @@
   renumbering is a permutation whose levels respect the sweep dependencies;
   the BILU(0) factors reproduce K on its pattern ((L + I)(D + U) = K there).
 * Invalid meshes are rejected with GKS_EINVAL.
+* The SpMV kernels' order of 64-row groups is a permutation that goes
+  through the colours chunk by chunk.
 """
 import os
 import re
@@ -197,3 +199,37 @@ def test_bilu0_has_no_fill_on_triangle_free_cell_graphs():
     assert all(np.array_equal(U[key], K[key]) for key in U)
     K, U = _factor_blocks(g.host_inspect(split_some_triangles(mesh)))
     assert not all(np.array_equal(U[key], K[key]) for key in U)
+
+
+def test_spmv_wave_order_is_a_chunked_permutation():
+    """Multicolour order: the SpMV kernels take the 64-row groups of solver
+    rows in an order that goes through the colours chunk by chunk.  It must
+    visit every group exactly once, keep each colour's groups ascending
+    (RCM order inside a colour), and switch colour only between chunks, so
+    that the groups near in the order lie in one part of the mesh.  The RCM
+    level order keeps the natural order (no table)."""
+    left, _ = gi.shock_vortex_states()
+    walls = ((gi.BC_INFLOW, left), (gi.BC_OUTFLOW, None), (gi.BC_SLIP, None), (gi.BC_SLIP, None))
+    mesh = gi.jss_mesh(240, 120, 3, Lx=2.0, Ly=1.0, periodic=False, walls=walls)   # 115,200 triangles
+    hs = g.host_inspect(mesh)
+    n = hs["nt"]
+    order = hs["spmv_order"]
+    nw = (n + 63) // 64
+    assert order is not None and len(order) == nw
+    assert np.array_equal(np.sort(order), np.arange(nw))
+    # colour of each group = level of its first row
+    colour = np.searchsorted(hs["lev_ptr"], 64 * order, side="right") - 1
+    for c in range(hs["n_levels"]):
+        seq = order[colour == c]
+        assert np.all(np.diff(seq) > 0)
+    groups = [(hs["lev_ptr"][c + 1] + 63) // 64 - (hs["lev_ptr"][c] + 63) // 64 for c in range(hs["n_levels"])]
+    chunks = max(1, (max(groups) + 63) // 64)
+    runs = 1 + int(np.count_nonzero(np.diff(colour)))
+    assert chunks >= 4 and chunks <= runs <= chunks * hs["n_levels"]
+    # a chunk spans about the same RCM fraction of every colour
+    pos = [np.flatnonzero(colour == c) for c in range(hs["n_levels"])]
+    for c in range(1, hs["n_levels"]):
+        a = np.interp(np.linspace(0, 1, 50), np.linspace(0, 1, len(pos[0])), pos[0])
+        b = np.interp(np.linspace(0, 1, 50), np.linspace(0, 1, len(pos[c])), pos[c])
+        assert np.max(np.abs(a - b)) <= 1.2 * nw / chunks + 2
+    assert g.host_inspect(mesh, ordering=g.GKS_ORDER_RCM)["spmv_order"] is None
