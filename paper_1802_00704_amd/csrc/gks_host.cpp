@@ -749,6 +749,20 @@ void build_system(const gks_mesh_desc* de, const gks_params& prm, HostSystem& S)
             col[i] = c;
             nkeys = std::max(nkeys, c + 1);
         }
+        // Order of the colour classes.  After the first sweep, level 0 has a
+        // backward pass only and the last level a forward pass only, while
+        // middle levels take both: the largest class goes first, the second
+        // largest last, the smaller ones in between.
+        if (nkeys >= 3) {
+            std::vector<int> cnt(nkeys, 0), byc(nkeys), newc(nkeys);
+            for (int i = 0; i < nt; ++i) ++cnt[col[i]];
+            std::iota(byc.begin(), byc.end(), 0);
+            std::stable_sort(byc.begin(), byc.end(), [&](int a, int b) { return cnt[a] > cnt[b]; });
+            newc[byc[0]] = 0;
+            newc[byc[1]] = nkeys - 1;
+            for (int k = 2; k < nkeys; ++k) newc[byc[k]] = k - 1;
+            for (int i = 0; i < nt; ++i) col[i] = newc[col[i]];
+        }
         key = col;
         S.n_colors = nkeys;
     }
