@@ -15,8 +15,8 @@ w = 0.3 (Eq. A:B:b:3).  All rows over all pairs form one over-determined
 system C u = b (Eq. spdConserved:4), solved in the least-squares sense
 through its normal equations C^T C u = C^T b (Eq. spdConserved:5).
 
-Reading of the paper used here (stated in the design doc): the normal equations
-are those of the single global system ("reading G").  ``reading='P'``
+Reading of the paper used here: the normal equations are those of the
+single global system ("reading G"), as Eq. spdConserved:5 is written.  ``reading='P'``
 switches to the per-cell reading (only A^T applied), which has the same
 right-hand side and sparsity.
 

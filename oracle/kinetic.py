@@ -222,7 +222,8 @@ def side_slopes(W, Wn, Wt, Wnn, Wnt, Wtt, mom_full, with_At=False):
 
 def collision_time(pL, pR, p0, dt, mu, eps):
     """Eq. tauIns (mu = 0) or Eq. tauVis (mu > 0); the pressure-jump term is
-    multiplied by dt (reading stated in the design doc)."""
+    multiplied by dt (as printed it has no time unit, so it is read as a
+    fraction of the step)."""
     jump = np.abs(pL - pR) / np.abs(pL + pR) * dt
     if mu > 0.0:
         return mu / p0 + jump

@@ -4,7 +4,8 @@
   derivatives at the two Gauss points of each face (Eq. fluxgauss) and rotate
   them into the face frame (normal, tangent).
 * The face flux is sum_l (S/2) F_l of the time-integrated Gauss-point fluxes
-  (two-point Gauss-Legendre rule, reading stated in the design doc), rotated back.
+  (two-point Gauss-Legendre rule: the paper leaves the number of points
+  open), rotated back.
 * The update is Eq. fvm3: W_i <- W_i - (1/|Omega_i|) sum_f s_if F_f with
   s = +1 for the owner and -1 for the neighbour.
 * The time step (the paper gives none) is
