@@ -160,7 +160,22 @@ def rhs(geo: Geometry, pairs, W: np.ndarray) -> np.ndarray:
     return R
 
 
-def solve(K, R: np.ndarray) -> np.ndarray:
+def factorize(K, spd: bool = True):
+    """SuperLU factorisation of K.  Under reading G, K is symmetric positive
+    definite (the normal equations of one global least-squares system), so
+    the factorisation takes a symmetric fill-reducing order (minimum degree
+    on K + K^T) and keeps the diagonal pivots (no pivoting is needed for an
+    SPD matrix); this changes the rounding order of the direct solve, not
+    what it computes, and keeps the fill of meshes with 10^6 cells within
+    host memory.  Reading P's matrix is not symmetric and takes SuperLU's
+    default column order with partial pivoting."""
+    if spd:
+        return spla.splu(K.tocsc(), permc_spec="MMD_AT_PLUS_A", diag_pivot_thresh=0.0,
+                         options=dict(SymmetricMode=True))
+    return spla.splu(K.tocsc())
+
+
+def solve(K, R: np.ndarray, spd: bool = True) -> np.ndarray:
     """Direct solve of K X = R for the four columns; returns X [4, 5, nt]
     in the layout of the library (variable, coefficient, cell)."""
     nt = R.shape[1]
@@ -168,15 +183,14 @@ def solve(K, R: np.ndarray) -> np.ndarray:
     if 5 * nt <= 4000:
         Xf = np.linalg.solve(K.toarray(), rhs_mat)
     else:
-        lu = spla.splu(K.tocsc())
-        Xf = lu.solve(rhs_mat)
+        Xf = factorize(K, spd).solve(rhs_mat)
     return np.ascontiguousarray(Xf.T.reshape(4, nt, 5).transpose(0, 2, 1))
 
 
 def reconstruct(geo: Geometry, W: np.ndarray, k=None, reading: str = "G", w: float = CLS_W):
     """Coefficients X [4, 5, nt] of the CLS reconstruction of W [4, nt]."""
     K, pairs = assemble(geo, k, w, reading)
-    return solve(K, rhs(geo, pairs, W))
+    return solve(K, rhs(geo, pairs, W), spd=reading == "G")
 
 
 def residual(K, R: np.ndarray, X: np.ndarray) -> np.ndarray:

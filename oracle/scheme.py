@@ -239,8 +239,7 @@ class Solver:
         nt = self.geo.nt
         b = R.reshape(4, 5 * nt).T
         if self._lu is None:
-            import scipy.sparse.linalg as spla
-            self._lu = spla.splu(self.K.tocsc())
+            self._lu = cls_mod.factorize(self.K, spd=self.prm.reading == "G")
         Xf = self._lu.solve(b)
         return np.ascontiguousarray(Xf.T.reshape(4, nt, 5).transpose(0, 2, 1))
 
