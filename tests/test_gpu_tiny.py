@@ -9,6 +9,7 @@ import pytest
 import gks_inputs as gi
 from oracle import cls, limiter, scheme
 from oracle.mesh import build_geometry
+from parity import state_relinf
 
 torch = pytest.importorskip("torch")
 import paper_1802_00704_amd as g  # noqa: E402
@@ -44,8 +45,9 @@ def test_tiny_step_parity(nx, ny, precision):
     for _ in range(3):
         dt, _ = gm.step(W)
         Wr, _ = s.step(Wr, dt)
-    rel = max(np.abs(W.cpu().numpy()[q] - Wr[q]).max() / np.abs(Wr[q]).max() for q in (0, 1, 3))
-    assert rel <= (1e-11 if precision == g.GKS_FP64 else 1e-9), rel
+    rel = state_relinf(W.cpu().numpy(), Wr, per_component=True)
+    print("relative L-inf per component", rel, flush=True)
+    assert rel.max() <= (1e-12 if precision == g.GKS_FP64 else 1e-9), rel
     gm.close()
 
 
