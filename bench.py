@@ -68,13 +68,25 @@ def workload(name: str):
     raise SystemExit("unknown workload %r" % name)
 
 
-def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
-    """The oracle (plain FP64 NumPy/SciPy, single thread) on a bounded sample:
-    the same workload family on a smaller mesh, timed over whole steps."""
+def host_cpu() -> dict:
+    """Host CPU model and the cores this process may run on."""
+    model = None
     try:
-        from threadpoolctl import threadpool_limits
-    except ImportError:  # pragma: no cover
-        threadpool_limits = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "os_cpu_count": os.cpu_count()}
+
+
+def _oracle_sample(name: str):
     import gks_inputs as gi
     from oracle import scheme
     if name == "shock_vortex_1m":
@@ -100,27 +112,58 @@ def cpu_baseline(name: str, budget_s: float = 15.0) -> dict:
         W = gi.density_advection_ic(m)
         sample = "density advection JSS 64x64 (8,192 triangles)"
         prm = scheme.Params()
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    return m, W, sample, prm
+
+
+def oracle_worker(name: str, budget_s: float):
+    """One single-threaded oracle run on the bounded sample: (cells, steps,
+    seconds, sample text).  Runs in the parent or in a pool worker."""
     try:
-        s = scheme.Solver(m, prm)
-        s.step(W)  # factorisation of the CLS matrix (setup, not timed)
-        steps = 0
-        t0 = time.perf_counter()
-        while True:
-            W, _ = s.step(W)
-            steps += 1
-            el = time.perf_counter() - t0
-            if el >= budget_s or steps >= 50:
-                break
-    finally:
-        if ctx is not None:
-            ctx.unregister() if hasattr(ctx, "unregister") else None
-    return {"value": m.nt * steps / el, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
-            "sample": "%s, %d steps in %.1f s" % (sample, steps, el)}
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    from oracle import scheme
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    m, W, sample, prm = _oracle_sample(name)
+    s = scheme.Solver(m, prm)
+    s.step(W)  # factorisation of the CLS matrix (setup, not timed)
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        W, _ = s.step(W)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or steps >= 200:
+            break
+    del ctx
+    return m.nt, steps, el, sample
+
+
+def cpu_baseline(name: str, budget_s: float = 12.0) -> dict:
+    """The oracle (plain FP64 NumPy/SciPy) on a bounded sample: the same
+    workload family on a smaller mesh, timed over whole steps, on one core
+    and on every usable host core (one single-threaded oracle process per
+    core, each on its own copy of the sample; the aggregate is reported).
+    Runs before the GPU is touched."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    cpu = host_cpu()
+    nt, steps, el, sample = oracle_worker(name, budget_s)
+    one = nt * steps / el
+    workers = max(1, min(16, cpu["nproc"] or 1))
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        res = list(ex.map(oracle_worker, [name] * workers, [budget_s] * workers))
+    allc = sum(r[0] * r[1] / r[2] for r in res)
+    return {"value": one, "unit": "cell-steps/s", "cores": 1, "kind": "oracle",
+            "sample": "%s, %d steps in %.1f s on one core" % (sample, steps, el),
+            "all_cores": {"value": allc, "unit": "cell-steps/s", "cores": workers,
+                          "sample": "%d single-threaded oracle processes, one per core, each on the same sample"
+                                    % workers},
+            "host_cpu": cpu}
 
 
 def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, graphs: int = 1, limiter: int = 0,
-             extra: dict | None = None):
+             extra: dict | None = None, late_at: int = 0):
     import torch
     import paper_1802_00704_amd as g
     t0 = time.perf_counter()
@@ -135,6 +178,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
     lat = []
     iters = []
     limited = []
+    nonphys = []
     t_start = time.perf_counter()
     for _ in range(steps):
         t = time.perf_counter()
@@ -142,8 +186,28 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         lat.append(time.perf_counter() - t)
         iters.append(max(info["iters"]))
         limited.append(info["limited"])
+        nonphys.append(info["nonphys"])
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
+    done = warmup + steps
+    # a second timed window late in the run (steps late_at + 1 .. late_at +
+    # steps), where the flow has developed, after untimed steps up to it
+    late = None
+    if late_at > done:
+        for _ in range(late_at - done):
+            gm.step(W)
+        torch.cuda.synchronize()
+        l_iters, l_np = [], []
+        t_l = time.perf_counter()
+        for _ in range(steps):
+            _, info = gm.step(W)
+            l_iters.append(max(info["iters"]))
+            l_np.append(info["nonphys"])
+        torch.cuda.synchronize()
+        el_l = time.perf_counter() - t_l
+        late = {"steps": "%d-%d" % (late_at + 1, late_at + steps), "value": m.nt * steps / el_l,
+                "ms_per_step": el_l * 1e3 / steps, "krylov_iters_per_step": float(np.mean(l_iters)),
+                "gauss_point_fallbacks_per_step": float(np.mean(l_np))}
     # Kernel durations: the same number of steps again with a HIP event pair
     # around every launch on the library's stream (events add host latency
     # between launches, so these steps are not part of the timed value).
@@ -167,6 +231,8 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         "step_ms_p99": float(np.percentile(lat_ms, 99)),
         "krylov_iters_per_step": float(np.mean(iters)),
         "limited_cells_per_step": float(np.mean(limited)),
+        "gauss_point_fallbacks_per_step": float(np.mean(nonphys)),
+        "late_window": late,
         "setup_s": setup_s,
         "stats": stats,
         "profile": prof,
@@ -205,18 +271,40 @@ def measured_flops(kernel_class: str):
     return table.get(kernel_class)
 
 
-def flux_fp64(prof: dict):
-    """FP64 VALU roofline of the flux kernel: counted FLOPs per launch over
-    the live average launch duration."""
+OPCOUNT_SUMMARY = os.path.join(ROOT, "profiles", "gks_flux_opcount.txt")
+
+
+def algorithmic_flux_flops():
+    """FP64 FLOPs per Gauss point of the method as the oracle writes it out
+    (operation count of its flux, profiles/gks_flux_opcount.txt)."""
+    try:
+        with open(OPCOUNT_SUMMARY) as f:
+            for line in f:
+                if line.startswith("flop_per_gauss_point"):
+                    return float(line.split()[1])
+    except OSError:
+        return None
+    return None
+
+
+def flux_fp64(prof: dict, n_gauss: int):
+    """FP64 VALU roofline of the flux kernel: FP64 FLOPs executed per launch
+    (the counters) over the live average launch duration; beside it the
+    method's FLOPs (the oracle's operation count) at the same duration."""
     d = prof.get("flux") if prof else None
     fl = measured_flops("flux")
     if not d or d["ms"] <= 0 or not fl:
         return None
     us = d["ms"] * 1e3 / max(1, d["launches"])
     achieved = fl / (us * 1e-6) / 1e12
-    return {"bound": "fp64_valu", "kernel": "flux", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
-            "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "avg_launch_us": round(us, 2),
-            "flop_per_launch": fl}
+    out = {"bound": "fp64_valu", "kernel": "flux", "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
+           "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "avg_launch_us": round(us, 2),
+           "flop_per_launch": fl, "executed_flop_per_gauss_point": round(fl / n_gauss, 1)}
+    fg = algorithmic_flux_flops()
+    if fg:
+        out["algorithmic_flop_per_gauss_point"] = fg
+        out["algorithmic_rate_TFLOPs"] = round(fg * n_gauss / (us * 1e-6) / 1e12, 2)
+    return out
 
 
 def roofline(prof: dict, elapsed_s: float):
@@ -298,6 +386,9 @@ def main():
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving stream to run after the throughput legs (0: skip)")
     ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--late-window", type=int, default=480,
+                    help="shock-vortex workload: also time steps late_window+1 .. late_window+steps of the "
+                         "500-step run (0: skip)")
     ap.add_argument("--no-limiter-leg", action="store_true",
                     help="skip the extra runs of the mixed form with the DWBAP limiter on")
     args = ap.parse_args()
@@ -305,14 +396,18 @@ def main():
         print("bench.py measures one MI355X only; multi-GPU runs are not part of this build "
               "(requested --gpus %d)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    # the oracle's CPU baseline runs first, before anything touches the GPU
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload)
     import torch
     import paper_1802_00704_amd as g
     m, W0, desc, extra = workload(args.workload)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    late_at = args.late_window if args.workload == "shock_vortex_1m" else 0
     res = {}
     for f in forms:
         prec = g.GKS_MIXED if f == "mixed" else g.GKS_FP64
-        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile, args.graphs, extra=extra)
+        res[f] = run_form(m, W0, prec, args.steps, args.warmup, not args.no_profile, args.graphs, extra=extra,
+                          late_at=late_at)
         print("# %s: %.4g cell-steps/s, %.3f ms/step, %.1f Krylov iterations/step" %
               (f, res[f]["value"], res[f]["ms_per_step"], res[f]["krylov_iters_per_step"]), file=sys.stderr,
               flush=True)
@@ -348,7 +443,6 @@ def main():
         print("# serving: %.4g cell-steps/s, step p50/p99 %.2f/%.2f ms, solve p50/p99 %.2f/%.2f ms" %
               (serving["throughput_cell_steps_per_s"], serving["step_ms_p50"], serving["step_ms_p99"],
                serving["solve_ms_p50"], serving["solve_ms_p99"]), file=sys.stderr, flush=True)
-    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload)
     out = {
         "metric": METRIC,
         "value": r["value"],
@@ -369,7 +463,7 @@ def main():
                    else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from the last three solutions",
                    "cells": m.nt},
         "roofline": roofline(r["profile"], r["profiled_elapsed_s"]),
-        "flux_fp64": flux_fp64(r["profile"]),
+        "flux_fp64": flux_fp64(r["profile"], 2 * int(r["stats"]["nf"])),
         "cpu_baseline": cpu,
         "forms": {f: dict({k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")},
                           hbm_kernels=kernel_table(res[f]["profile"]))
