@@ -231,6 +231,31 @@ int gks_profile_get(gks_mesh* m, int n, const char** names, int64_t* launches, d
 int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold,
               int32_t variables, int32_t* n_limited);
 
+/* Limited cells that gks_limit_noalloc can hold (its static scratch). */
+#define GKS_LIMIT_NOALLOC_MAX_CELLS 65536
+
+/* gks_limit without any allocation, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc): gks_limit allocates its list of limited cells and
+ * their coefficients on its first call on a handle, while this call keeps
+ * them in a static device array of 10,748,160 bytes (the count, the list and
+ * the coefficients of at most GKS_LIMIT_NOALLOC_MAX_CELLS limited cells)
+ * that every device the library runs on holds from module load until the
+ * process ends.  It calls no hipMalloc, hipFree or other allocating routine
+ * and records no profiling events.  Arguments, layouts and results are those
+ * of gks_limit (identical kernels, bitwise the same Xout).  Every call on one
+ * device shares that device's array: calls that overlap on one device (other
+ * streams, other host threads) race and must be serialised by the caller.
+ * The call synchronises the handle's stream twice (after marking, to read
+ * the count, and at the end).
+ * Errors: GKS_EINVAL for bad arguments, or when more than
+ * GKS_LIMIT_NOALLOC_MAX_CELLS cells reach the threshold (*n_limited then
+ * holds their number and Xout holds X unlimited; gks_limit has no such
+ * limit); GKS_EHIP when the array's device address could not be found at
+ * the handle's creation, or a launch fails. */
+int gks_limit_noalloc(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold,
+                      int32_t variables, int32_t* n_limited);
+
 /* Apply the solve's preconditioner to four columns: Z = P(V), where P is
  * the BILU(0) factorisation of section 3.2 (form GKS_FP64: one forward and
  * one backward block substitution in FP64), or the inner iteration of the
@@ -278,6 +303,7 @@ const char* gks_last_error(const gks_mesh* m);
 
 /* Release every resource of the handle; NULL is a no-op. */
 void gks_destroy(gks_mesh* m);
+
 
 #ifdef __cplusplus
 }

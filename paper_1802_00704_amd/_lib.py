@@ -21,6 +21,7 @@ GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM = 0, 1
 
 EXPORTS = ("gks_params_default", "gks_mesh_create", "gks_cls_reconstruct", "gks_flux", "gks_step",
            "gks_faces", "gks_mesh_get_stats", "gks_profile_enable", "gks_profile_get", "gks_apply_precond", "gks_limit",
+           "gks_limit_noalloc",
            "gks_host_inspect", "gks_host_free", "gks_last_error", "gks_destroy")
 
 
@@ -104,6 +105,8 @@ def lib():
         L.gks_faces.argtypes = [vp, vp, vp]
         L.gks_limit.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_int32)]
         L.gks_limit.restype = C.c_int
+        L.gks_limit_noalloc.argtypes = [vp, vp, vp, vp, C.c_double, C.c_int32, C.POINTER(C.c_int32)]
+        L.gks_limit_noalloc.restype = C.c_int
         L.gks_apply_precond.argtypes = [vp, vp, vp, C.c_int]
         L.gks_apply_precond.restype = C.c_int
         L.gks_faces.restype = C.c_int
@@ -283,6 +286,16 @@ class GksMesh:
                                C.byref(n))
         _check(code, self._h)
         return Xout, int(n.value)
+
+    def limit_noalloc(self, W, X, Xout, threshold: float = 1.0, variables: int = 1):
+        """n_limited: Xout = X limited by gks_limit_noalloc (no allocation;
+        Xout must be given)."""
+        n = C.c_int32(0)
+        code = lib().gks_limit_noalloc(self._h, _dev(W, (4, self.nt), "W"), _dev(X, (4, 5, self.nt), "X"),
+                                       _dev(Xout, (4, 5, self.nt), "Xout"), float(threshold), int(variables),
+                                       C.byref(n))
+        _check(code, self._h)
+        return int(n.value)
 
     def apply_precond(self, V, form: int = 0, Z=None):
         """Z = P(V) with the solver's preconditioner (gks_apply_precond)."""

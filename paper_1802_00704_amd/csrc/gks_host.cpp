@@ -1176,6 +1176,9 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
         w.scal_host = (double*)(hp + o_scal);
     }
     launch_set_scalar(m, &w.ks->tol, prm.tol);
+    // device address of the static limiter scratch (gks_limit_noalloc), looked
+    // up once per device with this handle's device current
+    m->scratch = scratch_device_ptr(&m->scratch_err);
     pt.mark("work space");
 }
 
@@ -1620,6 +1623,43 @@ int gks_limit(gks_mesh* m, const double* W, const double* X, double* Xout, doubl
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
         if (n_limited) *n_limited = m->w.counters_host[2];
+        return GKS_OK;
+    } catch (const Fail& f) {
+        return fail(m, f);
+    } catch (const LaunchError& e) {
+        return fail(m, Fail{GKS_EHIP, std::string("launch of ") + e.kernel + " failed: " + hipGetErrorString(e.err)});
+    }
+}
+
+int gks_limit_noalloc(gks_mesh* m, const double* W, const double* X, double* Xout, double threshold,
+                      int32_t variables, int32_t* n_limited) {
+    if (!m) return GKS_EINVAL;
+    if (!W || !X || !Xout || (const void*)X == (const void*)Xout || !(threshold == threshold)) {
+        m->err = "gks_limit_noalloc needs W, X, Xout (not aliasing X) and a threshold";
+        return GKS_EINVAL;
+    }
+    if (variables != GKS_LIMIT_CONSERVATIVE && variables != GKS_LIMIT_CHARACTERISTIC) {
+        m->err = "gks_limit_noalloc: variables must be GKS_LIMIT_CONSERVATIVE or GKS_LIMIT_CHARACTERISTIC";
+        return GKS_EINVAL;
+    }
+    if (!m->scratch) {
+        m->err = "gks_limit_noalloc: no static scratch on this device (" + m->scratch_err + ")";
+        return GKS_EHIP;
+    }
+    try {
+        launch_limit_noalloc(m, m->scratch, 1, W, X, Xout, threshold, variables);
+        HIPCHK(hipMemcpyAsync(m->w.counters_host + 3, scratch_count(m->scratch), sizeof(int32_t),
+                              hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+        const int32_t cnt = m->w.counters_host[3];
+        if (n_limited) *n_limited = cnt;
+        if (cnt > GKS_LIMIT_NOALLOC_MAX_CELLS) {
+            m->err = "gks_limit_noalloc: " + std::to_string(cnt) + " cells to limit exceed the static scratch (" +
+                     std::to_string(GKS_LIMIT_NOALLOC_MAX_CELLS) + " cells); Xout holds X unlimited";
+            return GKS_EINVAL;
+        }
+        if (cnt > 0) launch_limit_noalloc(m, m->scratch, 2, W, X, Xout, threshold, variables);
+        HIPCHK(hipStreamSynchronize(m->stream));
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);

@@ -189,6 +189,9 @@ struct gks_mesh {
     int64_t graph_steps = 0;      // steps run through the graphs
     int capture_failures = 0;     // captures that failed (3 turn graphs off)
     std::string capture_err;      // the last capture failure
+    void* scratch = nullptr;      // device address of the static limiter scratch on this
+                                  // handle's device (gks_limit_noalloc), or null
+    std::string scratch_err;      // why the scratch lookup failed
     std::string err;
 };
 
@@ -264,6 +267,16 @@ void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt
 void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, double* dst, double threshold,
                   int variables, int32_t* count);
 void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
+// Static scratch of gks_limit_noalloc (a file-scope device array of the
+// kernel library): its address on the current device, looked up once per
+// device (null on failure, err set); the limiter on it in two phases (1:
+// copy X to Xout, clear and mark; 2: limit the listed cells and scatter);
+// the device address of its count of limited cells.
+void* scratch_device_ptr(std::string* err);
+
+void launch_limit_noalloc(gks_mesh* m, void* scr, int phase, const double* W, const double* X, double* Xout,
+                          double threshold, int variables);
+int32_t* scratch_count(void* scr);
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out);
 void launch_set_scalar(gks_mesh* m, double* p, double v);
 void launch_zero(gks_mesh* m, double* p, int64_t count);

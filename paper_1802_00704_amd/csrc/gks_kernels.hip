@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstdlib>
+#include <mutex>
 
 #include "gks_flux_device.h"
 #include "gks_char_basis.h"
@@ -1504,9 +1505,12 @@ struct LimArgs {
     int all_quadratic;
     int charvars;         // 1: limit characteristic variables, 0: conserved ones
     int32_t* count;       // number of limited cells (list length)
-    int32_t* list;        // [nt] limited cells, in no particular order
-    double* lbuf;         // [20][nt] limited coefficients of list entry k at column k
+    int32_t* list;        // [cap] limited cells, in no particular order
+    double* lbuf;         // [20][lstride] limited coefficients of list entry k at column k
     double* dst;          // scatter target [20][nt]
+    int cap;              // entries the list holds (nt, or the static scratch's limit);
+                          // the count goes on past it, entries beyond are not stored
+    int lstride;          // column stride of lbuf (>= the entries processed)
 };
 
 // Face-neighbour stencil of cell i: interior neighbours, their slots and
@@ -1560,7 +1564,10 @@ __global__ void __launch_bounds__(TPB) k_limit_mark(LimArgs a) {
         umax = fmax(umax, a.W[j]);
     }
     const double hk = ki == 2 ? hi * sqrt(hi) : hi;   // h_i^((k+1)/2)
-    if (num / (J * hk * umax) >= a.threshold) a.list[atomicAdd(a.count, 1)] = i;
+    if (num / (J * hk * umax) >= a.threshold) {
+        const int pos = atomicAdd(a.count, 1);
+        if (pos < a.cap) a.list[pos] = i;
+    }
 }
 
 using gksdev::CharBasis;
@@ -1610,7 +1617,7 @@ __device__ __forceinline__ void limit_vec(double cand[4][4], const double w[4], 
 // in their slots (ok[] marks the interior ones; candidate 1 + s belongs to
 // slot s), so every array index is a compile-time constant.
 __global__ void __launch_bounds__(64) k_limit_apply(LimArgs a) {
-    const int cnt = *a.count;
+    const int cnt = min(*a.count, a.cap);
     const int nt = a.nt;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
         const int i = a.list[k];
@@ -1770,18 +1777,18 @@ __global__ void __launch_bounds__(64) k_limit_apply(LimArgs a) {
 #pragma unroll
         for (int v = 0; v < 4; ++v)
 #pragma unroll
-            for (int l = 0; l < 5; ++l) a.lbuf[(int64_t)(v * 5 + l) * nt + k] = Xi[v][l];
+            for (int l = 0; l < 5; ++l) a.lbuf[(int64_t)(v * 5 + l) * a.lstride + k] = Xi[v][l];
     }
 }
 
 // Limited coefficients of the listed cells into their places in dst.
 __global__ void __launch_bounds__(TPB) k_limit_scatter(LimArgs a) {
-    const int cnt = *a.count;
+    const int cnt = min(*a.count, a.cap);
     const int nt = a.nt;
     for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < cnt; k += gridDim.x * blockDim.x) {
         const int i = a.list[k];
 #pragma unroll
-        for (int l = 0; l < 20; ++l) a.dst[(int64_t)l * nt + i] = a.lbuf[(int64_t)l * nt + k];
+        for (int l = 0; l < 20; ++l) a.dst[(int64_t)l * nt + i] = a.lbuf[(int64_t)l * a.lstride + k];
     }
 }
 
@@ -2139,8 +2146,9 @@ void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn) {
                                        m->d.cface, m->d.area, W, F, Wn, m->prm.gamma, m->w.counters + 1));
 }
 
-void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, double* dst, double threshold,
-                  int variables, int32_t* count) {
+static LimArgs limit_args(gks_mesh* m, const double* W, const double* X, double* Xcopy, double* dst,
+                          double threshold, int variables, int32_t* count, int32_t* list, double* lbuf, int cap,
+                          int lstride) {
     LimArgs a;
     a.nt = m->d.nt;
     a.nf = m->d.nf;
@@ -2159,9 +2167,18 @@ void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, 
     a.all_quadratic = m->prm.all_quadratic;
     a.charvars = variables == GKS_LIMIT_CHARACTERISTIC;
     a.count = count;
-    a.list = m->w.lim_list;
-    a.lbuf = m->w.lim_buf;
+    a.list = list;
+    a.lbuf = lbuf;
     a.dst = dst;
+    a.cap = cap;
+    a.lstride = lstride;
+    return a;
+}
+
+void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, double* dst, double threshold,
+                  int variables, int32_t* count) {
+    const LimArgs a = limit_args(m, W, X, Xcopy, dst, threshold, variables, count, m->w.lim_list, m->w.lim_buf,
+                                 m->d.nt, m->d.nt);
     // unique bytes per cell (a neighbour's data is the same array element as
     // that cell's own): density average and its five coefficients, h and the
     // moments, neighbour slots and offsets; plus the copy of X if asked
@@ -2174,6 +2191,80 @@ void launch_limit(gks_mesh* m, const double* W, const double* X, double* Xcopy, 
     PROF(KC_LIMIT_APPLY, hipLaunchKernelGGL(k_limit_scatter, dim3(std::min(256, nblocks(a.nt))), dim3(TPB), 0,
                                             m->stream, a));
 }
+
+__global__ void k_zero_i32(int count, int32_t* p) {
+    if ((int)threadIdx.x < count) p[threadIdx.x] = 0;
+}
+
+// ------------------------------------------------------------------ static limiter scratch
+// Work space of gks_limit_noalloc: the count of limited cells, their list and
+// their limited coefficients, for at most GKS_LIMIT_NOALLOC_MAX_CELLS limited
+// cells, in one array of the code object.  Each device holds its own copy
+// from module load until the process ends; in host code the array's name is
+// only a stand-in, so kernels receive the device address that
+// hipGetSymbolAddress returns for the current device (scratch_device_ptr).
+constexpr size_t SCR_COUNT = 0;                                                   // int32 count
+constexpr size_t SCR_LIST = 256;                                                  // int32 [MAX]
+constexpr size_t SCR_LBUF = SCR_LIST + ((size_t)GKS_LIMIT_NOALLOC_MAX_CELLS * 4 + 255) / 256 * 256;  // double [20][MAX]
+constexpr size_t SCR_BYTES = SCR_LBUF + (size_t)20 * GKS_LIMIT_NOALLOC_MAX_CELLS * sizeof(double);
+static_assert(SCR_BYTES == 10748160, "size of the static limiter scratch");
+
+static __device__ __align__(256) unsigned char scratch[SCR_BYTES];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (hipGetSymbolAddress with that device current) and kept; null when
+// the lookup fails (err receives the reason).
+void* scratch_device_ptr(std::string* err) {
+    static std::mutex mu;
+    static void* ptrs[64] = {nullptr};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= 64) {
+        if (err) *err = std::string("hipGetDevice: ") + hipGetErrorString(e);
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    if (!ptrs[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) {
+            if (err) *err = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        ptrs[dev] = p;
+    }
+    return ptrs[dev];
+}
+
+// The limiter of launch_limit with its list, buffer and count in the static
+// scratch at scr (the device address of `scratch`).  Phase 1 copies X to
+// Xout, clears the count and marks the cells (entries past the scratch's
+// limit are counted but not stored); phase 2, run only when the host has
+// read a count within the limit, limits the listed cells and scatters them
+// into Xout.  No profiling events (nothing is created or allocated).
+void launch_limit_noalloc(gks_mesh* m, void* scr, int phase, const double* W, const double* X, double* Xout,
+                          double threshold, int variables) {
+    char* base = (char*)scr;
+    int32_t* count = (int32_t*)(base + SCR_COUNT);
+    const LimArgs a = limit_args(m, W, X, phase == 1 ? Xout : nullptr, Xout, threshold, variables, count,
+                                 (int32_t*)(base + SCR_LIST), (double*)(base + SCR_LBUF),
+                                 GKS_LIMIT_NOALLOC_MAX_CELLS, GKS_LIMIT_NOALLOC_MAX_CELLS);
+    if (phase == 1) {
+        hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, m->stream, 1, count);
+        check_launch(KC_MISC);
+        hipLaunchKernelGGL(k_limit_mark, dim3(nblocks(a.nt)), dim3(TPB), 0, m->stream, a);
+        check_launch(KC_LIMIT);
+        return;
+    }
+    const int nb = std::max(1, std::min(2048, nblocks(std::min(a.nt, a.cap), 64)));
+    hipLaunchKernelGGL(k_limit_apply, dim3(nb), dim3(64), 0, m->stream, a);
+    check_launch(KC_LIMIT_APPLY);
+    hipLaunchKernelGGL(k_limit_scatter, dim3(std::min(256, nblocks(std::min(a.nt, a.cap)))), dim3(TPB), 0,
+                       m->stream, a);
+    check_launch(KC_LIMIT_APPLY);
+}
+
+int32_t* scratch_count(void* scr) { return (int32_t*)((char*)scr + SCR_COUNT); }
 
 void launch_cfl(gks_mesh* m, const double* W, double* dt_out) {
     const int nt = m->d.nt;
@@ -2193,10 +2284,6 @@ void launch_zero(gks_mesh* m, double* p, int64_t count) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_zero, dim3(nblocks(count)), dim3(TPB), 0, m->stream, count, p);
     check_launch(KC_MISC);
-}
-
-__global__ void k_zero_i32(int count, int32_t* p) {
-    if ((int)threadIdx.x < count) p[threadIdx.x] = 0;
 }
 
 void launch_zero_i32(gks_mesh* m, int32_t* p, int count) {
