@@ -304,6 +304,47 @@ const char* gks_last_error(const gks_mesh* m);
 /* Release every resource of the handle; NULL is a no-op. */
 void gks_destroy(gks_mesh* m);
 
+/* ---------------------------------------------------------------- batched steps
+ * One step of Eq. fvm3 (as gks_step) for several handles at once, for
+ * serving many meshes on one device: every kernel of the step runs once for
+ * all the handles of the batch (grouped launches over the concatenated
+ * meshes, each handle at its own offset in the launch grid with the grid of
+ * its own launch), so small meshes share launches instead of queueing their
+ * own.  Each handle keeps its own state (mesh, factors, Krylov basis,
+ * solution history) and its arithmetic is exactly that of gks_step with
+ * eager launches (graphs = 0): results are bitwise those of stepping the
+ * handle alone.  The GMRES cycles of the handles run in lockstep with one
+ * status read per Arnoldi step for the batch. */
+typedef struct gks_batch gks_batch;
+
+#define GKS_BATCH_MAX 64   /* handles per gks_batch_step call */
+
+/* A batch context whose work is ordered on hip_stream (NULL: a stream of its
+ * own), on the current device.  Errors: GKS_EINVAL, GKS_ENOMEM, GKS_EHIP. */
+int gks_batch_create(void* hip_stream, gks_batch** out);
+
+/* One step of each of the n handles meshes[0..n-1] (distinct, created on the
+ * batch's device, all GKS_FP64 or all GKS_MIXED; mixed handles need the
+ * split-form sweeps, see gks_mesh_stats.split_form; no limiter), with device
+ * states W[r] ([4][nt_r], updated in place on success, as gks_step).
+ * dt: host [n] time steps, entries <= 0 (or dt = NULL) take the CFL rule.
+ * dt_used (host [n], may be NULL) receives the steps taken; info (host [n],
+ * may be NULL) the per-handle solve reports, with solve_ms and call_ms the
+ * batch's; status (host [n]) each handle's outcome: GKS_OK, GKS_ENOCONV or
+ * GKS_ENONPHYS (that W unchanged, as gks_step; the others still step).
+ * Work is ordered on the batch's stream; the handles' own streams must hold
+ * no pending work of the caller's (the call waits for them).  Synchronises
+ * the batch's stream before returning.
+ * Returns GKS_OK when every handle's step was attempted; GKS_EINVAL for bad
+ * arguments (nothing runs); GKS_EHIP for a failed launch or runtime call. */
+int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* const* W, const double* dt,
+                   double* dt_used, gks_solve_info* info, int32_t* status);
+
+/* Message of the batch's last failure. */
+const char* gks_batch_last_error(const gks_batch* b);
+
+/* Release the batch (not its handles); NULL is a no-op. */
+void gks_batch_destroy(gks_batch* b);
 
 #ifdef __cplusplus
 }

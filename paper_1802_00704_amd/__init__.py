@@ -5,9 +5,9 @@ this package is its thin Python binding.  Importing it does not load the
 library; the first call does, and raises if it has not been built.
 """
 from ._lib import (GKS_FP64, GKS_MIXED, GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM, LIMIT_CHARACTERISTIC,
-                   LIMIT_CONSERVATIVE, GksError, GksMesh, NonConvergence, NonPhysical, default_params,
+                   LIMIT_CONSERVATIVE, GksBatch, GksError, GksMesh, NonConvergence, NonPhysical, default_params,
                    host_inspect, lib)
 
-__all__ = ["GksMesh", "GksError", "NonConvergence", "NonPhysical", "default_params", "host_inspect", "lib",
+__all__ = ["GksMesh", "GksBatch", "GksError", "NonConvergence", "NonPhysical", "default_params", "host_inspect", "lib",
            "GKS_FP64", "GKS_MIXED", "GKS_ORDER_MULTICOLOR", "GKS_ORDER_RCM", "LIMIT_CONSERVATIVE",
            "LIMIT_CHARACTERISTIC"]

@@ -21,7 +21,8 @@ GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM = 0, 1
 
 EXPORTS = ("gks_params_default", "gks_mesh_create", "gks_cls_reconstruct", "gks_flux", "gks_step",
            "gks_faces", "gks_mesh_get_stats", "gks_profile_enable", "gks_profile_get", "gks_apply_precond", "gks_limit",
-           "gks_limit_noalloc",
+           "gks_limit_noalloc", "gks_batch_create", "gks_batch_step", "gks_batch_last_error",
+           "gks_batch_destroy",
            "gks_host_inspect", "gks_host_free", "gks_last_error", "gks_destroy")
 
 
@@ -125,6 +126,15 @@ def lib():
         L.gks_last_error.restype = C.c_char_p
         L.gks_destroy.argtypes = [vp]
         L.gks_destroy.restype = None
+        L.gks_batch_create.argtypes = [vp, C.POINTER(vp)]
+        L.gks_batch_create.restype = C.c_int
+        L.gks_batch_step.argtypes = [vp, C.c_int32, C.POINTER(vp), C.POINTER(vp), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_double), C.POINTER(SolveInfo), C.POINTER(C.c_int32)]
+        L.gks_batch_step.restype = C.c_int
+        L.gks_batch_last_error.argtypes = [vp]
+        L.gks_batch_last_error.restype = C.c_char_p
+        L.gks_batch_destroy.argtypes = [vp]
+        L.gks_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -321,3 +331,55 @@ class GksMesh:
             _check(k, self._h)
         return {names[i].decode(): {"launches": int(launches[i]), "ms": float(ms[i]), "bytes": float(by[i])}
                 for i in range(k) if names[i]}
+
+
+class GksBatch:
+    """A batch context (gks_batch): one step of several mesh handles at once
+    in shared grouped launches, each handle's result bitwise that of its own
+    eager step."""
+
+    MAX = 64
+
+    def __init__(self, stream=None):
+        self._b = None
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        sp = C.c_void_p(int(getattr(stream, "cuda_stream", stream) or 0))
+        b = C.c_void_p()
+        code = lib().gks_batch_create(sp, C.byref(b))
+        if code != GKS_OK:
+            raise GksError(code, "gks_batch_create failed")
+        self._b = b
+
+    def close(self):
+        if self._b is not None:
+            lib().gks_batch_destroy(self._b)
+            self._b = None
+
+    __del__ = close
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, meshes, states, dt=None):
+        """One step of each (GksMesh, W) pair.  Returns a list of
+        (status code, dt used, info dict); a handle whose step failed keeps
+        its W, as gks_step (status GKS_ENOCONV or GKS_ENONPHYS)."""
+        n = len(meshes)
+        if n != len(states) or not 1 <= n <= self.MAX:
+            raise ValueError("1 to %d (mesh, W) pairs" % self.MAX)
+        hs = (C.c_void_p * n)(*[m._h for m in meshes])
+        ws = (C.c_void_p * n)(*[_dev(W, (4, m.nt), "W") for m, W in zip(meshes, states)])
+        dts = (C.c_double * n)(*([0.0] * n if dt is None else [float(x) for x in dt]))
+        used = (C.c_double * n)()
+        infos = (SolveInfo * n)()
+        st = (C.c_int32 * n)()
+        code = lib().gks_batch_step(self._b, n, hs, ws, dts, used, infos, st)
+        if code != GKS_OK:
+            raise GksError(code, lib().gks_batch_last_error(self._b).decode(errors="replace"))
+        return [(int(st[r]), float(used[r]), infos[r].as_dict()) for r in range(n)]

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libgks.so")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=fast",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-Wno-unused-command-line-argument"]
-SOURCES = ["gks_kernels.hip", "gks_host.cpp"]
+SOURCES = ["gks_kernels.hip", "gks_host.cpp", "gks_batch.cpp"]
 
 
 def hipcc() -> str:

@@ -35,6 +35,7 @@ constexpr int KW = 4;             // ELL width of K (diagonal + 3 neighbours)
 constexpr int LW = 3;             // ELL width of the strict lower / upper factors
 constexpr int MAXM = 64;          // largest GMRES restart length
 constexpr int NPROF = 24;         // profiled kernel classes
+constexpr int MAXB = 16;          // handles per grouped launch
 
 struct Profile {
     bool on = false;
@@ -274,6 +275,30 @@ void launch_update(gks_mesh* m, const double* W, const double* F, double* Wn);
 // the device address of its count of limited cells.
 void* scratch_device_ptr(std::string* err);
 
+// ---------------------------------------------------------------- grouped launches (gks_batch_step)
+// Each call launches its kernels once for all the handles given (at most
+// MAXB = 16 per launch, more are split), each handle with the arguments and
+// grid of its own launch, on stream st; see the single-handle launchers of
+// the same names for what each computes.
+struct BatchSlot {                // one handle's state as read back by the host
+    Status st;
+    int32_t counters[4];
+    double dt;
+};
+void glaunch_gather(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<BatchSlot*>& out,
+                    bool counters);
+// counters = 0 and, where dt[r] > 0, the step's dt set to it
+void glaunch_zero_counters(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<double>& dt);
+void glaunch_cfl(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W);
+void glaunch_extrap(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& order);
+void glaunch_rhs(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W);
+void glaunch_ctl(hipStream_t st, const std::vector<gks_mesh*>& ms, int mode);
+void glaunch_mask_cols(hipStream_t st, const std::vector<gks_mesh*>& ms);
+void glaunch_cycle_start(hipStream_t st, const std::vector<gks_mesh*>& ms);
+void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k);
+void glaunch_end_cycle(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& nvec);
+void glaunch_flux_update(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W);
+void glaunch_commit(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<double*>& W);
 void launch_limit_noalloc(gks_mesh* m, void* scr, int phase, const double* W, const double* X, double* Xout,
                           double threshold, int variables);
 int32_t* scratch_count(void* scr);

@@ -37,13 +37,57 @@ constexpr int AXPY_BLOCKS = 2040;
 // renumber workgroups such that every XCD works on one contiguous range of
 // rows and its neighbours stay in that XCD's L2.
 constexpr int NXCD = 8;
-__device__ __forceinline__ int xcd_block() {
-    const int G = gridDim.x, b = blockIdx.x;
-    const int q = G / NXCD, r = G % NXCD;
+
+// ------------------------------------------------------------------ launch grids
+// Kernel bodies take their block index and grid size from a grid policy.
+// Grid1 reads the hardware's (one mesh per launch).  GridV holds a block's
+// virtual index and grid inside a grouped launch, which runs the same kernel
+// for several meshes at once (Group below): each mesh's blocks see the grid
+// its own launch would have, so they do exactly the same arithmetic, and
+// block partials of reductions land where its own launch puts them.
+struct Grid1 {
+    __device__ __forceinline__ int b() const { return (int)blockIdx.x; }
+    __device__ __forceinline__ int g() const { return (int)gridDim.x; }
+};
+struct GridV {
+    int vb, vn;
+    __device__ __forceinline__ int b() const { return vb; }
+    __device__ __forceinline__ int g() const { return vn; }
+};
+
+// Arguments of a grouped launch, passed by value: per mesh r, its kernel
+// arguments a[r], its first block start[r] (a multiple of NXCD, so that a
+// block's XCD is the one its own launch would give it) and its grid nblk[r].
+// Blocks between a mesh's grid and the next mesh's start do nothing.
+template <class A>
+struct Group {
+    int n;
+    int start[MAXB + 1];
+    int nblk[MAXB];
+    A a[MAXB];
+};
+
+// Mesh of this block in a grouped launch (or -1 for a padding block) and its
+// virtual grid.  Uniform over the block: scalar loads of the kernel arguments.
+template <class A>
+__device__ __forceinline__ int group_locate(const Group<A>& g, GridV& vg) {
+    const int b = (int)blockIdx.x;
+    int r = 0;
+    while (r + 1 < g.n && g.start[r + 1] <= b) ++r;
+    vg.vb = b - g.start[r];
+    vg.vn = g.nblk[r];
+    return vg.vb < vg.vn ? r : -1;
+}
+
+template <class G = Grid1>
+__device__ __forceinline__ int xcd_block(G grid = G()) {
+    const int Gn = grid.g(), b = grid.b();
+    const int q = Gn / NXCD, r = Gn % NXCD;
     const int x = b % NXCD, k = b / NXCD;
     return x * q + min(x, r) + k;
 }
-__device__ __forceinline__ int xcd_row() { return xcd_block() * blockDim.x + threadIdx.x; }
+template <class G = Grid1>
+__device__ __forceinline__ int xcd_row(G grid = G()) { return xcd_block(grid) * blockDim.x + threadIdx.x; }
 
 // Row of a thread in the SpMV kernels.  With a wave order, the launch's
 // waves take the 64-row groups in that order: in multicolour order it
@@ -51,8 +95,9 @@ __device__ __forceinline__ int xcd_row() { return xcd_block() * blockDim.x + thr
 // on at a time cover one part of the mesh in every colour and the neighbour
 // rows they gather (all in other colours) meet again in that XCD's L2.
 // Waves past the table get rows past n (no work).
-__device__ __forceinline__ int spmv_row(const int32_t* __restrict__ worder, int n) {
-    const int r = xcd_row();
+template <class G = Grid1>
+__device__ __forceinline__ int spmv_row(const int32_t* __restrict__ worder, int n, G grid = G()) {
+    const int r = xcd_row(grid);
     if (!worder) return r;
     const int nw = (n + 63) >> 6;
     const int g = r >> 6;   // wave-uniform
@@ -94,7 +139,8 @@ __device__ __forceinline__ void load_block(const T* __restrict__ val, int64_t np
 // the block in a fixed order (wave butterfly, then the block's waves) to
 // partial[c * gridDim.x + blockIdx.x].  Every thread of the block must call
 // it (no early return before it); blockDim.x == TPB.
-__device__ __forceinline__ void block_sumsq4(const double (&s)[NC], double* __restrict__ partial) {
+template <class G = Grid1>
+__device__ __forceinline__ void block_sumsq4(const double (&s)[NC], double* __restrict__ partial, G grid = G()) {
     __shared__ double sh[NC][TPB / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -109,7 +155,7 @@ __device__ __forceinline__ void block_sumsq4(const double (&s)[NC], double* __re
         double t = 0.0;
 #pragma unroll
         for (int q = 0; q < TPB / 64; ++q) t += sh[threadIdx.x][q];
-        partial[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = t;
+        partial[(int64_t)threadIdx.x * grid.g() + grid.b()] = t;
     }
 }
 
@@ -118,11 +164,9 @@ __device__ __forceinline__ void block_sumsq4(const double (&s)[NC], double* __re
 // One thread per cell in the caller's order (W reads stay local); the
 // 160-byte block goes to the cell's solver row.
 // With partial != NULL the block also writes the per-column sums of R^2.
-__global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__ iperm,
-                                             const int32_t* __restrict__ nbc, const double* __restrict__ a0c,
-                                             const double* __restrict__ W, double* __restrict__ R,
-                                             double* __restrict__ partial) {
-    const int oi = xcd_row();
+template <class GRID>
+__device__ __forceinline__ void rhs_body(GRID grid, int nt, const int32_t* __restrict__ iperm, const int32_t* __restrict__ nbc, const double* __restrict__ a0c, const double* __restrict__ W, double* __restrict__ R, double* __restrict__ partial) {
+    const int oi = xcd_row(grid);
     double sq[NC] = {0.0, 0.0, 0.0, 0.0};
     if (oi < nt) {
         double wi[NC];
@@ -155,8 +199,34 @@ __global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__
                 sq[c] += acc[c][l] * acc[c][l];
             }
     }
-    if (partial) block_sumsq4(sq, partial);
+    if (partial) block_sumsq4(sq, partial, grid);
 }
+
+__global__ void __launch_bounds__(TPB) k_rhs(int nt, const int32_t* __restrict__ iperm,
+                                             const int32_t* __restrict__ nbc, const double* __restrict__ a0c,
+                                             const double* __restrict__ W, double* __restrict__ R,
+                                             double* __restrict__ partial) {
+    rhs_body(Grid1(), nt, iperm, nbc, a0c, W, R, partial);
+}
+
+struct RhsArgs {
+    int nt;
+    const int32_t* iperm;
+    const int32_t* nbc;
+    const double* a0c;
+    const double* W;
+    double* R;
+    double* partial;
+};
+
+__global__ void __launch_bounds__(TPB) kg_rhs(Group<RhsArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const RhsArgs& a = g.a[r];
+    rhs_body(v, a.nt, a.iperm, a.nbc, a.a0c, a.W, a.R, a.partial);
+}
+
 
 // Row-major [.][CB] vectors of a wave's rows [i0, i0 + nr) pass through the
 // wave's LDS area: lanes copy 16-byte chunks lane-contiguously to or from
@@ -205,15 +275,11 @@ __device__ __forceinline__ void rows_store(T* __restrict__ a, int64_t i0, int nr
 // MT: matrix element type; XT: element type of the input vector x.
 // In RESID mode with partial != NULL the block also writes the per-column
 // sums of y^2 (no early return then: every thread reaches the reduction).
-template <typename T, typename XT, bool RESID>
-__global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col,
-                                              const int32_t* __restrict__ worder,
-                                              const XT* __restrict__ x, const double* __restrict__ xscale,
-                                              const double* __restrict__ b, double* __restrict__ y,
-    const int32_t* __restrict__ gate, double* __restrict__ partial = nullptr) {
+template <class GRID, typename T, typename XT, bool RESID>
+__device__ __forceinline__ void spmv_body(GRID grid, int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col, const int32_t* __restrict__ worder, const XT* __restrict__ x, const double* __restrict__ xscale, const double* __restrict__ b, double* __restrict__ y, const int32_t* __restrict__ gate, double* __restrict__ partial) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
-    const int i = spmv_row(worder, n);
+    const int i = spmv_row(worder, n, grid);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)i - lane;                  // first row of the wave
     const int nr = (int)max((int64_t)0, min((int64_t)64, (int64_t)n - i0));
@@ -265,13 +331,49 @@ __global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict
         }
     }
     if (nr > 0) rows_store(y, i0, nr, st, lane, out);
-    if (RESID && partial) block_sumsq4(sq, partial);
+    if (RESID && partial) block_sumsq4(sq, partial, grid);
 }
+
+template <typename T, typename XT, bool RESID>
+__global__ void __launch_bounds__(TPB) k_spmv(int n, int np, const T* __restrict__ val, const int32_t* __restrict__ col,
+                                              const int32_t* __restrict__ worder,
+                                              const XT* __restrict__ x, const double* __restrict__ xscale,
+                                              const double* __restrict__ b, double* __restrict__ y,
+    const int32_t* __restrict__ gate, double* __restrict__ partial = nullptr) {
+    spmv_body<Grid1, T, XT, RESID>(Grid1(), n, np, val, col, worder, x, xscale, b, y, gate, partial);
+}
+
+template <typename T, typename XT>
+struct SpmvArgs {
+    int n;
+    int np;
+    const T* val;
+    const int32_t* col;
+    const int32_t* worder;
+    const XT* x;
+    const double* xscale;
+    const double* b;
+    double* y;
+    const int32_t* gate;
+    double* partial;
+};
+
+template <typename T, typename XT, bool RESID>
+__global__ void __launch_bounds__(TPB) kg_spmv(Group<SpmvArgs<T, XT>> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const SpmvArgs<T, XT>& a = g.a[r];
+    spmv_body<GridV, T, XT, RESID>(v, a.n, a.np, a.val, a.col, a.worder, a.x, a.xscale, a.b, a.y, a.gate, a.partial);
+}
+
 
 // Per-column dot products d[j][c] (j < nj <= RED_CHUNK) of a thread, reduced
 // over the block in a fixed order to partial[(j * NC + c) * gridDim.x +
 // blockIdx.x].  Every thread of the block must call it.
-__device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int nj, double* __restrict__ partial) {
+template <class G = Grid1>
+__device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int nj, double* __restrict__ partial,
+                                           G grid = G()) {
     __shared__ double sh[RED_CHUNK * NC][TPB / 64];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
@@ -289,7 +391,7 @@ __device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int
 #pragma unroll
         for (int q = 0; q < TPB / 64; ++q) t += sh[threadIdx.x][q];
         const int j = threadIdx.x / NC, c = threadIdx.x % NC;
-        partial[((int64_t)j * NC + c) * gridDim.x + blockIdx.x] = t;
+        partial[((int64_t)j * NC + c) * grid.g() + grid.b()] = t;
     }
 }
 
@@ -297,16 +399,11 @@ __device__ __forceinline__ void block_dots(const double (&d)[RED_CHUNK][NC], int
 // V_j . y for j < nvd <= RED_CHUNK (block partials to dpart).  y leaves
 // through the wave's LDS area, and the products run over the wave's
 // contiguous rows in 16-byte pairs, so every V_j read is lane-contiguous.
-template <typename XT>
-__global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* __restrict__ val,
-                                                   const int32_t* __restrict__ col, const int32_t* __restrict__ worder,
-                                                   const XT* __restrict__ x,
-                                                   double* __restrict__ y, const double* __restrict__ V,
-                                                   int64_t vstride, int nvd, double* __restrict__ dpart,
-                                                   const int32_t* __restrict__ gate) {
+template <class GRID, typename XT>
+__device__ __forceinline__ void spmv_dots_body(GRID grid, int n, int np, const double* __restrict__ val, const int32_t* __restrict__ col, const int32_t* __restrict__ worder, const XT* __restrict__ x, double* __restrict__ y, const double* __restrict__ V, int64_t vstride, int nvd, double* __restrict__ dpart, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
-    const int i = spmv_row(worder, n);
+    const int i = spmv_row(worder, n, grid);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)i - lane;
     const int nr = (int)max((int64_t)0, min((int64_t)64, (int64_t)n - i0));
@@ -359,8 +456,44 @@ __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* 
             }
         }
     }
-    block_dots(d, nvd, dpart);
+    block_dots(d, nvd, dpart, grid);
 }
+
+template <typename XT>
+__global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* __restrict__ val,
+                                                   const int32_t* __restrict__ col, const int32_t* __restrict__ worder,
+                                                   const XT* __restrict__ x,
+                                                   double* __restrict__ y, const double* __restrict__ V,
+                                                   int64_t vstride, int nvd, double* __restrict__ dpart,
+                                                   const int32_t* __restrict__ gate) {
+    spmv_dots_body<Grid1, XT>(Grid1(), n, np, val, col, worder, x, y, V, vstride, nvd, dpart, gate);
+}
+
+template <typename XT>
+struct SpmvDotsArgs {
+    int n;
+    int np;
+    const double* val;
+    const int32_t* col;
+    const int32_t* worder;
+    const XT* x;
+    double* y;
+    const double* V;
+    int64_t vstride;
+    int nvd;
+    double* dpart;
+    const int32_t* gate;
+};
+
+template <typename XT>
+__global__ void __launch_bounds__(TPB) kg_spmv_dots(Group<SpmvDotsArgs<XT>> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const SpmvDotsArgs<XT>& a = g.a[r];
+    spmv_dots_body<GridV, XT>(v, a.n, a.np, a.val, a.col, a.worder, a.x, a.y, a.V, a.vstride, a.nvd, a.dpart, a.gate);
+}
+
 
 // out = w - sum_j h_j[c] scale_j[c] V_j and, in the same pass, the second
 // Gram-Schmidt products V_j . out for j < nvec <= RED_CHUNK (block partials
@@ -368,13 +501,11 @@ __global__ void __launch_bounds__(TPB) k_spmv_dots(int n, int np, const double* 
 // the launch makes the grid a multiple of 10 threads, so each thread keeps
 // one pair position, hence fixed columns c0, c1 and fixed coefficients.
 // out may alias w.
-__global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
-                                                   const double* __restrict__ h, const double* __restrict__ scale,
-                                                   const double* w, double* out, double* __restrict__ dpart,
-                                                   const int32_t* __restrict__ gate) {
+template <class GRID>
+__device__ __forceinline__ void axpy_dots_body(GRID grid, int n, const double* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ h, const double* __restrict__ scale, const double* w, double* out, double* __restrict__ dpart, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     const int64_t npair = (int64_t)n * 10;
-    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t0 = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     const int p = (int)(t0 % 10);
     const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
     double hs0[RED_CHUNK], hs1[RED_CHUNK], d0[RED_CHUNK], d1[RED_CHUNK];
@@ -385,7 +516,7 @@ __global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restri
         d0[j] = 0.0;
         d1[j] = 0.0;
     }
-    for (int64_t t = t0; t < npair; t += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = t0; t < npair; t += (int64_t)grid.g() * blockDim.x) {
         const int64_t off = (t / 10) * CB + 2 * p;
         const double2 w2 = *reinterpret_cast<const double2*>(w + off);
         double a0 = w2.x, a1 = w2.y;
@@ -412,8 +543,37 @@ __global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restri
     for (int j = 0; j < RED_CHUNK; ++j)
 #pragma unroll
         for (int c = 0; c < NC; ++c) d[j][c] = (c == c0 ? d0[j] : 0.0) + (c == c1 ? d1[j] : 0.0);
-    block_dots(d, nvec, dpart);
+    block_dots(d, nvec, dpart, grid);
 }
+
+__global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                                   const double* __restrict__ h, const double* __restrict__ scale,
+                                                   const double* w, double* out, double* __restrict__ dpart,
+                                                   const int32_t* __restrict__ gate) {
+    axpy_dots_body(Grid1(), n, V, vstride, nvec, h, scale, w, out, dpart, gate);
+}
+
+struct AxpyDotsArgs {
+    int n;
+    const double* V;
+    int64_t vstride;
+    int nvec;
+    const double* h;
+    const double* scale;
+    const double* w;
+    double* out;
+    double* dpart;
+    const int32_t* gate;
+};
+
+__global__ void __launch_bounds__(TPB) kg_axpy_dots(Group<AxpyDotsArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const AxpyDotsArgs& a = g.a[r];
+    axpy_dots_body(v, a.n, a.V, a.vstride, a.nvec, a.h, a.scale, a.w, a.out, a.dpart, a.gate);
+}
+
 
 // ------------------------------------------------------------------ BILU(0) sweeps
 // Factor storage ("sliced"): the rows of one dependency level are cut into
@@ -525,15 +685,11 @@ __device__ __forceinline__ void slice_sub_lo(ACC (&acc)[CB], const T* __restrict
 // pass skips them and reads s .* v where it gathers them, and their backward
 // pass reads v with the scale.  Rows of the last level have no upper
 // neighbours: its forward pass (LAST) writes z_i = Dinv_i y_i directly.
-template <bool LAST>
-__global__ void __launch_bounds__(TPB) k_ilu_fwd(int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li,
-                                                 const double* __restrict__ Lv, const double* __restrict__ Dinv,
-                                                 const double* __restrict__ v, const double* __restrict__ vscale,
-                                                 double* __restrict__ y, double* __restrict__ z,
-                                                 const int32_t* __restrict__ gate) {
+template <class GRID, bool LAST>
+__device__ __forceinline__ void ilu_fwd_body(GRID grid, int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li, const double* __restrict__ Lv, const double* __restrict__ Dinv, const double* __restrict__ v, const double* __restrict__ vscale, double* __restrict__ y, double* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];   // a wave's 64 FP64 rows
-    const int rl = xcd_row();
+    const int rl = xcd_row(grid);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)r0 + rl - lane;            // first row of the wave
     if (i0 >= r1) return;                                   // the whole wave is past the level
@@ -571,13 +727,46 @@ __global__ void __launch_bounds__(TPB) k_ilu_fwd(int np, int r0, int r1, int sba
     }
 }
 
-__global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
-                                                 const double* __restrict__ Uv, const double* __restrict__ Dinv,
-                                                 const double* __restrict__ y, const double* __restrict__ yscale,
-                                                 double* __restrict__ z, const int32_t* __restrict__ gate) {
+template <bool LAST>
+__global__ void __launch_bounds__(TPB) k_ilu_fwd(int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li,
+                                                 const double* __restrict__ Lv, const double* __restrict__ Dinv,
+                                                 const double* __restrict__ v, const double* __restrict__ vscale,
+                                                 double* __restrict__ y, double* __restrict__ z,
+                                                 const int32_t* __restrict__ gate) {
+    ilu_fwd_body<Grid1, LAST>(Grid1(), np, r0, r1, sbase, zrows, Li, Lv, Dinv, v, vscale, y, z, gate);
+}
+
+struct IluFwdArgs {
+    int np;
+    int r0;
+    int r1;
+    int sbase;
+    int zrows;
+    SlicedIdx Li;
+    const double* Lv;
+    const double* Dinv;
+    const double* v;
+    const double* vscale;
+    double* y;
+    double* z;
+    const int32_t* gate;
+};
+
+template <bool LAST>
+__global__ void __launch_bounds__(TPB) kg_ilu_fwd(Group<IluFwdArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const IluFwdArgs& a = g.a[r];
+    ilu_fwd_body<GridV, LAST>(v, a.np, a.r0, a.r1, a.sbase, a.zrows, a.Li, a.Lv, a.Dinv, a.v, a.vscale, a.y, a.z, a.gate);
+}
+
+
+template <class GRID>
+__device__ __forceinline__ void ilu_bwd_body(GRID grid, int np, int r0, int r1, int sbase, SlicedIdx Ui, const double* __restrict__ Uv, const double* __restrict__ Dinv, const double* __restrict__ y, const double* __restrict__ yscale, double* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * 2 * CB / 4];
-    const int rl = xcd_row();
+    const int rl = xcd_row(grid);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)r0 + rl - lane;
     if (i0 >= r1) return;
@@ -613,6 +802,36 @@ __global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sba
     }
     rows_store(z, i0, nr, st, lane, zi);
 }
+
+__global__ void __launch_bounds__(TPB) k_ilu_bwd(int np, int r0, int r1, int sbase, SlicedIdx Ui,
+                                                 const double* __restrict__ Uv, const double* __restrict__ Dinv,
+                                                 const double* __restrict__ y, const double* __restrict__ yscale,
+                                                 double* __restrict__ z, const int32_t* __restrict__ gate) {
+    ilu_bwd_body(Grid1(), np, r0, r1, sbase, Ui, Uv, Dinv, y, yscale, z, gate);
+}
+
+struct IluBwdArgs {
+    int np;
+    int r0;
+    int r1;
+    int sbase;
+    SlicedIdx Ui;
+    const double* Uv;
+    const double* Dinv;
+    const double* y;
+    const double* yscale;
+    double* z;
+    const int32_t* gate;
+};
+
+__global__ void __launch_bounds__(TPB) kg_ilu_bwd(Group<IluBwdArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const IluBwdArgs& a = g.a[r];
+    ilu_bwd_body(v, a.np, a.r0, a.r1, a.sbase, a.Ui, a.Uv, a.Dinv, a.y, a.yscale, a.z, a.gate);
+}
+
 
 // ------------------------------------------------------------------ mixed-precision inner sweeps
 // One BILU(0)-preconditioned Richardson sweep z <- z + M^-1 (b - K z) with
@@ -754,17 +973,12 @@ __device__ __forceinline__ void block_add(ACC (&acc)[CB], const float (&blk)[25]
             for (int q = 0; q < NB; ++q) acc[c * NB + r] += (ACC)blk[r * NB + q] * (ACC)x[c * NB + q];
 }
 
-template <bool FIRST, bool LAST, typename ACC>
-__global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li,
-                                                const float* __restrict__ KLv, const float* __restrict__ G,
-                                                const float* __restrict__ Dinv, const double* __restrict__ v,
-                                                const double* __restrict__ vscale, float* __restrict__ b,
-                                                float* __restrict__ t, float* __restrict__ w,
-                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
+template <class GRID, bool FIRST, bool LAST, typename ACC>
+__device__ __forceinline__ void es_fwd_body(GRID grid, int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li, const float* __restrict__ KLv, const float* __restrict__ G, const float* __restrict__ Dinv, const double* __restrict__ v, const double* __restrict__ vscale, float* __restrict__ b, float* __restrict__ t, float* __restrict__ w, float* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     constexpr int SK = FIRST ? 2 * CB / 4 : CB / 4;   // 16-byte chunks per staged row (FP64 v first)
     __shared__ float4 stage[TPB / 64][64 * SK];
-    const int rl = xcd_row();
+    const int rl = xcd_row(grid);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)r0 + rl - lane;       // first row of the wave
     if (i0 >= r1) return;                              // the whole wave is past the level
@@ -834,13 +1048,50 @@ __global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbas
         rows_store(w, i0, nr, st, lane, wi);
 }
 
-template <typename ACC>
-__global__ void __launch_bounds__(TPB) k_es_bwd(int r0, int r1, int sbase, SlicedIdx Ui,
-                                                const float* __restrict__ KUv, const float* __restrict__ w,
+template <bool FIRST, bool LAST, typename ACC>
+__global__ void __launch_bounds__(TPB) k_es_fwd(int np, int r0, int r1, int sbase, int zrows, SlicedIdx Li,
+                                                const float* __restrict__ KLv, const float* __restrict__ G,
+                                                const float* __restrict__ Dinv, const double* __restrict__ v,
+                                                const double* __restrict__ vscale, float* __restrict__ b,
+                                                float* __restrict__ t, float* __restrict__ w,
                                                 float* __restrict__ z, const int32_t* __restrict__ gate) {
+    es_fwd_body<Grid1, FIRST, LAST, ACC>(Grid1(), np, r0, r1, sbase, zrows, Li, KLv, G, Dinv, v, vscale, b, t, w, z, gate);
+}
+
+struct EsFwdArgs {
+    int np;
+    int r0;
+    int r1;
+    int sbase;
+    int zrows;
+    SlicedIdx Li;
+    const float* KLv;
+    const float* G;
+    const float* Dinv;
+    const double* v;
+    const double* vscale;
+    float* b;
+    float* t;
+    float* w;
+    float* z;
+    const int32_t* gate;
+};
+
+template <bool FIRST, bool LAST, typename ACC>
+__global__ void __launch_bounds__(TPB) kg_es_fwd(Group<EsFwdArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const EsFwdArgs& a = g.a[r];
+    es_fwd_body<GridV, FIRST, LAST, ACC>(v, a.np, a.r0, a.r1, a.sbase, a.zrows, a.Li, a.KLv, a.G, a.Dinv, a.v, a.vscale, a.b, a.t, a.w, a.z, a.gate);
+}
+
+
+template <class GRID, typename ACC>
+__device__ __forceinline__ void es_bwd_body(GRID grid, int r0, int r1, int sbase, SlicedIdx Ui, const float* __restrict__ KUv, const float* __restrict__ w, float* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ float4 stage[TPB / 64][64 * CB / 4];
-    const int rl = xcd_row();
+    const int rl = xcd_row(grid);
     const int lane = threadIdx.x & 63;
     const int64_t i0 = (int64_t)r0 + rl - lane;
     if (i0 >= r1) return;
@@ -860,13 +1111,40 @@ __global__ void __launch_bounds__(TPB) k_es_bwd(int r0, int r1, int sbase, Slice
     rows_store(z, i0, nr, st, lane, zn);
 }
 
+template <typename ACC>
+__global__ void __launch_bounds__(TPB) k_es_bwd(int r0, int r1, int sbase, SlicedIdx Ui,
+                                                const float* __restrict__ KUv, const float* __restrict__ w,
+                                                float* __restrict__ z, const int32_t* __restrict__ gate) {
+    es_bwd_body<Grid1, ACC>(Grid1(), r0, r1, sbase, Ui, KUv, w, z, gate);
+}
+
+struct EsBwdArgs {
+    int r0;
+    int r1;
+    int sbase;
+    SlicedIdx Ui;
+    const float* KUv;
+    const float* w;
+    float* z;
+    const int32_t* gate;
+};
+
+template <typename ACC>
+__global__ void __launch_bounds__(TPB) kg_es_bwd(Group<EsBwdArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const EsBwdArgs& a = g.a[r];
+    es_bwd_body<GridV, ACC>(v, a.r0, a.r1, a.sbase, a.Ui, a.KUv, a.w, a.z, a.gate);
+}
+
+
 // ------------------------------------------------------------------ reductions
 // Per-column dot products p_j = V_j . w for j in a chunk of RED_CHUNK vectors
 // (blockIdx.y selects the chunk).  Each block writes its partial sums to
 // partial[(j * NC + c) * nblk + blockIdx.x].
-__global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
-                                              const double* __restrict__ w, double* __restrict__ partial,
-    const int32_t* __restrict__ gate) {
+template <class GRID>
+__device__ __forceinline__ void dots_body(GRID grid, int n, const double* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ w, double* __restrict__ partial, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ double sh[RED_CHUNK * NC][TPB / 64];
     const int j0 = blockIdx.y * RED_CHUNK;
@@ -876,7 +1154,7 @@ __global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ 
     for (int j = 0; j < RED_CHUNK; ++j)
 #pragma unroll
         for (int c = 0; c < NC; ++c) acc[j][c] = 0.0;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    for (int i = grid.b() * blockDim.x + threadIdx.x; i < n; i += grid.g() * blockDim.x) {
         double wv[CB];
         const double* wi = w + (int64_t)i * CB;
 #pragma unroll
@@ -909,9 +1187,34 @@ __global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ 
 #pragma unroll
         for (int q = 0; q < TPB / 64; ++q) s += sh[threadIdx.x][q];
         const int j = threadIdx.x / NC, c = threadIdx.x % NC;
-        partial[((int64_t)(j0 + j) * NC + c) * gridDim.x + blockIdx.x] = s;
+        partial[((int64_t)(j0 + j) * NC + c) * grid.g() + grid.b()] = s;
     }
 }
+
+__global__ void __launch_bounds__(TPB) k_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                              const double* __restrict__ w, double* __restrict__ partial,
+    const int32_t* __restrict__ gate) {
+    dots_body(Grid1(), n, V, vstride, nvec, w, partial, gate);
+}
+
+struct DotsArgs {
+    int n;
+    const double* V;
+    int64_t vstride;
+    int nvec;
+    const double* w;
+    double* partial;
+    const int32_t* gate;
+};
+
+__global__ void __launch_bounds__(TPB) kg_dots(Group<DotsArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const DotsArgs& a = g.a[r];
+    dots_body(v, a.n, a.V, a.vstride, a.nvec, a.w, a.partial, a.gate);
+}
+
 
 // Vector kernels over the Krylov basis map one 16-byte group of a cell's 20
 // values to a thread (10 threads per cell for FP64, 5 for FP32), so each load
@@ -925,14 +1228,12 @@ struct Grp {
 
 // out = w - sum_j h_j[c] scale_j[c] V_j   (out may alias w).  With partial
 // != NULL the block also writes the per-column sums of out^2.
-__global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ V, int64_t vstride, int nvec,
-                                              const double* __restrict__ h, const double* __restrict__ scale,
-                                              const double* w, double* out,
-    const int32_t* __restrict__ gate, double* __restrict__ partial) {
+template <class GRID>
+__device__ __forceinline__ void axpy_body(GRID grid, int n, const double* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ h, const double* __restrict__ scale, const double* w, double* out, const int32_t* __restrict__ gate, double* __restrict__ partial) {
     if (gate && *gate == 0) return;
     double sq[NC] = {0.0, 0.0, 0.0, 0.0};
     const int64_t npair = (int64_t)n * 10;
-    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < npair; t += (int64_t)gridDim.x * blockDim.x) {
+    for (int64_t t = (int64_t)grid.b() * blockDim.x + threadIdx.x; t < npair; t += (int64_t)grid.g() * blockDim.x) {
         const int64_t i = t / 10;
         const int p = (int)(t - i * 10);
         const int c0 = (2 * p) / NB, c1 = (2 * p + 1) / NB;
@@ -950,21 +1251,47 @@ __global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ 
 #pragma unroll
         for (int c = 0; c < NC; ++c) sq[c] += (c == c0 ? a0 * a0 : 0.0) + (c == c1 ? a1 * a1 : 0.0);
     }
-    if (partial) block_sumsq4(sq, partial);
+    if (partial) block_sumsq4(sq, partial, grid);
 }
+
+__global__ void __launch_bounds__(TPB) k_axpy(int n, const double* __restrict__ V, int64_t vstride, int nvec,
+                                              const double* __restrict__ h, const double* __restrict__ scale,
+                                              const double* w, double* out,
+    const int32_t* __restrict__ gate, double* __restrict__ partial) {
+    axpy_body(Grid1(), n, V, vstride, nvec, h, scale, w, out, gate, partial);
+}
+
+struct AxpyArgs {
+    int n;
+    const double* V;
+    int64_t vstride;
+    int nvec;
+    const double* h;
+    const double* scale;
+    const double* w;
+    double* out;
+    const int32_t* gate;
+    double* partial;
+};
+
+__global__ void __launch_bounds__(TPB) kg_axpy(Group<AxpyArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const AxpyArgs& a = g.a[r];
+    axpy_body(v, a.n, a.V, a.vstride, a.nvec, a.h, a.scale, a.w, a.out, a.gate, a.partial);
+}
+
 
 // out = sum_j y_j[c] scale_j[c] V_j
 // out = sum_j y_j scale_j V_j, or out += that sum (ACCUM: the mixed form's
 // X += Z y in one pass)
-template <typename VT, bool ACCUM = false>
-__global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V, int64_t vstride, int nvec,
-                                                 const double* __restrict__ y, const double* __restrict__ scale,
-                                                 double* __restrict__ out, const int32_t* __restrict__ nvec_dev,
-                                                 const int32_t* __restrict__ gate) {
+template <class GRID, typename VT, bool ACCUM>
+__device__ __forceinline__ void combine_body(GRID grid, int n, const VT* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ y, const double* __restrict__ scale, double* __restrict__ out, const int32_t* __restrict__ nvec_dev, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     if (nvec_dev) nvec = min(nvec, *nvec_dev);
     constexpr int E = Grp<VT>::E, TC = Grp<VT>::T;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t t = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     const int64_t i = t / TC;
     const int p = (int)(t - i * TC);
     if (i >= n) return;
@@ -992,25 +1319,76 @@ __global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V
     }
 }
 
+template <typename VT, bool ACCUM = false>
+__global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V, int64_t vstride, int nvec,
+                                                 const double* __restrict__ y, const double* __restrict__ scale,
+                                                 double* __restrict__ out, const int32_t* __restrict__ nvec_dev,
+                                                 const int32_t* __restrict__ gate) {
+    combine_body<Grid1, VT, ACCUM>(Grid1(), n, V, vstride, nvec, y, scale, out, nvec_dev, gate);
+}
+
+template <typename VT>
+struct CombineArgs {
+    int n;
+    const VT* V;
+    int64_t vstride;
+    int nvec;
+    const double* y;
+    const double* scale;
+    double* out;
+    const int32_t* nvec_dev;
+    const int32_t* gate;
+};
+
+template <typename VT, bool ACCUM = false>
+__global__ void __launch_bounds__(TPB) kg_combine(Group<CombineArgs<VT>> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const CombineArgs<VT>& a = g.a[r];
+    combine_body<GridV, VT, ACCUM>(v, a.n, a.V, a.vstride, a.nvec, a.y, a.scale, a.out, a.nvec_dev, a.gate);
+}
+
+
 // X += z
-__global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X, const double* __restrict__ z,
-                                             const int32_t* __restrict__ gate) {
+template <class GRID>
+__device__ __forceinline__ void acc_body(GRID grid, int64_t len, double* __restrict__ X, const double* __restrict__ z, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t i = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     if (i < len) X[i] += z[i];
 }
+
+__global__ void __launch_bounds__(TPB) k_acc(int64_t len, double* __restrict__ X, const double* __restrict__ z,
+                                             const int32_t* __restrict__ gate) {
+    acc_body(Grid1(), len, X, z, gate);
+}
+
+struct AccArgs {
+    int64_t len;
+    double* X;
+    const double* z;
+    const int32_t* gate;
+};
+
+__global__ void __launch_bounds__(TPB) kg_acc(Group<AccArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const AccArgs& a = g.a[r];
+    acc_body(v, a.len, a.X, a.z, a.gate);
+}
+
 
 // Sum partials of nval values in a fixed order: one wave per value.
 // mode 0: out[v] = sum;  mode 1: out[v] = sum * scale[v]
 // One block per value: each thread sums a strided subset with four
 // independent accumulators (loads in flight), then the block reduces them;
 // the order is fixed, so results are reproducible.
-__global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const double* __restrict__ partial,
-                                                      const double* __restrict__ scale, double* __restrict__ out,
-    const int32_t* __restrict__ gate) {
+template <class GRID>
+__device__ __forceinline__ void sum_partials_body(GRID grid, int nval, int nblk, const double* __restrict__ partial, const double* __restrict__ scale, double* __restrict__ out, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     __shared__ double sh[TPB / 64];
-    const int v = blockIdx.x;
+    const int v = grid.b();
     const double* p = partial + (int64_t)v * nblk;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     int b = threadIdx.x;
@@ -1033,13 +1411,38 @@ __global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const 
     }
 }
 
+__global__ void __launch_bounds__(TPB) k_sum_partials(int nval, int nblk, const double* __restrict__ partial,
+                                                      const double* __restrict__ scale, double* __restrict__ out,
+    const int32_t* __restrict__ gate) {
+    sum_partials_body(Grid1(), nval, nblk, partial, scale, out, gate);
+}
+
+struct SumArgs {
+    int nval;
+    int nblk;
+    const double* partial;
+    const double* scale;
+    double* out;
+    const int32_t* gate;
+};
+
+__global__ void __launch_bounds__(TPB) kg_sum_partials(Group<SumArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const SumArgs& a = g.a[r];
+    sum_partials_body(v, a.nval, a.nblk, a.partial, a.scale, a.out, a.gate);
+}
+
+
 // ------------------------------------------------------------------ GMRES bookkeeping (one wave)
 // mode 0 (BNORM):   ||R_c|| from sq, active = ||R_c|| > 0
 // mode 1 (BETA):    start of a cycle from ||r_c||^2: beta, scale_0, g, k = 0
 // mode 2 (ARNOLDI): column k of H from h1 + h2 and ||w||^2, Givens rotation,
 //                   residual estimate, k += 1
 // mode 3 (SOLVE):   y = R^{-1} g over the first k columns
-__global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restrict__ ks, int mres, int gated) {
+template <class GRID>
+__device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState* __restrict__ ks, int mres, int gated) {
     if (mode == 2 && ks->st.run == 0) return;   // the cycle has ended
     if (gated && ks->st.fin == 0) return;        // end-of-cycle work while the cycle still runs
     const int c = threadIdx.x;
@@ -1124,27 +1527,70 @@ __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restr
     }
 }
 
+__global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restrict__ ks, int mres, int gated) {
+    gmres_ctl_body(Grid1(), mode, ks, mres, gated);
+}
+
+struct CtlArgs {
+    int mode;
+    KrylovState* ks;
+    int mres;
+    int gated;
+};
+
+__global__ void __launch_bounds__(64) kg_gmres_ctl(Group<CtlArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const CtlArgs& a = g.a[r];
+    gmres_ctl_body(v, a.mode, a.ks, a.mres, a.gated);
+}
+
+
 // ------------------------------------------------------------------ layout conversion
 // X in the caller's layout [4][5][nt] from the solver vector: one thread per
 // cell in the caller's order (coalesced writes, one 160-byte read).
-template <typename T>
-__global__ void __launch_bounds__(TPB) k_copyout(int nt, const int32_t* __restrict__ iperm,
-                                                 const T* __restrict__ Xs, double* __restrict__ Xc) {
-    const int oi = xcd_row();
+template <class GRID, typename T>
+__device__ __forceinline__ void copyout_body(GRID grid, int nt, const int32_t* __restrict__ iperm, const T* __restrict__ Xs, double* __restrict__ Xc) {
+    const int oi = xcd_row(grid);
     if (oi >= nt) return;
     const T* xi = Xs + (int64_t)iperm[oi] * CB;
 #pragma unroll
     for (int q = 0; q < CB; ++q) Xc[(int64_t)q * nt + oi] = (double)xi[q];
 }
 
+template <typename T>
+__global__ void __launch_bounds__(TPB) k_copyout(int nt, const int32_t* __restrict__ iperm,
+                                                 const T* __restrict__ Xs, double* __restrict__ Xc) {
+    copyout_body<Grid1, T>(Grid1(), nt, iperm, Xs, Xc);
+}
+
+template <typename T>
+struct CopyoutArgs {
+    int nt;
+    const int32_t* iperm;
+    const T* Xs;
+    double* Xc;
+};
+
+template <typename T>
+__global__ void __launch_bounds__(TPB) kg_copyout(Group<CopyoutArgs<T>> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const CopyoutArgs<T>& a = g.a[r];
+    copyout_body<GridV, T>(v, a.nt, a.iperm, a.Xs, a.Xc);
+}
+
+
 // Initial guess for the next step's solve by polynomial extrapolation in
 // time of the last solutions (uniform steps): order 0 X, order 1 2X - Xp,
 // order 2 3X - 3Xp + Xpp; the history shifts (Xpp <- Xp, Xp <- X).  The
 // history is kept in FP32: it only shapes the starting point, which the
 // solve then corrects to its tolerance.
-__global__ void __launch_bounds__(TPB) k_extrap(int64_t len, int order, double* __restrict__ X,
-                                                float* __restrict__ Xp, float* __restrict__ Xpp) {
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <class GRID>
+__device__ __forceinline__ void extrap_body(GRID grid, int64_t len, int order, double* __restrict__ X, float* __restrict__ Xp, float* __restrict__ Xpp) {
+    const int64_t e = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     if (e >= len) return;
     const double x = X[e];
     const float p = Xp[e];
@@ -1155,6 +1601,28 @@ __global__ void __launch_bounds__(TPB) k_extrap(int64_t len, int order, double* 
     Xpp[e] = p;
     Xp[e] = (float)x;
 }
+
+__global__ void __launch_bounds__(TPB) k_extrap(int64_t len, int order, double* __restrict__ X,
+                                                float* __restrict__ Xp, float* __restrict__ Xpp) {
+    extrap_body(Grid1(), len, order, X, Xp, Xpp);
+}
+
+struct ExtrapArgs {
+    int64_t len;
+    int order;
+    double* X;
+    float* Xp;
+    float* Xpp;
+};
+
+__global__ void __launch_bounds__(TPB) kg_extrap(Group<ExtrapArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const ExtrapArgs& a = g.a[r];
+    extrap_body(v, a.len, a.order, a.X, a.Xp, a.Xpp);
+}
+
 
 // solver vector from the caller's layout [4][5][nt] (inverse of k_copyout)
 __global__ void __launch_bounds__(TPB) k_copyin(int nt, const int32_t* __restrict__ iperm,
@@ -1173,14 +1641,35 @@ __global__ void __launch_bounds__(TPB) k_zero(int64_t len, double* __restrict__ 
     if (i < len) p[i] = 0.0;
 }
 
-__global__ void __launch_bounds__(TPB) k_copy(int64_t len, double* __restrict__ d, const double* __restrict__ s) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <class GRID>
+__device__ __forceinline__ void copy_body(GRID grid, int64_t len, double* __restrict__ d, const double* __restrict__ s) {
+    const int64_t i = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     if (i < len) d[i] = s[i];
 }
 
+__global__ void __launch_bounds__(TPB) k_copy(int64_t len, double* __restrict__ d, const double* __restrict__ s) {
+    copy_body(Grid1(), len, d, s);
+}
+
+struct CopyArgs {
+    int64_t len;
+    double* d;
+    const double* s;
+};
+
+__global__ void __launch_bounds__(TPB) kg_copy(Group<CopyArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const CopyArgs& a = g.a[r];
+    copy_body(v, a.len, a.d, a.s);
+}
+
+
 // zero the inactive columns of X (a zero right-hand side has X = 0)
-__global__ void __launch_bounds__(TPB) k_mask_cols(int n, double* __restrict__ X, const KrylovState* __restrict__ ks) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+template <class GRID>
+__device__ __forceinline__ void mask_cols_body(GRID grid, int n, double* __restrict__ X, const KrylovState* __restrict__ ks) {
+    const int i = grid.b() * blockDim.x + threadIdx.x;
     if (i >= n) return;
 #pragma unroll
     for (int c = 0; c < NC; ++c)
@@ -1188,6 +1677,25 @@ __global__ void __launch_bounds__(TPB) k_mask_cols(int n, double* __restrict__ X
 #pragma unroll
             for (int l = 0; l < NB; ++l) X[(int64_t)i * CB + c * NB + l] = 0.0;
 }
+
+__global__ void __launch_bounds__(TPB) k_mask_cols(int n, double* __restrict__ X, const KrylovState* __restrict__ ks) {
+    mask_cols_body(Grid1(), n, X, ks);
+}
+
+struct MaskArgs {
+    int n;
+    double* X;
+    const KrylovState* ks;
+};
+
+__global__ void __launch_bounds__(TPB) kg_mask_cols(Group<MaskArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const MaskArgs& a = g.a[r];
+    mask_cols_body(v, a.n, a.X, a.ks);
+}
+
 
 // ------------------------------------------------------------------ flux
 struct FluxArgs {
@@ -1329,8 +1837,9 @@ __device__ __forceinline__ void ghost(const FluxArgs& a, int row, int o, const d
 }
 
 // One thread per Gauss point; lanes 2f and 2f+1 hold the two points of face f.
-__global__ void __launch_bounds__(128) k_flux(FluxArgs a) {
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+template <class GRID>
+__device__ __forceinline__ void flux_body(GRID grid, const FluxArgs& a) {
+    const int64_t t = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     const int f = (int)(t >> 1);
     const int g = (int)(t & 1);
     const bool valid = f < a.nf;
@@ -1376,12 +1885,19 @@ __global__ void __launch_bounds__(128) k_flux(FluxArgs a) {
     }
 }
 
+__global__ void __launch_bounds__(128) k_flux(FluxArgs a) { flux_body(Grid1(), a); }
+
+__global__ void __launch_bounds__(128) kg_flux(Group<FluxArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    flux_body(v, g.a[r]);
+}
+
 // ------------------------------------------------------------------ update (Eq. fvm3)
-__global__ void __launch_bounds__(TPB) k_update(int nt, int nf, const int32_t* __restrict__ cface,
-                                                const double* __restrict__ area, const double* __restrict__ W,
-                                                const double* __restrict__ F, double* __restrict__ Wn,
-                                                double gamma, int32_t* __restrict__ nonphys) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+template <class GRID>
+__device__ __forceinline__ void update_body(GRID grid, int nt, int nf, const int32_t* __restrict__ cface, const double* __restrict__ area, const double* __restrict__ W, const double* __restrict__ F, double* __restrict__ Wn, double gamma, int32_t* __restrict__ nonphys) {
+    const int i = grid.b() * blockDim.x + threadIdx.x;
     if (i >= nt) return;
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -1402,14 +1918,40 @@ __global__ void __launch_bounds__(TPB) k_update(int nt, int nf, const int32_t* _
     if (!(w[0] > 0.0 && gksdev::pressure(w, gamma) > 0.0)) atomicAdd(nonphys, 1);
 }
 
+__global__ void __launch_bounds__(TPB) k_update(int nt, int nf, const int32_t* __restrict__ cface,
+                                                const double* __restrict__ area, const double* __restrict__ W,
+                                                const double* __restrict__ F, double* __restrict__ Wn,
+                                                double gamma, int32_t* __restrict__ nonphys) {
+    update_body(Grid1(), nt, nf, cface, area, W, F, Wn, gamma, nonphys);
+}
+
+struct UpdateArgs {
+    int nt;
+    int nf;
+    const int32_t* cface;
+    const double* area;
+    const double* W;
+    const double* F;
+    double* Wn;
+    double gamma;
+    int32_t* nonphys;
+};
+
+__global__ void __launch_bounds__(TPB) kg_update(Group<UpdateArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const UpdateArgs& a = g.a[r];
+    update_body(v, a.nt, a.nf, a.cface, a.area, a.W, a.F, a.Wn, a.gamma, a.nonphys);
+}
+
+
 // ------------------------------------------------------------------ CFL
-__global__ void __launch_bounds__(TPB) k_cfl(int nt, int nf, const int32_t* __restrict__ cface,
-                                             const double* __restrict__ area, const double* __restrict__ fgeo,
-                                             const double* __restrict__ W, double gamma,
-                                             double* __restrict__ partial) {
+template <class GRID>
+__device__ __forceinline__ void cfl_body(GRID grid, int nt, int nf, const int32_t* __restrict__ cface, const double* __restrict__ area, const double* __restrict__ fgeo, const double* __restrict__ W, double gamma, double* __restrict__ partial) {
     __shared__ double sh[TPB / 64];
     double best = INFINITY;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nt; i += gridDim.x * blockDim.x) {
+    for (int i = grid.b() * blockDim.x + threadIdx.x; i < nt; i += grid.g() * blockDim.x) {
         const double rho = W[i], u = W[(int64_t)nt + i] / rho, v = W[2 * (int64_t)nt + i] / rho;
         const double p = (gamma - 1.0) * (W[3 * (int64_t)nt + i] - 0.5 * rho * (u * u + v * v));
         const double c = sqrt(gamma * p / rho);
@@ -1429,11 +1971,61 @@ __global__ void __launch_bounds__(TPB) k_cfl(int nt, int nf, const int32_t* __re
     if (threadIdx.x == 0) {
         double b = sh[0];
         for (int q = 1; q < TPB / 64; ++q) b = fmin(b, sh[q]);
-        partial[blockIdx.x] = b;
+        partial[grid.b()] = b;
     }
 }
 
+__global__ void __launch_bounds__(TPB) k_cfl(int nt, int nf, const int32_t* __restrict__ cface,
+                                             const double* __restrict__ area, const double* __restrict__ fgeo,
+                                             const double* __restrict__ W, double gamma,
+                                             double* __restrict__ partial) {
+    cfl_body(Grid1(), nt, nf, cface, area, fgeo, W, gamma, partial);
+}
+
+struct CflArgs {
+    int nt;
+    int nf;
+    const int32_t* cface;
+    const double* area;
+    const double* fgeo;
+    const double* W;
+    double gamma;
+    double* partial;
+};
+
+__global__ void __launch_bounds__(TPB) kg_cfl(Group<CflArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const CflArgs& a = g.a[r];
+    cfl_body(v, a.nt, a.nf, a.cface, a.area, a.fgeo, a.W, a.gamma, a.partial);
+}
+
+
+__device__ __forceinline__ void cfl_final_body(int nblk, const double* __restrict__ partial, double cfl,
+                                               double* __restrict__ dt);
+
 __global__ void k_cfl_final(int nblk, const double* __restrict__ partial, double cfl, double* __restrict__ dt) {
+    cfl_final_body(nblk, partial, cfl, dt);
+}
+
+struct CflFinalArgs {
+    int nblk;
+    const double* partial;
+    double cfl;
+    double* dt;
+};
+
+__global__ void __launch_bounds__(64) kg_cfl_final(Group<CflFinalArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const CflFinalArgs& a = g.a[r];
+    cfl_final_body(a.nblk, a.partial, a.cfl, a.dt);
+}
+
+__device__ __forceinline__ void cfl_final_body(int nblk, const double* __restrict__ partial, double cfl,
+                                               double* __restrict__ dt) {
     double b = INFINITY;
     for (int q = threadIdx.x; q < nblk; q += 64) b = fmin(b, partial[q]);
 #pragma unroll
@@ -2295,6 +2887,510 @@ void launch_copy(gks_mesh* m, double* dst, const double* src, int64_t count) {
     if (count <= 0) return;
     hipLaunchKernelGGL(k_copy, dim3(nblocks(count)), dim3(TPB), 0, m->stream, count, dst, src);
     check_launch(KC_MISC);
+}
+
+
+// ================================================================== grouped launches
+// The same kernels for several handles at once (gks_batch_step): one launch
+// per kernel and level covers every handle of the group, each with the
+// arguments and grid of its own launch (Group, GridV), so each handle's
+// arithmetic is exactly that of its own launches.  Handles whose grid is
+// empty for a launch are left out of it.
+
+// Launch `kernel` over the items (arguments, own grid in blocks) in groups
+// of at most MAXB, each item's first block on a multiple of NXCD.
+template <class A, class K>
+static void glaunch(hipStream_t st, K kernel, int tpb, const std::vector<std::pair<A, int>>& items, int kc,
+                    dim3 extra = dim3(1, 1, 1)) {
+    static_assert(sizeof(Group<A>) <= 4000, "grouped kernel arguments");
+    size_t q = 0;
+    while (q < items.size()) {
+        Group<A> g;
+        g.n = 0;
+        int tot = 0;
+        for (; q < items.size() && g.n < MAXB; ++q) {
+            if (items[q].second <= 0) continue;
+            g.start[g.n] = tot;
+            g.nblk[g.n] = items[q].second;
+            g.a[g.n] = items[q].first;
+            tot += (items[q].second + NXCD - 1) / NXCD * NXCD;
+            ++g.n;
+        }
+        if (g.n == 0) continue;
+        g.start[g.n] = tot;
+        hipLaunchKernelGGL(kernel, dim3(tot, extra.y, extra.z), dim3(tpb), 0, st, g);
+        check_launch(kc);
+    }
+}
+
+// Status words of the group's solves and the step counters, copied by the
+// device into one pinned host array (read after one synchronisation).
+struct StatArgs {
+    const Status* st;
+    const int32_t* counters;
+    const double* dt;
+    BatchSlot* out;
+};
+__global__ void __launch_bounds__(64) kg_gather(Group<StatArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const StatArgs& a = g.a[r];
+    const int t = threadIdx.x;
+    constexpr int NW = (int)(sizeof(Status) / sizeof(int32_t));
+    static_assert(sizeof(Status) % sizeof(int32_t) == 0, "Status words");
+    const int32_t* src = reinterpret_cast<const int32_t*>(a.st);
+    int32_t* dst = reinterpret_cast<int32_t*>(&a.out->st);
+    for (int k = t; k < NW; k += 64) dst[k] = src[k];
+    if (a.counters && t < 4) a.out->counters[t] = a.counters[t];
+    if (a.dt && t == 0) a.out->dt = *a.dt;
+}
+
+struct ZeroArgs {
+    int32_t* p;
+    int count;
+    double* dt;      // when set, receives dtv
+    double dtv;
+};
+__global__ void __launch_bounds__(64) kg_zero_set(Group<ZeroArgs> g) {
+    GridV v;
+    const int r = group_locate(g, v);
+    if (r < 0) return;
+    const ZeroArgs& a = g.a[r];
+    if ((int)threadIdx.x < a.count) a.p[threadIdx.x] = 0;
+    if (a.dt && threadIdx.x == 0) *a.dt = a.dtv;
+}
+
+void glaunch_gather(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<BatchSlot*>& out,
+                    bool counters) {
+    std::vector<std::pair<StatArgs, int>> it;
+    for (size_t r = 0; r < ms.size(); ++r)
+        it.push_back({StatArgs{&ms[r]->w.ks->st, counters ? ms[r]->w.counters : nullptr,
+                               counters ? ms[r]->w.dt_dev : nullptr, out[r]}, 1});
+    glaunch(st, kg_gather, 64, it, KC_MISC);
+}
+
+void glaunch_zero_counters(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<double>& dt) {
+    std::vector<std::pair<ZeroArgs, int>> it;
+    for (size_t r = 0; r < ms.size(); ++r)
+        it.push_back({ZeroArgs{ms[r]->w.counters, 4, dt[r] > 0.0 ? ms[r]->w.dt_dev : nullptr, dt[r]}, 1});
+    glaunch(st, kg_zero_set, 64, it, KC_MISC);
+}
+
+void glaunch_cfl(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W) {
+    std::vector<std::pair<CflArgs, int>> a;
+    std::vector<std::pair<CflFinalArgs, int>> b;
+    for (size_t r = 0; r < ms.size(); ++r) {
+        gks_mesh* m = ms[r];
+        const int nt = m->d.nt;
+        const int nb = std::min(1024, nblocks(nt));
+        a.push_back({CflArgs{nt, m->d.nf, m->d.cface, m->d.area, m->d.fgeo, W[r], m->prm.gamma, m->w.dtpart}, nb});
+        b.push_back({CflFinalArgs{nb, m->w.dtpart, m->prm.cfl, m->w.dt_dev}, 1});
+    }
+    glaunch(st, kg_cfl, TPB, a, KC_CFL);
+    glaunch(st, kg_cfl_final, 64, b, KC_CFL);
+}
+
+void glaunch_extrap(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& order) {
+    std::vector<std::pair<ExtrapArgs, int>> it;
+    for (size_t r = 0; r < ms.size(); ++r) {
+        gks_mesh* m = ms[r];
+        const int64_t len = (int64_t)m->d.n * CB;
+        it.push_back({ExtrapArgs{len, order[r], m->w.X, m->w.Xp, m->w.Xpp}, nblocks(len)});
+    }
+    glaunch(st, kg_extrap, TPB, it, KC_EXTRAP);
+}
+
+// sum partials of nval values per handle (partial, nblk per handle) into out
+static void gsum(hipStream_t st, const std::vector<SumArgs>& sa) {
+    std::vector<std::pair<SumArgs, int>> it;
+    for (const auto& a : sa) it.push_back({a, a.nval});
+    glaunch(st, kg_sum_partials, TPB, it, KC_FINAL);
+}
+
+void glaunch_rhs(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W) {
+    std::vector<std::pair<RhsArgs, int>> it;
+    std::vector<SumArgs> sa;
+    for (size_t r = 0; r < ms.size(); ++r) {
+        gks_mesh* m = ms[r];
+        const int nt = m->d.nt, nb = nblocks(nt);
+        it.push_back({RhsArgs{nt, m->d.iperm, m->d.nbc, m->d.a0c, W[r], m->w.R, m->w.npart}, nb});
+        sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, nullptr});
+    }
+    glaunch(st, kg_rhs, TPB, it, KC_RHS);
+    gsum(st, sa);
+}
+
+void glaunch_ctl(hipStream_t st, const std::vector<gks_mesh*>& ms, int mode) {
+    std::vector<std::pair<CtlArgs, int>> it;
+    for (gks_mesh* m : ms) it.push_back({CtlArgs{mode, m->w.ks, m->prm.restart, 0}, 1});
+    glaunch(st, kg_gmres_ctl, 64, it, KC_MISC);
+}
+
+void glaunch_mask_cols(hipStream_t st, const std::vector<gks_mesh*>& ms) {
+    std::vector<std::pair<MaskArgs, int>> it;
+    for (gks_mesh* m : ms) it.push_back({MaskArgs{m->d.n, m->w.X, m->w.ks}, nblocks(m->d.n)});
+    glaunch(st, kg_mask_cols, TPB, it, KC_MISC);
+}
+
+// r = R - K X with its norms, then the start of a cycle (as cycle_start)
+void glaunch_cycle_start(hipStream_t st, const std::vector<gks_mesh*>& ms) {
+    std::vector<std::pair<SpmvArgs<double, double>, int>> it;
+    std::vector<SumArgs> sa;
+    for (gks_mesh* m : ms) {
+        const int n = m->d.n, nb = nblocks(n);
+        it.push_back({SpmvArgs<double, double>{n, m->d.np, m->d.Kval, m->d.Kcol, m->d.worder, m->w.X, nullptr, m->w.R,
+                                               m->w.V, nullptr, m->w.npart},
+                      nb});
+        sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, nullptr});
+    }
+    glaunch(st, kg_spmv<double, double, true>, TPB, it, KC_SPMV_RES);
+    gsum(st, sa);
+    glaunch_ctl(st, ms, 1);
+}
+
+// FP64 BILU(0) solve out = M^-1 (s .* in) for every handle (as launch_ilu):
+// level l of each handle in one launch per kernel variant
+static void gilu(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& in,
+                 const std::vector<const double*>& in_scale, const std::vector<double*>& tmp,
+                 const std::vector<double*>& out) {
+    int maxl = 0;
+    for (gks_mesh* m : ms) maxl = std::max(maxl, (int)m->d.lev_ptr.size() - 1);
+    auto tpb_of = [&](const std::vector<int>& rows) {
+        int tb = TPB;
+        for (int r : rows) tb = std::min(tb, sweep_tpb(r));
+        return tb;
+    };
+    for (int l = 0; l < maxl; ++l) {
+        std::vector<std::pair<IluFwdArgs, int>> f[2];
+        std::vector<int> rows[2];
+        for (size_t r = 0; r < ms.size(); ++r) {
+            const DevMesh& D = ms[r]->d;
+            const auto& lp = D.lev_ptr;
+            const int nl = (int)lp.size() - 1;
+            const int l0 = nl >= 2 ? 1 : 0;
+            if (l < l0 || l >= nl || lp[l + 1] <= lp[l]) continue;
+            const int zrows = l0 ? lp[1] : 0;
+            const int last = l == nl - 1;
+            f[last].push_back({IluFwdArgs{D.np, lp[l], lp[l + 1], D.Lsbase[l], zrows, D.Li, D.Lval, D.Dinv, in[r],
+                                          in_scale[r], tmp[r], out[r], nullptr},
+                               lp[l + 1] - lp[l]});
+            rows[last].push_back(lp[l + 1] - lp[l]);
+        }
+        for (int last = 0; last < 2; ++last) {
+            if (f[last].empty()) continue;
+            const int tb = tpb_of(rows[last]);
+            for (auto& e : f[last]) e.second = nblocks(e.second, tb);
+            if (last)
+                glaunch(st, kg_ilu_fwd<true>, tb, f[last], KC_ILU_FWD);
+            else
+                glaunch(st, kg_ilu_fwd<false>, tb, f[last], KC_ILU_FWD);
+        }
+    }
+    for (int l = maxl - 2; l >= 0; --l) {
+        std::vector<std::pair<IluBwdArgs, int>> b;
+        std::vector<int> rows;
+        for (size_t r = 0; r < ms.size(); ++r) {
+            const DevMesh& D = ms[r]->d;
+            const auto& lp = D.lev_ptr;
+            const int nl = (int)lp.size() - 1;
+            if (l > nl - 2 || lp[l + 1] <= lp[l]) continue;
+            const int l0 = nl >= 2 ? 1 : 0;
+            const bool from_v = l == 0 && l0 == 1;
+            b.push_back({IluBwdArgs{D.np, lp[l], lp[l + 1], D.Usbase[l], D.Ui, D.Uval, D.Dinv, from_v ? in[r] : tmp[r],
+                                    from_v ? in_scale[r] : nullptr, out[r], nullptr},
+                         lp[l + 1] - lp[l]});
+            rows.push_back(lp[l + 1] - lp[l]);
+        }
+        if (b.empty()) continue;
+        const int tb = tpb_of(rows);
+        for (auto& e : b) e.second = nblocks(e.second, tb);
+        glaunch(st, kg_ilu_bwd, tb, b, KC_ILU_BWD);
+    }
+}
+
+// The mixed form's inner sweeps in the split form for every handle (as
+// mx_sweeps_split): sweep sw and level l of each handle in one launch per
+// kernel variant.
+static void gmx_split(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& v,
+                      const std::vector<const double*>& vscale, const std::vector<float*>& z) {
+    using ACC = double;
+    int maxl = 0, maxq = 0;
+    for (gks_mesh* m : ms) {
+        maxl = std::max(maxl, (int)m->d.lev_ptr.size() - 1);
+        maxq = std::max(maxq, m->prm.inner_iters);
+    }
+    for (int sw = 0; sw < maxq; ++sw) {
+        const bool first = sw == 0;
+        for (int l = 0; l < maxl; ++l) {
+            std::vector<std::pair<EsFwdArgs, int>> f[2];
+            std::vector<int> rows[2];
+            for (size_t r = 0; r < ms.size(); ++r) {
+                gks_mesh* m = ms[r];
+                const DevMesh& D = m->d;
+                const auto& lp = D.lev_ptr;
+                const int nl = (int)lp.size() - 1;
+                if (sw >= m->prm.inner_iters || l >= nl || lp[l + 1] <= lp[l]) continue;
+                if (!(first || nl < 2) && l == 0) continue;   // no level-0 forward pass after the first sweep
+                const int last = l == nl - 1;
+                f[last].push_back({EsFwdArgs{D.np, lp[l], lp[l + 1], D.Lsbase[l], lp[1], D.Li, D.Lval32, D.E32,
+                                             D.Dinv32, v[r], vscale[r], m->w.bf, m->w.df, m->w.yf, z[r], nullptr},
+                                   lp[l + 1] - lp[l]});
+                rows[last].push_back(lp[l + 1] - lp[l]);
+            }
+            for (int last = 0; last < 2; ++last) {
+                if (f[last].empty()) continue;
+                int tb = TPB;
+                for (int rr : rows[last]) tb = std::min(tb, sweep_tpb(rr));
+                for (auto& e : f[last]) e.second = nblocks(e.second, tb);
+                if (first && last)
+                    glaunch(st, kg_es_fwd<true, true, ACC>, tb, f[last], KC_ILU_FWD32);
+                else if (first)
+                    glaunch(st, kg_es_fwd<true, false, ACC>, tb, f[last], KC_ILU_FWD32);
+                else if (last)
+                    glaunch(st, kg_es_fwd<false, true, ACC>, tb, f[last], KC_ILU_FWD32);
+                else
+                    glaunch(st, kg_es_fwd<false, false, ACC>, tb, f[last], KC_ILU_FWD32);
+            }
+        }
+        for (int l = maxl - 2; l >= 0; --l) {
+            std::vector<std::pair<EsBwdArgs, int>> b;
+            std::vector<int> rows;
+            for (size_t r = 0; r < ms.size(); ++r) {
+                gks_mesh* m = ms[r];
+                const DevMesh& D = m->d;
+                const auto& lp = D.lev_ptr;
+                const int nl = (int)lp.size() - 1;
+                if (sw >= m->prm.inner_iters || l > nl - 2 || lp[l + 1] <= lp[l]) continue;
+                b.push_back({EsBwdArgs{lp[l], lp[l + 1], D.Usbase[l], D.Ui, D.Uval32, l == 0 ? m->w.bf : m->w.yf, z[r],
+                                       nullptr},
+                             lp[l + 1] - lp[l]});
+                rows.push_back(lp[l + 1] - lp[l]);
+            }
+            if (b.empty()) continue;
+            int tb = TPB;
+            for (int rr : rows) tb = std::min(tb, sweep_tpb(rr));
+            for (auto& e : b) e.second = nblocks(e.second, tb);
+            glaunch(st, kg_es_bwd<ACC>, tb, b, KC_ILU_BWD32);
+        }
+    }
+}
+
+// Arnoldi step k for every handle (as arnoldi_step without a gate)
+void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
+    const bool fused = k + 1 <= FUSED_DOTS_MAX;
+    const bool mixed = ms[0]->prm.precision == GKS_MIXED;
+    std::vector<const double*> vk, sk;
+    std::vector<double*> t1, t2;
+    std::vector<float*> zk;
+    for (gks_mesh* m : ms) {
+        const int64_t vs = (int64_t)(m->d.n + 1) * CB;
+        vk.push_back(m->w.V + (int64_t)k * vs);
+        sk.push_back(&m->w.ks->scale[k][0]);
+        t1.push_back(m->w.t1);
+        t2.push_back(m->w.t2);
+        zk.push_back(mixed ? m->w.Z + (int64_t)k * vs : nullptr);
+    }
+    if (mixed)
+        gmx_split(st, ms, vk, sk, zk);
+    else
+        gilu(st, ms, vk, sk, t1, t2);
+    std::vector<SumArgs> sa;
+    if (fused) {
+        if (mixed) {
+            std::vector<std::pair<SpmvDotsArgs<float>, int>> it;
+            for (size_t r = 0; r < ms.size(); ++r) {
+                gks_mesh* m = ms[r];
+                const int n = m->d.n, nb = nblocks(n);
+                const int64_t vs = (int64_t)(n + 1) * CB;
+                it.push_back({SpmvDotsArgs<float>{n, m->d.np, m->d.Kval, m->d.Kcol, m->d.worder, zk[r], m->w.w, m->w.V,
+                                                  vs, k + 1, m->w.dpart, nullptr},
+                              nb});
+                sa.push_back(SumArgs{(k + 1) * NC, nb, m->w.dpart, &m->w.ks->scale[0][0], &m->w.ks->h1[0][0], nullptr});
+            }
+            glaunch(st, kg_spmv_dots<float>, TPB, it, KC_SPMV);
+        } else {
+            std::vector<std::pair<SpmvDotsArgs<double>, int>> it;
+            for (size_t r = 0; r < ms.size(); ++r) {
+                gks_mesh* m = ms[r];
+                const int n = m->d.n, nb = nblocks(n);
+                const int64_t vs = (int64_t)(n + 1) * CB;
+                it.push_back({SpmvDotsArgs<double>{n, m->d.np, m->d.Kval, m->d.Kcol, m->d.worder, m->w.t2, m->w.w,
+                                                   m->w.V, vs, k + 1, m->w.dpart, nullptr},
+                              nb});
+                sa.push_back(SumArgs{(k + 1) * NC, nb, m->w.dpart, &m->w.ks->scale[0][0], &m->w.ks->h1[0][0], nullptr});
+            }
+            glaunch(st, kg_spmv_dots<double>, TPB, it, KC_SPMV);
+        }
+        gsum(st, sa);
+        // out = w - V h1 with the second products
+        std::vector<std::pair<AxpyDotsArgs, int>> ad;
+        sa.clear();
+        for (gks_mesh* m : ms) {
+            const int n = m->d.n;
+            const int64_t vs = (int64_t)(n + 1) * CB;
+            const int nb = (std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10)) + 4) / 5 * 5;
+            ad.push_back({AxpyDotsArgs{n, m->w.V, vs, k + 1, &m->w.ks->h1[0][0], &m->w.ks->scale[0][0], m->w.w, m->w.w,
+                                       m->w.dpart, nullptr},
+                          nb});
+            sa.push_back(SumArgs{(k + 1) * NC, nb, m->w.dpart, &m->w.ks->scale[0][0], &m->w.ks->h2[0][0], nullptr});
+        }
+        glaunch(st, kg_axpy_dots, TPB, ad, KC_AXPY_DOTS);
+        gsum(st, sa);
+    } else {
+        // y = K M^-1 v_k
+        if (mixed) {
+            std::vector<std::pair<SpmvArgs<double, float>, int>> it;
+            for (size_t r = 0; r < ms.size(); ++r) {
+                gks_mesh* m = ms[r];
+                it.push_back({SpmvArgs<double, float>{m->d.n, m->d.np, m->d.Kval, m->d.Kcol, m->d.worder, zk[r], nullptr,
+                                                      nullptr, m->w.w, nullptr, nullptr},
+                              nblocks(m->d.n)});
+            }
+            glaunch(st, kg_spmv<double, float, false>, TPB, it, KC_SPMV);
+        } else {
+            std::vector<std::pair<SpmvArgs<double, double>, int>> it;
+            for (gks_mesh* m : ms)
+                it.push_back({SpmvArgs<double, double>{m->d.n, m->d.np, m->d.Kval, m->d.Kcol, m->d.worder, m->w.t2,
+                                                       nullptr, nullptr, m->w.w, nullptr, nullptr},
+                              nblocks(m->d.n)});
+            glaunch(st, kg_spmv<double, double, false>, TPB, it, KC_SPMV);
+        }
+        // h1 = V^T w, w -= V h1, h2 = V^T w (unfused passes, as launch_dots_reduce / launch_axpy)
+        const int nch = (k + 1 + RED_CHUNK - 1) / RED_CHUNK;
+        for (int pass = 0; pass < 2; ++pass) {
+            std::vector<std::pair<DotsArgs, int>> dt;
+            sa.clear();
+            for (gks_mesh* m : ms) {
+                const int64_t vs = (int64_t)(m->d.n + 1) * CB;
+                dt.push_back({DotsArgs{m->d.n, m->w.V, vs, k + 1, m->w.w, m->w.partial, nullptr}, m->w.nblk_red});
+                sa.push_back(SumArgs{(k + 1) * NC, m->w.nblk_red, m->w.partial, &m->w.ks->scale[0][0],
+                                     pass == 0 ? &m->w.ks->h1[0][0] : &m->w.ks->h2[0][0], nullptr});
+            }
+            glaunch(st, kg_dots, TPB, dt, KC_DOTS, dim3(1, nch, 1));
+            gsum(st, sa);
+            if (pass == 0) {
+                std::vector<std::pair<AxpyArgs, int>> ax;
+                for (gks_mesh* m : ms) {
+                    const int n = m->d.n;
+                    const int64_t vs = (int64_t)(n + 1) * CB;
+                    ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h1[0][0], &m->w.ks->scale[0][0], m->w.w,
+                                           m->w.w, nullptr, nullptr},
+                                  std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10))});
+                }
+                glaunch(st, kg_axpy, TPB, ax, KC_AXPY_DOTS);
+            }
+        }
+    }
+    // v_{k+1} = w - V h2 with its norm, then the control step
+    std::vector<std::pair<AxpyArgs, int>> ax;
+    sa.clear();
+    for (gks_mesh* m : ms) {
+        const int n = m->d.n;
+        const int64_t vs = (int64_t)(n + 1) * CB;
+        const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));
+        ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h2[0][0], &m->w.ks->scale[0][0], m->w.w,
+                               m->w.V + (int64_t)(k + 1) * vs, nullptr, m->w.npart},
+                      nb});
+        sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, nullptr});
+    }
+    glaunch(st, kg_axpy, TPB, ax, KC_AXPY_DOTS);
+    gsum(st, sa);
+    glaunch_ctl(st, ms, 2);
+}
+
+// End of a cycle of nvec[r] steps for every handle (as end_cycle without a
+// graph): y from the triangular system, then X += Z y (mixed) or
+// X += M^-1 (V y) (FP64).
+void glaunch_end_cycle(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& nvec) {
+    glaunch_ctl(st, ms, 3);
+    const bool mixed = ms[0]->prm.precision == GKS_MIXED;
+    if (mixed) {
+        std::vector<std::pair<CombineArgs<float>, int>> it;
+        for (size_t r = 0; r < ms.size(); ++r) {
+            gks_mesh* m = ms[r];
+            const int n = m->d.n;
+            const int64_t vs = (int64_t)(n + 1) * CB;
+            it.push_back({CombineArgs<float>{n, m->w.Z, vs, nvec[r], &m->w.ks->y[0][0], m->w.ones, m->w.X, nullptr,
+                                             nullptr},
+                          nblocks((int64_t)n * Grp<float>::T)});
+        }
+        glaunch(st, kg_combine<float, true>, TPB, it, KC_COMBINE);
+        return;
+    }
+    std::vector<std::pair<CombineArgs<double>, int>> it;
+    std::vector<const double*> in, sc;
+    std::vector<double*> tmp, out;
+    for (size_t r = 0; r < ms.size(); ++r) {
+        gks_mesh* m = ms[r];
+        const int n = m->d.n;
+        const int64_t vs = (int64_t)(n + 1) * CB;
+        it.push_back({CombineArgs<double>{n, m->w.V, vs, nvec[r], &m->w.ks->y[0][0], &m->w.ks->scale[0][0], m->w.t1,
+                                          nullptr, nullptr},
+                      nblocks((int64_t)n * Grp<double>::T)});
+        in.push_back(m->w.t1);
+        sc.push_back(nullptr);
+        tmp.push_back(m->w.t2);
+        out.push_back(m->w.t3);
+    }
+    glaunch(st, kg_combine<double, false>, TPB, it, KC_COMBINE);
+    gilu(st, ms, in, sc, tmp, out);
+    std::vector<std::pair<AccArgs, int>> ac;
+    for (gks_mesh* m : ms) {
+        const int64_t len = (int64_t)m->d.n * CB;
+        ac.push_back({AccArgs{len, m->w.X, m->w.t3, nullptr}, nblocks(len)});
+    }
+    glaunch(st, kg_acc, TPB, ac, KC_AXPY);
+}
+
+// Copy-out of X, fluxes and update for every handle (as the eager step)
+void glaunch_flux_update(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W) {
+    std::vector<std::pair<CopyoutArgs<double>, int>> co;
+    std::vector<std::pair<FluxArgs, int>> fl;
+    std::vector<std::pair<UpdateArgs, int>> up;
+    for (size_t r = 0; r < ms.size(); ++r) {
+        gks_mesh* m = ms[r];
+        const int nt = m->d.nt;
+        co.push_back({CopyoutArgs<double>{nt, m->d.iperm, m->w.X, m->w.Xcell}, nblocks(nt)});
+        FluxArgs a;
+        a.nf = m->d.nf;
+        a.nt = nt;
+        a.own = m->d.own;
+        a.nbr = m->d.nbr;
+        a.fgeo = m->d.fgeo;
+        a.gpd = m->d.gpd;
+        a.cgeo = m->d.cgeo;
+        a.bc_kind = m->d.bc_kind;
+        a.bc_state = m->d.bc_state;
+        a.W = W[r];
+        a.X = m->w.Xcell;
+        a.dt = m->w.dt_dev;
+        a.F = m->w.F;
+        a.nonphys = m->w.counters;
+        a.fp.gamma = m->prm.gamma;
+        a.fp.K = 2.0 / (m->prm.gamma - 1.0) - 2.0;
+        a.fp.mu = m->prm.mu;
+        a.fp.eps = m->prm.tau_eps;
+        a.fp.exact_time = m->prm.exact_time;
+        a.fallback = m->prm.nonphys_fallback;
+        fl.push_back({a, nblocks(2 * (int64_t)a.nf, 128)});
+        up.push_back({UpdateArgs{nt, m->d.nf, m->d.cface, m->d.area, W[r], m->w.F, m->w.Wn, m->prm.gamma,
+                                 m->w.counters + 1},
+                      nblocks(nt)});
+    }
+    glaunch(st, kg_copyout<double>, TPB, co, KC_COPYOUT);
+    glaunch(st, kg_flux, 128, fl, KC_FLUX);
+    glaunch(st, kg_update, TPB, up, KC_UPDATE);
+}
+
+// W <- Wn for every handle
+void glaunch_commit(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<double*>& W) {
+    std::vector<std::pair<CopyArgs, int>> it;
+    for (size_t r = 0; r < ms.size(); ++r) {
+        const int64_t len = (int64_t)4 * ms[r]->d.nt;
+        it.push_back({CopyArgs{len, W[r], ms[r]->w.Wn}, nblocks(len)});
+    }
+    glaunch(st, kg_copy, TPB, it, KC_MISC);
 }
 
 }  // namespace gks

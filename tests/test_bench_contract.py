@@ -55,6 +55,9 @@ def test_roofline_arithmetic(monkeypatch):
     assert r["achieved"] == pytest.approx(2.4e8 / 60e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
     assert r["traffic"] is None
-    f = b.flux_fp64(prof)
+    f = b.flux_fp64(prof, 3_000_000)
     assert f["achieved"] == pytest.approx(3.2e10 / 0.8e-3 / 1e12, rel=1e-3)
     assert f["frac"] == pytest.approx(f["achieved"] / 78.6, rel=1e-3)
+    assert f["executed_flop_per_gauss_point"] == pytest.approx(3.2e10 / 3e6, rel=1e-3)
+    fg = b.algorithmic_flux_flops()
+    assert fg and f["algorithmic_rate_TFLOPs"] == pytest.approx(fg * 3e6 / 0.8e-3 / 1e12, rel=1e-3)
