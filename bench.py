@@ -352,20 +352,22 @@ def kernel_table(prof: dict) -> dict:
     return out
 
 
-def serving_leg(n_requests: int, slots: int) -> dict:
-    """The first n_requests of the seeded serving stream (Poisson arrivals at
-    40/s; advection or shock-vortex, 2e3-2e5 triangles log-uniform, 50-500
-    steps, FP64 or mixed), served with continuous batching."""
+def serving_leg(n_requests: int, max_batch: int) -> dict:
+    """The first n_requests of the seeded serving stream of 2,000 requests
+    (Poisson arrivals at 40/s; advection or shock-vortex, 2e3-2e5 triangles
+    log-uniform, 50-500 steps, FP64 or mixed), served with continuous
+    batching: each request's mesh and initial state are generated by the
+    server's set-up threads after admission."""
     import gks_inputs as gi
     import paper_1802_00704_amd as g
     from paper_1802_00704_amd.serving import Request, Server
     reqs = []
-    for sp in gi.serving_specs(n_requests):
-        m, W0 = gi.serving_case(sp)
+    for sp in gi.serving_specs(2000)[:n_requests]:
         prm = {"precision": g.GKS_MIXED if sp["mixed"] else g.GKS_FP64, "nonphys_fallback": 1}
-        reqs.append(Request(rid=sp["rid"], mesh=m, W0=W0, steps=sp["steps"], params=prm, arrival=sp["arrival"]))
-    stats = Server(slots=slots).run(reqs, realtime=True)
-    stats["stream"] = ("first %d of 2000 seeded requests, Poisson 40/s, 2e3-2e5 triangles, 50-500 steps, "
+        reqs.append(Request(rid=sp["rid"], mesh=None, W0=None, make=lambda sp=sp: gi.serving_case(sp),
+                            nt_hint=gi.serving_cells(sp), steps=sp["steps"], params=prm, arrival=sp["arrival"]))
+    stats = Server(max_batch=max_batch).run(reqs, realtime=True)
+    stats["stream"] = ("first %d of the 2000 seeded requests, Poisson 40/s, 2e3-2e5 triangles, 50-500 steps, "
                        "50/50 FP64/mixed" % n_requests)
     return stats
 
@@ -385,7 +387,8 @@ def main():
                          "every traced launch does work)")
     ap.add_argument("--serving-requests", type=int, default=200,
                     help="requests of the serving stream to run after the throughput legs (0: skip)")
-    ap.add_argument("--serving-slots", type=int, default=8)
+    ap.add_argument("--serving-max-batch", type=int, default=64,
+                    help="requests per batched step (gks_batch_step) of each precision's driver")
     ap.add_argument("--late-window", type=int, default=480,
                     help="shock-vortex workload: also time steps late_window+1 .. late_window+steps of the "
                          "500-step run (0: skip)")
@@ -438,7 +441,7 @@ def main():
             lim[name] = leg
             print("# mixed + limiter (%s variables): %.4g cell-steps/s, %.3f ms/step, %.0f cells limited per step" %
                   (name, rl["value"], rl["ms_per_step"], rl["limited_cells_per_step"]), file=sys.stderr, flush=True)
-    serving = serving_leg(args.serving_requests, args.serving_slots) if args.serving_requests > 0 else None
+    serving = serving_leg(args.serving_requests, args.serving_max_batch) if args.serving_requests > 0 else None
     if serving:
         print("# serving: %.4g cell-steps/s, step p50/p99 %.2f/%.2f ms, solve p50/p99 %.2f/%.2f ms" %
               (serving["throughput_cell_steps_per_s"], serving["step_ms_p50"], serving["step_ms_p99"],

@@ -26,7 +26,7 @@ import numpy as np
 __all__ = [
     "Mesh", "jss_mesh", "cell_average", "density_advection_ic",
     "density_advection_exact", "shock_vortex_ic", "cavity_ic",
-    "prim_to_cons", "random_coefficients", "serving_specs", "serving_case", "BC_NONE", "BC_SLIP",
+    "prim_to_cons", "random_coefficients", "serving_specs", "serving_case", "serving_cells", "BC_NONE", "BC_SLIP",
     "BC_NOSLIP", "BC_INFLOW", "BC_OUTFLOW",
 ]
 
@@ -323,6 +323,15 @@ def serving_specs(n_requests: int = 2000, rate: float = 40.0, seed: int = 5, nt_
     return [{"rid": i, "kind": "advection" if kinds[i] == 0 else "shock_vortex", "nt": float(nts[i]),
              "steps": int(steps[i]), "mixed": bool(mixed[i]), "seed": int(seeds[i]), "arrival": float(arrivals[i])}
             for i in range(n_requests)]
+
+
+def serving_cells(spec: dict) -> int:
+    """Triangles of the mesh serving_case builds for spec (without building it)."""
+    if spec["kind"] == "advection":
+        n = max(3, int(round(np.sqrt(spec["nt"] / 2.0))))
+        return 2 * n * n
+    ny = max(2, int(round(np.sqrt(spec["nt"] / 4.0))))
+    return 4 * ny * ny
 
 
 def serving_case(spec: dict):

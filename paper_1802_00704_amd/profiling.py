@@ -57,6 +57,8 @@ def kernel_sources_sha256() -> str:
 
 def kernel_class(name: str) -> str | None:
     base = re.sub(r"\(.*", "", name).replace("void ", "").replace("gks::", "").strip()
+    if base.startswith("kg_"):          # grouped launches (batched steps) count with their kernel
+        base = "k_" + base[3:]
     for pat, cls in CLASS_OF:
         if base.startswith(pat):
             return cls
