@@ -39,6 +39,8 @@ class Params:
     fallback: bool = False     # non-physical Gauss-point state -> cell average
     reading: str = "G"
     all_quadratic: bool = False
+    solve: str = "auto"        # CLS solve: "direct", "cg", or "auto" (direct up to
+                               # cls.DIRECT_MAX_UNKNOWNS unknowns, CG beyond)
 
 
 def gp_states(geo: Geometry, W, X, cells, pts):
@@ -237,6 +239,11 @@ class Solver:
     def reconstruct(self, W):
         R = self.rhs(W)
         nt = self.geo.nt
+        mode = self.prm.solve
+        if mode == "auto":
+            mode = "direct" if 5 * nt <= cls_mod.DIRECT_MAX_UNKNOWNS or self.prm.reading != "G" else "cg"
+        if mode == "cg":
+            return cls_mod.solve_cg(self.K, R)
         b = R.reshape(4, 5 * nt).T
         if self._lu is None:
             self._lu = cls_mod.factorize(self.K, spd=self.prm.reading == "G")
