@@ -133,7 +133,10 @@ def test_characteristic_limiting(case):
     variables and finds less oscillation with the latter.  Measured at
     h = 1/100: the mean excursion falls 15% at Sod (1.12e-3 -> 0.96e-3) and
     2% at Lax, the L1 error a little in both; the single largest excursion
-    falls at Sod and rises 12% at Lax."""
+    falls at Sod and rises 12% at Lax.  So the observation holds at Sod on
+    every measure and at Lax only on the averaged ones: at Lax the test
+    checks the L1 error and the mean excursion, and makes no claim about the
+    largest one."""
     cons = run(100, case, g.LIMIT_CONSERVATIVE)
     char = run(100, case, g.LIMIT_CHARACTERISTIC)
     print("h=1/100 conservative", cons, "characteristic", char, flush=True)
@@ -144,7 +147,6 @@ def test_characteristic_limiting(case):
         assert char["overshoot"] < cons["overshoot"]
     else:
         assert char["osc_l1"] <= 1.02 * cons["osc_l1"]
-        assert char["overshoot"] < 1.25 * cons["overshoot"]
 
 
 def test_sod_first_steps_match_the_oracle():
