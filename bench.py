@@ -366,7 +366,7 @@ def serving_leg(n_requests: int, max_batch: int) -> dict:
         prm = {"precision": g.GKS_MIXED if sp["mixed"] else g.GKS_FP64, "nonphys_fallback": 1}
         reqs.append(Request(rid=sp["rid"], mesh=None, W0=None, make=lambda sp=sp: gi.serving_case(sp),
                             nt_hint=gi.serving_cells(sp), steps=sp["steps"], params=prm, arrival=sp["arrival"]))
-    stats = Server(max_batch=max_batch).run(reqs, realtime=True)
+    stats = Server(max_batch=max_batch, log_every=50).run(reqs, realtime=True)
     stats["stream"] = ("first %d of the 2000 seeded requests, Poisson 40/s, 2e3-2e5 triangles, 50-500 steps, "
                        "50/50 FP64/mixed" % n_requests)
     return stats

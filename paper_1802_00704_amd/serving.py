@@ -131,7 +131,7 @@ class Server:
     collects the result and frees the request's state."""
 
     def __init__(self, hbm_budget: int | None = None, max_batch: int = 64, setup_threads: int = 4,
-                 build=None, stepper=None, finish=None):
+                 build=None, stepper=None, finish=None, log_every: int = 0):
         if hbm_budget is None:
             import torch
             free, _ = torch.cuda.mem_get_info()
@@ -154,6 +154,7 @@ class Server:
         self.peak_batch = 0
         self.batch_steps = 0
         self.completed = []
+        self.log_every = int(log_every)   # > 0: a line on stderr every log_every finished requests
 
     # ----------------------------------------------------------- admission
     def submit(self, req: Request):
@@ -184,6 +185,10 @@ class Server:
             self._admitted -= 1
             self.completed.append(req)
             self._admit_locked()
+            done = len(self.completed)
+        if self.log_every > 0 and done % self.log_every == 0:
+            import sys
+            print("# serving: %d requests finished at %.1f s" % (done, req.t_done), file=sys.stderr, flush=True)
 
     def _idle_locked(self) -> bool:
         return self._closed and not self._queue and not self._setup and self._admitted == 0
