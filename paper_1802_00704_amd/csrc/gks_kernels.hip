@@ -124,6 +124,34 @@ template <> struct Vec16<double> {
     static __device__ __forceinline__ void put(double* o, const double2& v) { o[0] = v.x; o[1] = v.y; }
 };
 
+// Streams that a launch reads once (matrix blocks, factor blocks, Krylov
+// basis vectors, rows of the input vector) are read with nontemporal loads,
+// and the SpMV output with nontemporal stores: they bypass the L2 retention
+// that the vectors read again by neighbouring rows (the SpMV's gathered x,
+// the sweeps' solution) need.  The hints change no value: every result is
+// bitwise the same with plain loads.  The builtins take clang vector types.
+typedef float nvf4 __attribute__((ext_vector_type(4)));
+typedef double nvd2 __attribute__((ext_vector_type(2)));
+template <typename T> struct NV;
+template <> struct NV<float> { using type = nvf4; static constexpr int N = 4; };
+template <> struct NV<double> { using type = nvd2; static constexpr int N = 2; };
+
+// load_block with nontemporal loads.
+template <typename T>
+__device__ __forceinline__ void load_block_nt(const T* __restrict__ val, int64_t np, int s, int i, T (&blk)[25]) {
+    using VT = typename NV<T>::type;
+    constexpr int V = NV<T>::N;
+    const T* base = val + (int64_t)s * 25 * np;
+    const VT* vb = reinterpret_cast<const VT*>(base);
+#pragma unroll
+    for (int g = 0; g < 24 / V; ++g) {
+        const VT v = __builtin_nontemporal_load(vb + (int64_t)g * np + i);
+#pragma unroll
+        for (int e = 0; e < V; ++e) blk[g * V + e] = v[e];
+    }
+    blk[24] = __builtin_nontemporal_load(base + 24 * np + i);
+}
+
 template <typename T>
 __device__ __forceinline__ void load_block(const T* __restrict__ val, int64_t np, int s, int i, T (&blk)[25]) {
     using VT = typename Vec16<T>::type;
@@ -232,22 +260,49 @@ __global__ void __launch_bounds__(TPB) kg_rhs(Group<RhsArgs> g) {
 // wave's LDS area: lanes copy 16-byte chunks lane-contiguously to or from
 // global memory, and each lane reads or writes its own row in LDS.  Every
 // lane of the wave must take part (rows past nr are neither read nor
-// written in global memory).
+// written in global memory).  rows_load reads with nontemporal loads.
 template <typename T>
 __device__ __forceinline__ void rows_load(const T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
                                           T (&v)[CB]) {
     constexpr int K = CB * (int)sizeof(T) / 16;   // 16-byte chunks per row
-    const float4* src = reinterpret_cast<const float4*>(a + i0 * CB);
+    const nvf4* src = reinterpret_cast<const nvf4*>(a + i0 * CB);
     const int nc = nr * K;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int c = k * 64 + lane;
-        if (c < nc) st[c] = src[c];
+        if (c < nc) {
+            const nvf4 v = __builtin_nontemporal_load(src + c);
+            st[c] = make_float4(v[0], v[1], v[2], v[3]);
+        }
     }
     __builtin_amdgcn_wave_barrier();
     const T* my = reinterpret_cast<const T*>(st + lane * K);
 #pragma unroll
     for (int q = 0; q < CB; ++q) v[q] = my[q];
+    __builtin_amdgcn_wave_barrier();
+}
+
+// rows_store with nontemporal global stores (the SpMV output).
+template <typename T>
+__device__ __forceinline__ void rows_store_nt(T* __restrict__ a, int64_t i0, int nr, float4* st, int lane,
+                                              const T (&v)[CB]) {
+    constexpr int K = CB * (int)sizeof(T) / 16;
+    T* my = reinterpret_cast<T*>(st + lane * K);
+#pragma unroll
+    for (int q = 0; q < CB; ++q) my[q] = v[q];
+    __builtin_amdgcn_wave_barrier();
+    nvf4* dst = reinterpret_cast<nvf4*>(a + i0 * CB);
+    const int nc = nr * K;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = k * 64 + lane;
+        if (c < nc) {
+            const float4 w = st[c];
+            nvf4 nv;
+            nv[0] = w.x; nv[1] = w.y; nv[2] = w.z; nv[3] = w.w;
+            __builtin_nontemporal_store(nv, dst + c);
+        }
+    }
     __builtin_amdgcn_wave_barrier();
 }
 
@@ -299,7 +354,7 @@ __device__ __forceinline__ void spmv_body(GRID grid, int n, int np, const T* __r
 #pragma unroll
             for (int q = 0; q < CB; ++q) xv[q] = (double)xj[q];
             T blk[25];
-            load_block(val, np, s, i, blk);
+            load_block_nt(val, np, s, i, blk);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -330,7 +385,7 @@ __device__ __forceinline__ void spmv_body(GRID grid, int n, int np, const T* __r
             for (int r = 0; r < NB; ++r) out[c * NB + r] = sc * acc[c * NB + r];
         }
     }
-    if (nr > 0) rows_store(y, i0, nr, st, lane, out);
+    if (nr > 0) rows_store_nt(y, i0, nr, st, lane, out);
     if (RESID && partial) block_sumsq4(sq, partial, grid);
 }
 
@@ -425,7 +480,7 @@ __device__ __forceinline__ void spmv_dots_body(GRID grid, int n, int np, const d
 #pragma unroll
             for (int q = 0; q < CB; ++q) xv[q] = (double)xj[q];
             double blk[25];
-            load_block(val, np, s, i, blk);
+            load_block_nt(val, np, s, i, blk);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -448,7 +503,8 @@ __device__ __forceinline__ void spmv_dots_body(GRID grid, int n, int np, const d
 #pragma unroll
             for (int j = 0; j < RED_CHUNK; ++j) {
                 if (j < nvd) {
-                    const double2 vv = reinterpret_cast<const double2*>(V + (int64_t)j * vstride + i0 * CB)[c];
+                    const nvd2 vn = __builtin_nontemporal_load(reinterpret_cast<const nvd2*>(V + (int64_t)j * vstride + i0 * CB) + c);
+                    const double2 vv = make_double2(vn[0], vn[1]);
 #pragma unroll
                     for (int cc = 0; cc < NC; ++cc)
                         d[j][cc] += (cc == c0 ? vv.x * yv.x : 0.0) + (cc == c1 ? vv.y * yv.y : 0.0);
@@ -524,7 +580,10 @@ __device__ __forceinline__ void axpy_dots_body(GRID grid, int n, const double* _
 #pragma unroll
         for (int j = 0; j < RED_CHUNK; ++j) {
             if (j < nvec) {
-                vv[j] = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
+                {
+                    const nvd2 vn = __builtin_nontemporal_load(reinterpret_cast<const nvd2*>(V + (int64_t)j * vstride + off));
+                    vv[j] = make_double2(vn[0], vn[1]);
+                }
                 a0 -= hs0[j] * vv[j].x;
                 a1 -= hs1[j] * vv[j].y;
             }
@@ -624,7 +683,7 @@ __device__ __forceinline__ void slice_sub(ACC (&acc)[CB], const T* __restrict__ 
 #pragma unroll
         for (int q = 0; q < CB; ++q) xv[q] = xj[q];
         T blk[25];
-        load_block(val + ch * 25 * 64, 64, 0, sr.lane, blk);
+        load_block_nt(val + ch * 25 * 64, 64, 0, sr.lane, blk);
         block_sub(acc, blk, xv);
     }
 }
@@ -644,7 +703,7 @@ __device__ __forceinline__ void slice_sub_split(ACC (&acc)[CB], const T* __restr
 #pragma unroll
         for (int q = 0; q < CB; ++q) xv[q] = xj[q];
         T blk[25];
-        load_block(val + ch * 25 * 64, 64, 0, sr.lane, blk);
+        load_block_nt(val + ch * 25 * 64, 64, 0, sr.lane, blk);
         block_sub(acc, blk, xv);
     }
 }
@@ -673,7 +732,7 @@ __device__ __forceinline__ void slice_sub_lo(ACC (&acc)[CB], const T* __restrict
                 for (int r = 0; r < NB; ++r) xv[c * NB + r] *= xs[c];
         }
         T blk[25];
-        load_block(val + ch * 25 * 64, 64, 0, sr.lane, blk);
+        load_block_nt(val + ch * 25 * 64, 64, 0, sr.lane, blk);
         block_sub(acc, blk, xv);
     }
 }
@@ -710,7 +769,7 @@ __device__ __forceinline__ void ilu_fwd_body(GRID grid, int np, int r0, int r1, 
         for (int q = 0; q < CB; ++q) zi[q] = 0.0;
         if (lane < nr) {
             double d[25];
-            load_block(Dinv, np, 0, (int)i0 + lane, d);
+            load_block_nt(Dinv, np, 0, (int)i0 + lane, d);
 #pragma unroll
             for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -789,7 +848,7 @@ __device__ __forceinline__ void ilu_bwd_body(GRID grid, int np, int r0, int r1, 
     if (lane < nr) {
         slice_sub(acc, Uv, Ui.col, slice_ref(Ui, sbase, rl), z);
         double d[25];
-        load_block(Dinv, np, 0, i, d);
+        load_block_nt(Dinv, np, 0, i, d);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
@@ -1003,7 +1062,7 @@ __device__ __forceinline__ void es_fwd_body(GRID grid, int np, int r0, int r1, i
         for (int q = 0; q < CB; ++q) bs[q] = 0.0f;
         if (valid) {
             float db[25];
-            load_block(Dinv, np, 0, i, db);
+            load_block_nt(Dinv, np, 0, i, db);
             block_mul(bs, db, x);
         }
         rows_store(b, i0, nr, st, lane, bs);
@@ -1017,7 +1076,7 @@ __device__ __forceinline__ void es_fwd_body(GRID grid, int np, int r0, int r1, i
         for (int q = 0; q < CB; ++q) acc[q] = (ACC)bl[q];
         if (valid) {
             float gb[25];
-            load_block(G, np, 0, i, gb);
+            load_block_nt(G, np, 0, i, gb);
             block_add(acc, gb, zi);
         }
     }
@@ -1242,7 +1301,8 @@ __device__ __forceinline__ void axpy_body(GRID grid, int n, const double* __rest
         double a0 = w2.x, a1 = w2.y;
 #pragma unroll 4
         for (int j = 0; j < nvec; ++j) {
-            const double2 v = *reinterpret_cast<const double2*>(V + (int64_t)j * vstride + off);
+            const nvd2 vn = __builtin_nontemporal_load(reinterpret_cast<const nvd2*>(V + (int64_t)j * vstride + off));
+            const double2 v = make_double2(vn[0], vn[1]);
             a0 -= h[j * NC + c0] * scale[j * NC + c0] * v.x;
             a1 -= h[j * NC + c1] * scale[j * NC + c1] * v.y;
         }
@@ -1305,8 +1365,12 @@ __device__ __forceinline__ void combine_body(GRID grid, int n, const VT* __restr
 #pragma unroll 4
     for (int j = 0; j < nvec; ++j) {
         VT v[E];
-        *reinterpret_cast<typename Vec16<VT>::type*>(v) =
-            *reinterpret_cast<const typename Vec16<VT>::type*>(V + (int64_t)j * vstride + off);
+        {
+            const typename NV<VT>::type vn =
+                __builtin_nontemporal_load(reinterpret_cast<const typename NV<VT>::type*>(V + (int64_t)j * vstride + off));
+#pragma unroll
+            for (int e = 0; e < E; ++e) v[e] = vn[e];
+        }
 #pragma unroll
         for (int e = 0; e < E; ++e) acc[e] += y[j * NC + col[e]] * scale[j * NC + col[e]] * (double)v[e];
     }
