@@ -1170,8 +1170,10 @@ __device__ __forceinline__ void es_bwd_body(GRID grid, int r0, int r1, int sbase
     rows_store(z, i0, nr, st, lane, zn);
 }
 
+// At most 128 VGPRs (four waves per SIMD): the backward sweep fits them
+// without spills and the extra wave hides more of its gather latency.
 template <typename ACC>
-__global__ void __launch_bounds__(TPB) k_es_bwd(int r0, int r1, int sbase, SlicedIdx Ui,
+__global__ void __launch_bounds__(TPB, 4) k_es_bwd(int r0, int r1, int sbase, SlicedIdx Ui,
                                                 const float* __restrict__ KUv, const float* __restrict__ w,
                                                 float* __restrict__ z, const int32_t* __restrict__ gate) {
     es_bwd_body<Grid1, ACC>(Grid1(), r0, r1, sbase, Ui, KUv, w, z, gate);
@@ -1189,7 +1191,7 @@ struct EsBwdArgs {
 };
 
 template <typename ACC>
-__global__ void __launch_bounds__(TPB) kg_es_bwd(Group<EsBwdArgs> g) {
+__global__ void __launch_bounds__(TPB, 4) kg_es_bwd(Group<EsBwdArgs> g) {
     GridV v;
     const int r = group_locate(g, v);
     if (r < 0) return;
