@@ -8,7 +8,9 @@ the third-order flux).
 * Wall fluxes: no mass, energy or tangential-momentum flux through a slip
   wall; slip and no-slip ghosts coincide for a fluid at rest.
 * Third-order convergence on the density-advection exact solution
-  (section 4.1): the observed order rises towards 3 under refinement.
+  (section 4.1) on 16^2, 32^2 and 64^2 meshes: the observed L1 order
+  rises under refinement and exceeds 2.65 on the finest pair (2.55 and
+  2.74 measured; a scheme that loses its third-order terms falls to 2).
 * Linear stability of the boundary rules: the one-step Jacobian about a
   fluid at rest (finite differences of the whole step) has no growing mode
   in a closed slip-wall box, with fixed-state ends, or with transmissive
@@ -147,7 +149,7 @@ def test_noslip_at_rest_equals_slip_for_fluid_at_rest():
 def test_third_order_convergence():
     errs = []
     T = 0.05
-    for N in (8, 16, 32):
+    for N in (16, 32, 64):
         m = gi.jss_mesh(N, N, 2)
         W = gi.density_advection_ic(m)
         s = scheme.Solver(m, scheme.Params(eps=0.0))
@@ -158,8 +160,8 @@ def test_third_order_convergence():
         errs.append((e * s.geo.area).sum() / s.geo.area.sum())
     o1 = np.log2(errs[0] / errs[1])
     o2 = np.log2(errs[1] / errs[2])
-    assert o2 > o1 > 2.0
-    assert o2 > 2.45
+    assert o2 > o1 > 2.45
+    assert o2 > 2.65
 
 
 def _step_radius(m, rho, p):
