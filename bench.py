@@ -394,6 +394,9 @@ def main():
                          "500-step run (0: skip)")
     ap.add_argument("--no-limiter-leg", action="store_true",
                     help="skip the extra runs of the mixed form with the DWBAP limiter on")
+    ap.add_argument("--other-workloads", default="advection_512,cavity_256",
+                    help="also time both forms on these workloads (steps and warm-up as above, no event "
+                         "profile); empty to skip")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one MI355X only; multi-GPU runs are not part of this build "
@@ -441,6 +444,19 @@ def main():
             lim[name] = leg
             print("# mixed + limiter (%s variables): %.4g cell-steps/s, %.3f ms/step, %.0f cells limited per step" %
                   (name, rl["value"], rl["ms_per_step"], rl["limited_cells_per_step"]), file=sys.stderr, flush=True)
+    # the other workloads of the paper's test set (sections 4.1 and 4.7), both forms
+    others = {}
+    for name in [w.strip() for w in args.other_workloads.split(",") if w.strip() and w.strip() != args.workload]:
+        mo, Wo, desc_o, extra_o = workload(name)
+        leg = {"workload": desc_o, "cells": mo.nt}
+        for f in ("mixed", "fp64"):
+            prec = g.GKS_MIXED if f == "mixed" else g.GKS_FP64
+            ro = run_form(mo, Wo, prec, args.steps, args.warmup, False, args.graphs, extra=extra_o)
+            leg[f] = {k: ro[k] for k in ("value", "ms_per_step", "krylov_iters_per_step",
+                                         "gauss_point_fallbacks_per_step")}
+            print("# %s, %s: %.4g cell-steps/s, %.3f ms/step, %.1f Krylov iterations/step" %
+                  (name, f, ro["value"], ro["ms_per_step"], ro["krylov_iters_per_step"]), file=sys.stderr, flush=True)
+        others[name] = leg
     serving = serving_leg(args.serving_requests, args.serving_max_batch) if args.serving_requests > 0 else None
     if serving:
         print("# serving: %.4g cell-steps/s, step p50/p99 %.2f/%.2f ms, solve p50/p99 %.2f/%.2f ms" %
@@ -478,6 +494,7 @@ def main():
                        "serving_solve_p99": serving["solve_ms_p99"] if serving else None},
         "serving": serving,
         "limiter": lim,
+        "other_workloads": others or None,
         "device": torch.cuda.get_device_name(0),
     }
     print(json.dumps(out))
