@@ -19,6 +19,15 @@ SQ_INSTS_VALU_{FMA,ADD,MUL,TRANS}_F64 and SQ_INSTS_VALU: per kernel class,
 FP64 FLOPs per launch.  The FLOPS counter adds 2 per FMA and 1 per other
 FP64 instruction of a wave; times 64 lanes it gives the FLOPs of full
 waves (an upper bound where lanes are inactive).
+
+    python -m paper_1802_00704_amd.profiling --gathers
+
+prints, for the sweeps of the 1M-triangle shock-vortex mesh, the bytes of
+the neighbour rows that each level's launch must read from memory at least
+once: a sweep gathers the rows of its lower (forward) or upper (backward)
+neighbours, which other levels' launches produced, so every distinct
+neighbour row is one compulsory read per launch beside the launch's
+algorithmic bytes (host set-up only, no GPU).
 """
 from __future__ import annotations
 
@@ -134,7 +143,53 @@ def main_fp64(csv_dir: str) -> int:
     return 0
 
 
+def gathers(mesh, inner_iters: int = 5) -> dict:
+    """Distinct neighbour rows per level and the mean compulsory gather bytes
+    per launch of each sweep class, for the launch pattern of one
+    preconditioner application: split-form FP32 sweeps (80-byte rows; the
+    first sweep's forward pass covers every level, the later ones skip level
+    0; every sweep's backward pass covers all but the last level) and the
+    FP64 BILU(0) solve (160-byte rows; forward levels 1.., backward all but
+    the last)."""
+    import numpy as np
+    from ._lib import host_inspect
+    h = host_inspect(mesh)
+    lp, nt = h["lev_ptr"], h["nt"]
+    nl = len(lp) - 1
+    lo, up = [], []
+    for l in range(nl):
+        lc = h["lcol"][:, lp[l]:lp[l + 1]]
+        uc = h["ucol"][:, lp[l]:lp[l + 1]]
+        lo.append(int(np.unique(lc[lc < nt]).size))
+        up.append(int(np.unique(uc[uc < nt]).size))
+    fwd32 = [lo[l] for l in range(nl)] + [lo[l] for _ in range(inner_iters - 1) for l in range(1, nl)]
+    bwd32 = [up[l] for _ in range(inner_iters) for l in range(nl - 2, -1, -1)]
+    fwd64 = [lo[l] for l in range(1, nl)]
+    bwd64 = [up[l] for l in range(nl - 2, -1, -1)]
+    mean = lambda rows, b: b * float(np.mean(rows)) if rows else 0.0
+    return {"levels": [int(lp[l + 1] - lp[l]) for l in range(nl)], "lower_rows": lo, "upper_rows": up,
+            "ilu_fwd32": mean(fwd32, 80), "ilu_bwd32": mean(bwd32, 80),
+            "ilu_fwd": mean(fwd64, 160), "ilu_bwd": mean(bwd64, 160)}
+
+
+def main_gathers() -> int:
+    import gks_inputs as gi
+    left, _ = gi.shock_vortex_states()
+    walls = ((gi.BC_INFLOW, left), (gi.BC_OUTFLOW, None), (gi.BC_SLIP, None), (gi.BC_SLIP, None))
+    m = gi.jss_mesh(1000, 500, 3, Lx=2.0, Ly=1.0, periodic=False, walls=walls)
+    g = gathers(m)
+    print("levels (rows)          %s" % " ".join(str(r) for r in g["levels"]))
+    print("distinct lower rows    %s" % " ".join(str(r) for r in g["lower_rows"]))
+    print("distinct upper rows    %s" % " ".join(str(r) for r in g["upper_rows"]))
+    print("%-12s %22s" % ("class", "gather_B/launch"))
+    for cls in ("ilu_fwd32", "ilu_bwd32", "ilu_fwd", "ilu_bwd"):
+        print("%-12s %22.0f" % (cls, g[cls]))
+    return 0
+
+
 def main(argv):
+    if len(argv) == 2 and argv[1] == "--gathers":
+        return main_gathers()
     if len(argv) == 3 and argv[1] == "--fp64":
         return main_fp64(argv[2])
     if len(argv) != 3:
