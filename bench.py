@@ -190,10 +190,25 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t_start
     done = warmup + steps
+    # Kernel durations: the same number of steps again, right after the timed
+    # ones (so that they solve alike), with a HIP event pair around every
+    # launch on the library's stream (events add host latency between
+    # launches, so these steps are not part of the timed value).
+    prof, prof_elapsed = {}, 0.0
+    if profile:
+        gm.profile(True)
+        t_p = time.perf_counter()
+        for _ in range(steps):
+            gm.step(W)
+        torch.cuda.synchronize()
+        prof_elapsed = time.perf_counter() - t_p
+        prof = gm.profile_get()
+        gm.profile(False)
     # a second timed window late in the run (steps late_at + 1 .. late_at +
     # steps), where the flow has developed, after untimed steps up to it
     late = None
-    if late_at > done:
+    done += steps if profile else 0
+    if late_at >= done:
         for _ in range(late_at - done):
             gm.step(W)
         torch.cuda.synchronize()
@@ -208,19 +223,6 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         late = {"steps": "%d-%d" % (late_at + 1, late_at + steps), "value": m.nt * steps / el_l,
                 "ms_per_step": el_l * 1e3 / steps, "krylov_iters_per_step": float(np.mean(l_iters)),
                 "gauss_point_fallbacks_per_step": float(np.mean(l_np))}
-    # Kernel durations: the same number of steps again with a HIP event pair
-    # around every launch on the library's stream (events add host latency
-    # between launches, so these steps are not part of the timed value).
-    prof, prof_elapsed = {}, 0.0
-    if profile:
-        gm.profile(True)
-        t_p = time.perf_counter()
-        for _ in range(steps):
-            gm.step(W)
-        torch.cuda.synchronize()
-        prof_elapsed = time.perf_counter() - t_p
-        prof = gm.profile_get()
-        gm.profile(False)
     stats = gm.stats()
     gm.close()
     lat_ms = np.array(lat) * 1e3
