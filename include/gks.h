@@ -127,6 +127,13 @@ typedef struct {
                                 Eqs. ISD1-2 reaches 1, before the fluxes, in
                                 those variables; the solver keeps the
                                 unlimited X.  0: off                          */
+    double  reorth_tol;      /* Arnoldi orthogonalisation: classical Gram-
+                                Schmidt, with the second pass (CGS2) taken
+                                only when, for a column still iterating, the
+                                new vector w1 after the first pass has
+                                |V^T w1| > reorth_tol |w1|; 0 takes it at
+                                every step.  Each solve still ends on its true
+                                residual.  0 <= reorth_tol < 1; default 1e-8 */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -138,6 +145,8 @@ typedef struct {
     double  solve_ms;        /* host wall time of the reconstruction solve       */
     double  call_ms;         /* host wall time of the whole call                 */
     int32_t limited;         /* cells the limiter changed in this step            */
+    int32_t reorth;          /* Arnoldi steps that took the second Gram-Schmidt
+                                pass (see gks_params.reorth_tol)               */
 } gks_solve_info;
 
 /* Mesh statistics. */
@@ -158,7 +167,7 @@ typedef struct {
 
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
  * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
- * graph replay on. */
+ * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8. */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

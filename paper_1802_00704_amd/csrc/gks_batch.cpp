@@ -251,6 +251,7 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 in.solve_ms = solve_ms;
                 in.call_ms = call_ms;
                 in.limited = 0;
+                in.reorth = sl.st.reorths;
             }
         }
         return GKS_OK;

@@ -1153,7 +1153,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     ws.add(&w.t3, vec);
     w.nblk_red = std::max(1, std::min(1024, (n + 255) / 256));
     ws.add(&w.partial, (size_t)w.nblk_red * (MAXM + 1) * NC);
-    ws.add(&w.npart, (size_t)NC * (((size_t)n * 10 + 255) / 256 + 1));
+    ws.add(&w.npart, (size_t)NC * (((size_t)n * 10 + 255) / 256 + 5));   // blocks of k_axpy/k_axpy_dots
     ws.add(&w.dpart, (size_t)FUSED_DOTS_MAX * NC * (std::max<size_t>((n + 255) / 256, 2048) + 1));
     ws.add(&w.ks, 1);
     ws.add(&w.Xcell, (size_t)20 * nt);
@@ -1176,6 +1176,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
         w.scal_host = (double*)(hp + o_scal);
     }
     launch_set_scalar(m, &w.ks->tol, prm.tol);
+    launch_set_scalar(m, &w.ks->reorth_tol, prm.reorth_tol);
     // device address of the static limiter scratch (gks_limit_noalloc), looked
     // up once per device with this handle's device current
     m->scratch = scratch_device_ptr(&m->scratch_err);
@@ -1242,14 +1243,22 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
         else
             launch_spmv64(m, w.t2, nullptr, w.w, gate);
     }
+    // Classical Gram-Schmidt with a selective second pass (CGS2 where the
+    // first pass leaves the new vector measurably non-orthogonal, see the
+    // control kernel's mode 4): w1 = w - V h1 goes straight to slot k + 1
+    // with h2 = V^T w1 and |w1|^2; the second pass v_{k+1} = w1 - V h2 (in
+    // place, with its norm) runs only where the control kernel asks for it.
     if (fused) {
-        launch_axpy_dots(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, &ks->h2[0][0], gate);
+        launch_axpy_dots(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, vk1, &ks->h2[0][0], gate, ks->sq);
+        launch_ctl(m, 4);
+        launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], vk1, vk1, &ks->reorth, ks->sq);
     } else {
         launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0], gate);
         launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, gate);
         launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0], gate);
+        launch_ctl(m, 5);
+        launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, &ks->reorth, ks->sq);
     }
-    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, gate, ks->sq);
     launch_ctl(m, 2);
 }
 
@@ -1280,6 +1289,7 @@ void fill_info(gks_mesh* m, gks_solve_info* info) {
         info->restarts[c] = st->cycles;
         info->rel_resid[c] = st->bnorm[c] > 0.0 ? st->beta[c] / st->bnorm[c] : 0.0;
     }
+    info->reorth = st->reorths;
 }
 
 enum { RESUME_NONE = 0, RESUME_CYCLE_START = 1, RESUME_IN_CYCLE = 2 };
@@ -1488,7 +1498,8 @@ bool params_ok(const gks_params& p) {
            p.max_iter >= 1 && p.mu >= 0.0 && p.tau_eps >= 0.0 && p.cls_w > 0.0 &&
            (p.precision == GKS_FP64 || p.precision == GKS_MIXED) &&
            (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
-           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC);
+           (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC) &&
+           p.reorth_tol >= 0.0 && p.reorth_tol < 1.0;
 }
 
 int fail(gks_mesh* m, const Fail& f) {
@@ -1522,6 +1533,7 @@ void gks_params_default(gks_params* p) {
     p->graphs = 1;
     p->graph_budget = 0;
     p->limiter = 0;
+    p->reorth_tol = REORTH_TOL_DEFAULT;
 }
 
 int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_stream, gks_mesh** out) {

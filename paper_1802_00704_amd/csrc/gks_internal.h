@@ -61,7 +61,11 @@ struct Status {
     int32_t conv[NC];             // 1 once the estimate meets tol
     int32_t active[NC];           // 0 for a zero right-hand side
     int32_t its[NC];              // steps column c took part in before it converged
+    int32_t reorths;              // Arnoldi steps of this solve that took the second Gram-Schmidt pass
 };
+
+// default of gks_params.reorth_tol
+constexpr double REORTH_TOL_DEFAULT = 1e-8;
 
 struct KrylovState {
     Status st;
@@ -74,6 +78,8 @@ struct KrylovState {
     double g[MAXM + 1][NC];
     double y[MAXM][NC];
     double sq[NC];                // squared norms handed to the control kernel
+    double reorth_tol;            // second Gram-Schmidt pass when |V^T w1| > reorth_tol |w1| (0: always)
+    int32_t reorth;               // 1: the current Arnoldi step takes the second pass (gates it)
 };
 
 // Sliced storage of the BILU(0) factors (see the sweep kernels): per slice
@@ -232,14 +238,16 @@ void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const 
                  const double* w, double* out, const int32_t* gate = nullptr, double* sq_out = nullptr);
 // Fused Gram-Schmidt passes for nvec <= FUSED_DOTS_MAX basis vectors:
 // y = K x together with out = scale .* (V^T y), and the update out = w - V h
-// together with dots_out = scale .* (V^T out).
+// together with dots_out = scale .* (V^T out) and, with sq_out, the
+// per-column squared norms of out.
 constexpr int FUSED_DOTS_MAX = 8;
 void launch_spmv64_dots(gks_mesh* m, const double* x, double* y, const double* V, int64_t vstride, int nvd,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 void launch_spmv64_f32x_dots(gks_mesh* m, const float* x, double* y, const double* V, int64_t vstride, int nvd,
                              const double* scale, double* out, const int32_t* gate = nullptr);
 void launch_axpy_dots(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                      const double* w, double* out, double* dots_out, const int32_t* gate = nullptr);
+                      const double* w, double* out, double* dots_out, const int32_t* gate = nullptr,
+                      double* sq_out = nullptr);
 // nvec_dev: when non-null the number of vectors is min(nvec, *nvec_dev)
 void launch_combine(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* y, const double* scale,
                     double* out, const int32_t* nvec_dev = nullptr, const int32_t* gate = nullptr);

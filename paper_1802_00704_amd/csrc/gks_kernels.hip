@@ -31,6 +31,8 @@ static inline int nblocks(int64_t n, int tpb = TPB) { return (int)((n + tpb - 1)
 // CU, a multiple of 5 (k_axpy_dots needs a grid of a multiple of 10 threads)
 // and of the 8 XCDs
 constexpr int AXPY_BLOCKS = 2040;
+// blocks of k_axpy_dots for n rows: a multiple of 5, at most AXPY_BLOCKS
+static inline int axpy_dots_blocks(int n) { return (std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10)) + 4) / 5 * 5; }
 
 // The hardware hands consecutive workgroups of a grid to the 8 XCDs in turn,
 // and each XCD has its own L2.  Row kernels gather neighbour blocks, so they
@@ -556,10 +558,12 @@ __global__ void __launch_bounds__(TPB) kg_spmv_dots(Group<SpmvDotsArgs<XT>> g) {
 // to dpart).  Grid-stride over 16-byte groups (pair p of a 20-double row);
 // the launch makes the grid a multiple of 10 threads, so each thread keeps
 // one pair position, hence fixed columns c0, c1 and fixed coefficients.
-// out may alias w.
+// out may alias w.  With sqpart != NULL the block also writes the
+// per-column sums of out^2 (the norms that decide the second pass).
 template <class GRID>
-__device__ __forceinline__ void axpy_dots_body(GRID grid, int n, const double* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ h, const double* __restrict__ scale, const double* w, double* out, double* __restrict__ dpart, const int32_t* __restrict__ gate) {
+__device__ __forceinline__ void axpy_dots_body(GRID grid, int n, const double* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ h, const double* __restrict__ scale, const double* w, double* out, double* __restrict__ dpart, const int32_t* __restrict__ gate, double* __restrict__ sqpart) {
     if (gate && *gate == 0) return;
+    double sq[NC] = {0.0, 0.0, 0.0, 0.0};
     const int64_t npair = (int64_t)n * 10;
     const int64_t t0 = (int64_t)grid.b() * blockDim.x + threadIdx.x;
     const int p = (int)(t0 % 10);
@@ -596,6 +600,10 @@ __device__ __forceinline__ void axpy_dots_body(GRID grid, int n, const double* _
                 d1[j] += vv[j].y * a1;
             }
         }
+        if (sqpart) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) sq[c] += (c == c0 ? a0 * a0 : 0.0) + (c == c1 ? a1 * a1 : 0.0);
+        }
     }
     double d[RED_CHUNK][NC];
 #pragma unroll
@@ -603,13 +611,14 @@ __device__ __forceinline__ void axpy_dots_body(GRID grid, int n, const double* _
 #pragma unroll
         for (int c = 0; c < NC; ++c) d[j][c] = (c == c0 ? d0[j] : 0.0) + (c == c1 ? d1[j] : 0.0);
     block_dots(d, nvec, dpart, grid);
+    if (sqpart) block_sumsq4(sq, sqpart, grid);
 }
 
 __global__ void __launch_bounds__(TPB) k_axpy_dots(int n, const double* __restrict__ V, int64_t vstride, int nvec,
                                                    const double* __restrict__ h, const double* __restrict__ scale,
                                                    const double* w, double* out, double* __restrict__ dpart,
-                                                   const int32_t* __restrict__ gate) {
-    axpy_dots_body(Grid1(), n, V, vstride, nvec, h, scale, w, out, dpart, gate);
+                                                   const int32_t* __restrict__ gate, double* __restrict__ sqpart) {
+    axpy_dots_body(Grid1(), n, V, vstride, nvec, h, scale, w, out, dpart, gate, sqpart);
 }
 
 struct AxpyDotsArgs {
@@ -623,6 +632,7 @@ struct AxpyDotsArgs {
     double* out;
     double* dpart;
     const int32_t* gate;
+    double* sqpart;
 };
 
 __global__ void __launch_bounds__(TPB) kg_axpy_dots(Group<AxpyDotsArgs> g) {
@@ -630,7 +640,7 @@ __global__ void __launch_bounds__(TPB) kg_axpy_dots(Group<AxpyDotsArgs> g) {
     const int r = group_locate(g, v);
     if (r < 0) return;
     const AxpyDotsArgs& a = g.a[r];
-    axpy_dots_body(v, a.n, a.V, a.vstride, a.nvec, a.h, a.scale, a.w, a.out, a.dpart, a.gate);
+    axpy_dots_body(v, a.n, a.V, a.vstride, a.nvec, a.h, a.scale, a.w, a.out, a.dpart, a.gate, a.sqpart);
 }
 
 
@@ -1509,6 +1519,36 @@ __global__ void __launch_bounds__(TPB) kg_sum_partials(Group<SumArgs> g) {
 // mode 3 (SOLVE):   y = R^{-1} g over the first k columns
 template <class GRID>
 __device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState* __restrict__ ks, int mres, int gated) {
+    if (mode >= 4) {
+        // Whether the second Gram-Schmidt pass runs (ks->reorth gates it).
+        // Mode 5 forces it.  Mode 4 asks for it when, for a column still
+        // iterating, the first pass left the new vector w1 measurably
+        // non-orthogonal to the basis: |V^T w1| > reorth_tol |w1| (the
+        // second products h2 and the squared norm sq of w1 are in place).
+        // reorth_tol = 0 always takes the second pass (CGS2).
+        __shared__ int need[NC];
+        const int c = threadIdx.x;
+        const int run = ks->st.run;
+        if (c < NC) {
+            int nd = 1;
+            if (mode == 4 && ks->reorth_tol > 0.0) {
+                double hh = 0.0;
+                for (int j = 0; j <= ks->st.k; ++j) hh += ks->h2[j][c] * ks->h2[j][c];
+                const double t = ks->reorth_tol;
+                nd = ks->st.active[c] && !ks->st.conv[c] && hh > t * t * ks->sq[c];
+            }
+            need[c] = nd;
+        }
+        __syncthreads();
+        if (c == 0) {
+            int any = 0;
+            for (int q = 0; q < NC; ++q) any |= need[q];
+            const int r = run && any;
+            ks->reorth = r;
+            ks->st.reorths += r;
+        }
+        return;
+    }
     if (mode == 2 && ks->st.run == 0) return;   // the cycle has ended
     if (gated && ks->st.fin == 0) return;        // end-of-cycle work while the cycle still runs
     const int c = threadIdx.x;
@@ -1532,8 +1572,10 @@ __device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState*
             st.est[c] = bn > 0.0 ? b / bn : 0.0;
             st.conv[c] = (!st.active[c]) || b <= ks->tol * bn;
         } else if (mode == 2) {
+            // column of H: the products of the passes that ran
             double col[MAXM + 1];
-            for (int j = 0; j <= k; ++j) col[j] = ks->h1[j][c] + ks->h2[j][c];
+            const int two = ks->reorth;
+            for (int j = 0; j <= k; ++j) col[j] = two ? ks->h1[j][c] + ks->h2[j][c] : ks->h1[j][c];
             const double hn = sqrt(ks->sq[c]);
             col[k + 1] = hn;
             ks->scale[k + 1][c] = hn > 0.0 ? 1.0 / hn : 0.0;
@@ -1577,6 +1619,7 @@ __device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState*
         if (mode == 0) {
             ks->st.total = 0;
             ks->st.cycles = 0;
+            ks->st.reorths = 0;
         }
         if (mode == 1) {
             ks->st.k = 0;
@@ -2514,14 +2557,18 @@ void launch_spmv64_f32x_dots(gks_mesh* m, const float* x, double* y, const doubl
 }
 
 void launch_axpy_dots(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                      const double* w, double* out, double* dots_out, const int32_t* gate) {
+                      const double* w, double* out, double* dots_out, const int32_t* gate, double* sq_out) {
     const int n = m->d.n;
     // a multiple of 5 blocks of 256 threads: the grid is a multiple of 10 threads
-    const int nb = (std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10)) + 4) / 5 * 5;
+    const int nb = axpy_dots_blocks(n);
+    double* part = sq_out ? m->w.npart : nullptr;
     PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy_dots, dim3(nb), dim3(TPB), 0, m->stream, n, V, vstride,
-                                                                   nvec, h, scale, w, out, m->w.dpart, gate));
+                                                                   nvec, h, scale, w, out, m->w.dpart, gate, part));
     PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(nvec * NC), dim3(TPB), 0, m->stream, nvec * NC, nb, m->w.dpart,
                                       scale, dots_out, gate));
+    if (sq_out)
+        PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(NC), dim3(TPB), 0, m->stream, NC, nb, part, nullptr, sq_out,
+                                          gate));
 }
 
 void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, const int32_t* gate, double* sq_out) {
@@ -3289,20 +3336,23 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
             glaunch(st, kg_spmv_dots<double>, TPB, it, KC_SPMV);
         }
         gsum(st, sa);
-        // out = w - V h1 with the second products
+        // w1 = w - V h1 into the basis slot k + 1, with the second products
+        // and the norms of w1, then whether the second pass runs
         std::vector<std::pair<AxpyDotsArgs, int>> ad;
         sa.clear();
         for (gks_mesh* m : ms) {
             const int n = m->d.n;
             const int64_t vs = (int64_t)(n + 1) * CB;
-            const int nb = (std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10)) + 4) / 5 * 5;
-            ad.push_back({AxpyDotsArgs{n, m->w.V, vs, k + 1, &m->w.ks->h1[0][0], &m->w.ks->scale[0][0], m->w.w, m->w.w,
-                                       m->w.dpart, nullptr},
+            const int nb = axpy_dots_blocks(n);
+            ad.push_back({AxpyDotsArgs{n, m->w.V, vs, k + 1, &m->w.ks->h1[0][0], &m->w.ks->scale[0][0], m->w.w,
+                                       m->w.V + (int64_t)(k + 1) * vs, m->w.dpart, nullptr, m->w.npart},
                           nb});
             sa.push_back(SumArgs{(k + 1) * NC, nb, m->w.dpart, &m->w.ks->scale[0][0], &m->w.ks->h2[0][0], nullptr});
+            sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, nullptr});
         }
         glaunch(st, kg_axpy_dots, TPB, ad, KC_AXPY_DOTS);
         gsum(st, sa);
+        glaunch_ctl(st, ms, 4);
     } else {
         // y = K M^-1 v_k
         if (mixed) {
@@ -3347,18 +3397,22 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
                 glaunch(st, kg_axpy, TPB, ax, KC_AXPY_DOTS);
             }
         }
+        // unfused passes: the second pass always runs, from w into slot k + 1
+        glaunch_ctl(st, ms, 5);
     }
-    // v_{k+1} = w - V h2 with its norm, then the control step
+    // the second pass where ks->reorth asks for it: v_{k+1} = w1 - V h2
+    // with its norm (fused: in place in slot k + 1), then the control step
     std::vector<std::pair<AxpyArgs, int>> ax;
     sa.clear();
     for (gks_mesh* m : ms) {
         const int n = m->d.n;
         const int64_t vs = (int64_t)(n + 1) * CB;
         const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));
-        ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h2[0][0], &m->w.ks->scale[0][0], m->w.w,
-                               m->w.V + (int64_t)(k + 1) * vs, nullptr, m->w.npart},
+        double* vk1 = m->w.V + (int64_t)(k + 1) * vs;
+        ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h2[0][0], &m->w.ks->scale[0][0], fused ? vk1 : m->w.w,
+                               vk1, &m->w.ks->reorth, m->w.npart},
                       nb});
-        sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, nullptr});
+        sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, &m->w.ks->reorth});
     }
     glaunch(st, kg_axpy, TPB, ax, KC_AXPY_DOTS);
     gsum(st, sa);
