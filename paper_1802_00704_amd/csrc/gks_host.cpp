@@ -1246,19 +1246,18 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
     // Classical Gram-Schmidt with a selective second pass (CGS2 where the
     // first pass leaves the new vector measurably non-orthogonal, see the
     // control kernel's mode 4): w1 = w - V h1 goes straight to slot k + 1
-    // with h2 = V^T w1 and |w1|^2; the second pass v_{k+1} = w1 - V h2 (in
-    // place, with its norm) runs only where the control kernel asks for it.
+    // with h2 = V^T w1 and |w1|^2 (one fused pass while the basis is short,
+    // separate ones beyond); the second pass v_{k+1} = w1 - V h2 (in place,
+    // with its norm) runs only where the control kernel asks for it.
     if (fused) {
         launch_axpy_dots(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, vk1, &ks->h2[0][0], gate, ks->sq);
-        launch_ctl(m, 4);
-        launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], vk1, vk1, &ks->reorth, ks->sq);
     } else {
         launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h1[0][0], gate);
-        launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, w.w, gate);
-        launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, w.w, &ks->scale[0][0], &ks->h2[0][0], gate);
-        launch_ctl(m, 5);
-        launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], w.w, vk1, &ks->reorth, ks->sq);
+        launch_axpy(m, w.V, vs, k + 1, &ks->h1[0][0], &ks->scale[0][0], w.w, vk1, gate, ks->sq);
+        launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, vk1, &ks->scale[0][0], &ks->h2[0][0], gate);
     }
+    launch_ctl(m, 4);
+    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], vk1, vk1, &ks->reorth, ks->sq);
     launch_ctl(m, 2);
 }
 

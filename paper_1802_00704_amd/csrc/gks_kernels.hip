@@ -1519,19 +1519,18 @@ __global__ void __launch_bounds__(TPB) kg_sum_partials(Group<SumArgs> g) {
 // mode 3 (SOLVE):   y = R^{-1} g over the first k columns
 template <class GRID>
 __device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState* __restrict__ ks, int mres, int gated) {
-    if (mode >= 4) {
-        // Whether the second Gram-Schmidt pass runs (ks->reorth gates it).
-        // Mode 5 forces it.  Mode 4 asks for it when, for a column still
-        // iterating, the first pass left the new vector w1 measurably
-        // non-orthogonal to the basis: |V^T w1| > reorth_tol |w1| (the
-        // second products h2 and the squared norm sq of w1 are in place).
-        // reorth_tol = 0 always takes the second pass (CGS2).
+    if (mode == 4) {
+        // Whether the second Gram-Schmidt pass runs (ks->reorth gates it):
+        // it does when, for a column still iterating, the first pass left
+        // the new vector w1 measurably non-orthogonal to the basis,
+        // |V^T w1| > reorth_tol |w1| (the second products h2 and the squared
+        // norm sq of w1 are in place).  reorth_tol = 0 always takes it (CGS2).
         __shared__ int need[NC];
         const int c = threadIdx.x;
         const int run = ks->st.run;
         if (c < NC) {
             int nd = 1;
-            if (mode == 4 && ks->reorth_tol > 0.0) {
+            if (ks->reorth_tol > 0.0) {
                 double hh = 0.0;
                 for (int j = 0; j <= ks->st.k; ++j) hh += ks->h2[j][c] * ks->h2[j][c];
                 const double t = ks->reorth_tol;
@@ -3352,7 +3351,6 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
         }
         glaunch(st, kg_axpy_dots, TPB, ad, KC_AXPY_DOTS);
         gsum(st, sa);
-        glaunch_ctl(st, ms, 4);
     } else {
         // y = K M^-1 v_k
         if (mixed) {
@@ -3372,14 +3370,16 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
                               nblocks(m->d.n)});
             glaunch(st, kg_spmv<double, double, false>, TPB, it, KC_SPMV);
         }
-        // h1 = V^T w, w -= V h1, h2 = V^T w (unfused passes, as launch_dots_reduce / launch_axpy)
+        // h1 = V^T w, w1 = w - V h1 into slot k + 1 with its norms, h2 = V^T w1
+        // (unfused passes, as launch_dots_reduce / launch_axpy)
         const int nch = (k + 1 + RED_CHUNK - 1) / RED_CHUNK;
         for (int pass = 0; pass < 2; ++pass) {
             std::vector<std::pair<DotsArgs, int>> dt;
             sa.clear();
             for (gks_mesh* m : ms) {
                 const int64_t vs = (int64_t)(m->d.n + 1) * CB;
-                dt.push_back({DotsArgs{m->d.n, m->w.V, vs, k + 1, m->w.w, m->w.partial, nullptr}, m->w.nblk_red});
+                const double* x = pass == 0 ? m->w.w : m->w.V + (int64_t)(k + 1) * vs;
+                dt.push_back({DotsArgs{m->d.n, m->w.V, vs, k + 1, x, m->w.partial, nullptr}, m->w.nblk_red});
                 sa.push_back(SumArgs{(k + 1) * NC, m->w.nblk_red, m->w.partial, &m->w.ks->scale[0][0],
                                      pass == 0 ? &m->w.ks->h1[0][0] : &m->w.ks->h2[0][0], nullptr});
             }
@@ -3387,21 +3387,24 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
             gsum(st, sa);
             if (pass == 0) {
                 std::vector<std::pair<AxpyArgs, int>> ax;
+                sa.clear();
                 for (gks_mesh* m : ms) {
                     const int n = m->d.n;
                     const int64_t vs = (int64_t)(n + 1) * CB;
+                    const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));
                     ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h1[0][0], &m->w.ks->scale[0][0], m->w.w,
-                                           m->w.w, nullptr, nullptr},
-                                  std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10))});
+                                           m->w.V + (int64_t)(k + 1) * vs, nullptr, m->w.npart},
+                                  nb});
+                    sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, nullptr});
                 }
                 glaunch(st, kg_axpy, TPB, ax, KC_AXPY_DOTS);
+                gsum(st, sa);
             }
         }
-        // unfused passes: the second pass always runs, from w into slot k + 1
-        glaunch_ctl(st, ms, 5);
     }
+    glaunch_ctl(st, ms, 4);
     // the second pass where ks->reorth asks for it: v_{k+1} = w1 - V h2
-    // with its norm (fused: in place in slot k + 1), then the control step
+    // in place in slot k + 1 with its norm, then the control step
     std::vector<std::pair<AxpyArgs, int>> ax;
     sa.clear();
     for (gks_mesh* m : ms) {
@@ -3409,7 +3412,7 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
         const int64_t vs = (int64_t)(n + 1) * CB;
         const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));
         double* vk1 = m->w.V + (int64_t)(k + 1) * vs;
-        ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h2[0][0], &m->w.ks->scale[0][0], fused ? vk1 : m->w.w,
+        ax.push_back({AxpyArgs{n, m->w.V, vs, k + 1, &m->w.ks->h2[0][0], &m->w.ks->scale[0][0], vk1,
                                vk1, &m->w.ks->reorth, m->w.npart},
                       nb});
         sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, &m->w.ks->reorth});
