@@ -1257,7 +1257,7 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
         launch_dots_reduce(m, KC_DOTS, w.V, vs, k + 1, vk1, &ks->scale[0][0], &ks->h2[0][0], gate);
     }
     launch_ctl(m, 4);
-    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], vk1, vk1, &ks->reorth, ks->sq);
+    launch_axpy(m, w.V, vs, k + 1, &ks->h2[0][0], &ks->scale[0][0], vk1, vk1, &ks->reorth, ks->sq, true);
     launch_ctl(m, 2);
 }
 

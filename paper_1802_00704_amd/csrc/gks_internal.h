@@ -212,7 +212,7 @@ struct LaunchError {
 
 // kernel classes for profiling
 enum Kc {
-    KC_RHS = 0, KC_SPMV, KC_SPMV_RES, KC_ILU_FWD, KC_ILU_BWD, KC_DOTS, KC_AXPY_DOTS, KC_AXPY_NORM,
+    KC_RHS = 0, KC_SPMV, KC_SPMV_RES, KC_ILU_FWD, KC_ILU_BWD, KC_DOTS, KC_AXPY_DOTS, KC_REORTH,
     KC_FINAL, KC_COMBINE, KC_AXPY, KC_COPYOUT, KC_FLUX, KC_UPDATE, KC_CFL, KC_MISC,
     KC_SPMV32, KC_ILU_FWD32, KC_ILU_BWD32, KC_EXTRAP, KC_LIMIT, KC_LIMIT_APPLY, KC_COUNT
 };
@@ -234,8 +234,10 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
 void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate = nullptr);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
+// second_pass: the gated second Gram-Schmidt pass (profiler class "reorth")
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                 const double* w, double* out, const int32_t* gate = nullptr, double* sq_out = nullptr);
+                 const double* w, double* out, const int32_t* gate = nullptr, double* sq_out = nullptr,
+                 bool second_pass = false);
 // Fused Gram-Schmidt passes for nvec <= FUSED_DOTS_MAX basis vectors:
 // y = K x together with out = scale .* (V^T y), and the update out = w - V h
 // together with dots_out = scale .* (V^T out) and, with sq_out, the

@@ -19,7 +19,7 @@
 namespace gks {
 
 const char* kc_names[NPROF] = {"rhs",       "spmv",       "spmv_resid", "ilu_fwd",  "ilu_bwd",
-                               "dots",      "axpy_dots",  "axpy_norm",  "finalize", "combine",
+                               "dots",      "axpy_dots",  "reorth",     "finalize", "combine",
                                "axpy",      "copyout",    "flux",       "update",   "cfl",
                                "misc",      "spmv32",     "ilu_fwd32",  "ilu_bwd32", "extrap", "limit", "limit_apply", "", ""};
 
@@ -220,14 +220,15 @@ __device__ __forceinline__ void rhs_body(GRID grid, int nt, const int32_t* __res
                 for (int l = 0; l < NB; ++l) acc[c][l] += a[l] * d;
             }
         }
-        double* out = R + (int64_t)iperm[oi] * CB;
+        // the row is 160 contiguous bytes at a 16-byte boundary: ten 16-byte stores
+        double2* out = reinterpret_cast<double2*>(R + (int64_t)iperm[oi] * CB);
+        const double* flat = &acc[0][0];
+#pragma unroll
+        for (int q = 0; q < CB / 2; ++q) out[q] = make_double2(flat[2 * q], flat[2 * q + 1]);
 #pragma unroll
         for (int c = 0; c < NC; ++c)
 #pragma unroll
-            for (int l = 0; l < NB; ++l) {
-                out[c * NB + l] = acc[c][l];
-                sq[c] += acc[c][l] * acc[c][l];
-            }
+            for (int l = 0; l < NB; ++l) sq[c] += acc[c][l] * acc[c][l];
     }
     if (partial) block_sumsq4(sq, partial, grid);
 }
@@ -2749,12 +2750,14 @@ void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, i
 }
 
 void launch_axpy(gks_mesh* m, const double* V, int64_t vstride, int nvec, const double* h, const double* scale,
-                 const double* w, double* out, const int32_t* gate, double* sq_out) {
+                 const double* w, double* out, const int32_t* gate, double* sq_out, bool second_pass) {
     const int n = m->d.n;
     const int nb = std::min(AXPY_BLOCKS, nblocks((int64_t)n * 10));   // grid-stride beyond
     double* part = sq_out ? m->w.npart : nullptr;
-    PROFB(KC_AXPY_DOTS, (double)n * (nvec + 2) * VB, hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(TPB), 0, m->stream, n, V, vstride, nvec,
-                                          h, scale, w, out, gate, part));
+    // The second Gram-Schmidt pass is gated on the device (ks->reorth), so
+    // whether it moves its bytes is unknown here: its own class, no bytes.
+    PROFB(second_pass ? KC_REORTH : KC_AXPY_DOTS, second_pass ? 0.0 : (double)n * (nvec + 2) * VB,
+          hipLaunchKernelGGL(k_axpy, dim3(nb), dim3(TPB), 0, m->stream, n, V, vstride, nvec, h, scale, w, out, gate, part));
     if (sq_out)
         PROF(KC_FINAL, hipLaunchKernelGGL(k_sum_partials, dim3(NC), dim3(TPB), 0, m->stream, NC, nb, part, nullptr, sq_out,
                                           gate));
@@ -3417,7 +3420,7 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
                       nb});
         sa.push_back(SumArgs{NC, nb, m->w.npart, nullptr, m->w.ks->sq, &m->w.ks->reorth});
     }
-    glaunch(st, kg_axpy, TPB, ax, KC_AXPY_DOTS);
+    glaunch(st, kg_axpy, TPB, ax, KC_REORTH);
     gsum(st, sa);
     glaunch_ctl(st, ms, 2);
 }
