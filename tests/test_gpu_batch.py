@@ -10,6 +10,7 @@ iteration counts bitwise:
   * requests joining and leaving the batch between steps (continuous
     batching), including a request joining with no history;
   * more requests than one grouped launch holds (split launches);
+  * solves longer than the fused Gram-Schmidt passes hold, with restarts;
   * one request failing (a step far beyond the CFL limit with the fallback
     off: GKS_ENONPHYS, its W unchanged) beside requests that succeed;
   * argument errors: mixed precisions, a handle twice, a mixed-form handle
@@ -134,6 +135,51 @@ def test_more_requests_than_one_launch_holds():
             assert np.array_equal(Ws[r].cpu().numpy(), ref[r][k][0])
     b.close()
     for h in hs:
+        h.close()
+
+
+def cav(n=24, seed=4):
+    walls = ((gi.BC_NOSLIP, (0.0, 0.0, 0.0, 0.0)),) * 3 + ((gi.BC_NOSLIP, (0.0, 1.0, 0.0, 0.0)),)
+    m = gi.jss_mesh(n, n, seed, Lx=1.0, Ly=1.0, periodic=False, stretch=1.5, walls=walls)
+    return m, gi.cavity_ic(m)
+
+
+@pytest.mark.parametrize("precision", [g.GKS_FP64, g.GKS_MIXED])
+def test_long_solves_and_restarts_in_a_batch(precision):
+    """Viscous cavity meshes (section 4.7) whose FP64 solves take more Arnoldi
+    steps than the fused Gram-Schmidt passes hold (8) and, with restart 12,
+    several cycles: batch and alone bitwise equal, with the second pass
+    taken selectively on both paths."""
+    cases = [lambda: cav(24), lambda: cav(16, 9), lambda: adv(10)]
+    kw = dict(mu=1e-3, restart=12, tol=1e-12)
+
+    def mk(c):
+        m, W0 = c()
+        return g.GksMesh(m, precision=precision, nonphys_fallback=1, graphs=0, **kw), dev(W0)
+
+    ref = []
+    for c in cases:
+        h, W = mk(c)
+        out = []
+        for _ in range(3):
+            dt, info = h.step(W)
+            out.append((W.cpu().numpy().copy(), dt, info["iters"], info["restarts"], info["reorth"]))
+        h.close()
+        ref.append(out)
+    if precision == g.GKS_FP64:
+        assert max(max(r[2]) for r in ref[0]) > 12 and max(max(r[3]) for r in ref[0]) >= 2
+    pairs = [mk(c) for c in cases]
+    b = g.GksBatch()
+    for k in range(3):
+        res = b.step([p[0] for p in pairs], [p[1] for p in pairs])
+        for r, (code, dt, info) in enumerate(res):
+            assert code == 0
+            Wr, dtr, itr, rsr, ror = ref[r][k]
+            print("request", r, "step", k, "iters", itr, "restarts", rsr, "second passes", ror, flush=True)
+            assert dt == dtr and info["iters"] == itr and info["restarts"] == rsr and info["reorth"] == ror
+            assert np.array_equal(pairs[r][1].cpu().numpy(), Wr), (r, k)
+    b.close()
+    for h, _ in pairs:
         h.close()
 
 
