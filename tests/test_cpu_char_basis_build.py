@@ -26,9 +26,9 @@ def exe():
     if not os.path.exists(EXE) or os.path.getmtime(EXE) < max(os.path.getmtime(SRC), os.path.getmtime(dep)):
         san = "-fsanitize=" + "address,undefined"
         cmd = [CLANG, "-x", "c++", "-std=c++17", "-O1", "-g", "-D__HIP_PLATFORM_AMD__", "-I/opt/rocm/include",
-               san, "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", SRC, "-o", EXE + ".tmp"]
+               san, "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", SRC, "-o", EXE + ".tmp%d" % os.getpid()]
         subprocess.run(cmd, check=True)
-        shutil.move(EXE + ".tmp", EXE)
+        shutil.move(EXE + ".tmp%d" % os.getpid(), EXE)
     return EXE
 
 
