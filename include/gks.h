@@ -65,6 +65,11 @@ extern "C" {
 #define GKS_BC_INFLOW  3  /* fixed state (rho, u, v, p) = bc_state[row][0..3], no slopes */
 #define GKS_BC_OUTFLOW 4  /* transmissive: ghost = the boundary cell's average, no slopes */
 
+/* inner solver of the mixed form (gks_params.inner_solver) */
+#define GKS_INNER_RICHARDSON 0  /* inner_iters BILU(0)-preconditioned Richardson sweeps  */
+#define GKS_INNER_GMRES      1  /* inner_iters steps of GMRES, right-preconditioned by one
+                                   FP32 BILU(0) application, FP64 Arnoldi and matrix     */
+
 /* variables the limiter acts on (gks_params.limiter, gks_limit) */
 #define GKS_LIMIT_CONSERVATIVE   1
 #define GKS_LIMIT_CHARACTERISTIC 2
@@ -103,8 +108,8 @@ typedef struct {
     int32_t max_iter;        /* cap on Krylov iterations per solve (500)         */
     int32_t precision;       /* GKS_FP64 or GKS_MIXED                            */
     int32_t ordering;        /* GKS_ORDER_MULTICOLOR or GKS_ORDER_RCM            */
-    int32_t inner_iters;     /* GKS_MIXED: FP32 preconditioned sweeps per outer
-                                iteration (5)                                   */
+    int32_t inner_iters;     /* GKS_MIXED: FP32 preconditioned sweeps (or inner
+                                GMRES steps) per outer iteration (5)            */
     int32_t exact_time;      /* 0: time coefficients c_1..c_8 of Eq.
                                 Nomenclature2 as printed; 1: exact integrals     */
     int32_t nonphys_fallback;/* 0: non-physical Gauss-point state -> GKS_ENONPHYS;
@@ -134,6 +139,10 @@ typedef struct {
                                 |V^T w1| > reorth_tol |w1|; 0 takes it at
                                 every step.  Each solve still ends on its true
                                 residual.  0 <= reorth_tol < 1; default 1e-8 */
+    int32_t inner_solver;    /* GKS_MIXED: the preconditioner of each outer
+                                step, GKS_INNER_RICHARDSON (default) or
+                                GKS_INNER_GMRES (then 1 <= inner_iters <= 8;
+                                not with gks_batch_step)                      */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -270,7 +279,8 @@ int gks_limit_noalloc(gks_mesh* m, const double* W, const double* X, double* Xou
  * one backward block substitution in FP64), or the inner iteration of the
  * mixed form (form GKS_MIXED, handle created with precision GKS_MIXED:
  * inner_iters Richardson sweeps z += M^-1 (v - K z) from z = 0 with the FP32
- * matrix and factors).  V and Z are device arrays [4][5][nt] in the caller's
+ * matrix and factors, or with inner_solver GKS_INNER_GMRES inner_iters GMRES
+ * steps on K z = v, each column of V of unit norm).  V and Z are device arrays [4][5][nt] in the caller's
  * cell order (the layout of X), not aliased.  Uses the handle's work space;
  * for inspection and tests of the factor storage.
  * Errors: GKS_EINVAL, GKS_EHIP. */
@@ -334,7 +344,8 @@ int gks_batch_create(void* hip_stream, gks_batch** out);
 
 /* One step of each of the n handles meshes[0..n-1] (distinct, created on the
  * batch's device, all GKS_FP64 or all GKS_MIXED; mixed handles need the
- * split-form sweeps, see gks_mesh_stats.split_form; no limiter), with device
+ * split-form sweeps, see gks_mesh_stats.split_form, and the Richardson inner
+ * solver; no limiter), with device
  * states W[r] ([4][nt_r], updated in place on success, as gks_step).
  * dt: host [n] time steps, entries <= 0 (or dt = NULL) take the CFL rule.
  * dt_used (host [n], may be NULL) receives the steps taken; info (host [n],

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(HERE, "libgks.so")
 GKS_OK, GKS_EINVAL, GKS_ENOMEM, GKS_EHIP, GKS_ENOCONV, GKS_ENONPHYS = 0, -1, -2, -3, -4, -5
 LIMIT_CONSERVATIVE, LIMIT_CHARACTERISTIC = 1, 2
 GKS_FP64, GKS_MIXED = 0, 1
+GKS_INNER_RICHARDSON, GKS_INNER_GMRES = 0, 1
 GKS_ORDER_MULTICOLOR, GKS_ORDER_RCM = 0, 1
 
 EXPORTS = ("gks_params_default", "gks_mesh_create", "gks_cls_reconstruct", "gks_flux", "gks_step",
@@ -53,7 +54,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("ordering", C.c_int32), ("inner_iters", C.c_int32),
                 ("exact_time", C.c_int32), ("nonphys_fallback", C.c_int32), ("all_quadratic", C.c_int32),
                 ("graphs", C.c_int32), ("graph_budget", C.c_int32), ("limiter", C.c_int32),
-                ("reorth_tol", C.c_double)]
+                ("reorth_tol", C.c_double), ("inner_solver", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

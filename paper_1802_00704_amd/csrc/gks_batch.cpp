@@ -143,6 +143,10 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
             b->err = "gks_batch_step: handles with the limiter on are not batched";
             return GKS_EINVAL;
         }
+        if (m->prm.precision == GKS_MIXED && m->prm.inner_solver != GKS_INNER_RICHARDSON) {
+            b->err = "gks_batch_step: mixed-form handles with inner GMRES are not batched";
+            return GKS_EINVAL;
+        }
     }
     hipStream_t st = b->stream;
     std::vector<int> hist(n), all(n);

@@ -1144,6 +1144,11 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
         ws.add(&w.yf, vec);
         ws.add(&w.df, vec);
         ws.add(&w.bf, vec);
+        if (prm.inner_solver == GKS_INNER_GMRES) {
+            ws.add(&w.U, vec * (prm.inner_iters + 1));
+            ws.add(&w.T, vec * prm.inner_iters);
+            ws.add(&w.ks_in, 1);
+        }
     }
     ws.add(&w.Xp, vec);
     ws.add(&w.Xpp, vec);
@@ -1177,6 +1182,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
     }
     launch_set_scalar(m, &w.ks->tol, prm.tol);
     launch_set_scalar(m, &w.ks->reorth_tol, prm.reorth_tol);
+    if (w.ks_in) launch_set_scalar(m, &w.ks_in->reorth_tol, prm.reorth_tol);   // inner tolerance stays 0
     // device address of the static limiter scratch (gks_limit_noalloc), looked
     // up once per device with this handle's device current
     m->scratch = scratch_device_ptr(&m->scratch_err);
@@ -1498,7 +1504,9 @@ bool params_ok(const gks_params& p) {
            (p.precision == GKS_FP64 || p.precision == GKS_MIXED) &&
            (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
            (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC) &&
-           p.reorth_tol >= 0.0 && p.reorth_tol < 1.0;
+           p.reorth_tol >= 0.0 && p.reorth_tol < 1.0 &&
+           (p.inner_solver == GKS_INNER_RICHARDSON ||
+            (p.inner_solver == GKS_INNER_GMRES && p.inner_iters <= FUSED_DOTS_MAX));
 }
 
 int fail(gks_mesh* m, const Fail& f) {
@@ -1533,6 +1541,7 @@ void gks_params_default(gks_params* p) {
     p->graph_budget = 0;
     p->limiter = 0;
     p->reorth_tol = REORTH_TOL_DEFAULT;
+    p->inner_solver = GKS_INNER_RICHARDSON;
 }
 
 int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_stream, gks_mesh** out) {

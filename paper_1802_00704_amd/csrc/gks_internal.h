@@ -152,6 +152,9 @@ struct Work {
     double* partial = nullptr;    // block partial sums
     int nblk_red = 0;             // blocks of the reduction kernels
     KrylovState* ks = nullptr;    // device
+    double* U = nullptr;          // [(inner_iters+1)][n+1][CB] inner GMRES basis (mixed form, inner GMRES)
+    float* T = nullptr;           // [inner_iters][n+1][CB] its preconditioned basis (FP32)
+    KrylovState* ks_in = nullptr; // device: the inner GMRES state
     Status* st_host = nullptr;    // pinned mirror of ks->st
     double* Xcell = nullptr;
     int32_t* lim_list = nullptr;  // [nt] cells the limiter changes (allocated on first use)
@@ -262,6 +265,8 @@ void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate = n
 // 2: Arnoldi step (skipped once st.run is 0); 3: triangular solve for y.
 // gated: skip unless st.fin is 1 (end-of-cycle work in a captured graph).
 void launch_ctl(gks_mesh* m, int mode, bool gated = false);
+// the control kernel on another Krylov state (the inner GMRES), restart mres
+void launch_ctl_ks(gks_mesh* m, KrylovState* ks, int mode, int mres);
 void launch_mask_cols(gks_mesh* m, double* X);
 void launch_copyout(gks_mesh* m, const double* Xs, double* Xcell);
 void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell);

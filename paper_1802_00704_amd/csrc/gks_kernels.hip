@@ -1359,8 +1359,8 @@ __global__ void __launch_bounds__(TPB) kg_axpy(Group<AxpyArgs> g) {
 // out = sum_j y_j[c] scale_j[c] V_j
 // out = sum_j y_j scale_j V_j, or out += that sum (ACCUM: the mixed form's
 // X += Z y in one pass)
-template <class GRID, typename VT, bool ACCUM>
-__device__ __forceinline__ void combine_body(GRID grid, int n, const VT* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ y, const double* __restrict__ scale, double* __restrict__ out, const int32_t* __restrict__ nvec_dev, const int32_t* __restrict__ gate) {
+template <class GRID, typename VT, bool ACCUM, typename OT = double>
+__device__ __forceinline__ void combine_body(GRID grid, int n, const VT* __restrict__ V, int64_t vstride, int nvec, const double* __restrict__ y, const double* __restrict__ scale, OT* __restrict__ out, const int32_t* __restrict__ nvec_dev, const int32_t* __restrict__ gate) {
     if (gate && *gate == 0) return;
     if (nvec_dev) nvec = min(nvec, *nvec_dev);
     constexpr int E = Grp<VT>::E, TC = Grp<VT>::T;
@@ -1390,9 +1390,9 @@ __device__ __forceinline__ void combine_body(GRID grid, int n, const VT* __restr
 #pragma unroll
     for (int e = 0; e < E; ++e) {
         if (ACCUM)
-            out[off + e] += acc[e];
+            out[off + e] += (OT)acc[e];
         else
-            out[off + e] = acc[e];
+            out[off + e] = (OT)acc[e];
     }
 }
 
@@ -1402,6 +1402,14 @@ __global__ void __launch_bounds__(TPB) k_combine(int n, const VT* __restrict__ V
                                                  double* __restrict__ out, const int32_t* __restrict__ nvec_dev,
                                                  const int32_t* __restrict__ gate) {
     combine_body<Grid1, VT, ACCUM>(Grid1(), n, V, vstride, nvec, y, scale, out, nvec_dev, gate);
+}
+
+// z = sum_j y_j scale_j T_j into an FP32 vector (the inner GMRES result)
+__global__ void __launch_bounds__(TPB) k_combine_f32out(int n, const float* __restrict__ V, int64_t vstride, int nvec,
+                                                        const double* __restrict__ y, const double* __restrict__ scale,
+                                                        float* __restrict__ out, const int32_t* __restrict__ nvec_dev,
+                                                        const int32_t* __restrict__ gate) {
+    combine_body<Grid1, float, false, float>(Grid1(), n, V, vstride, nvec, y, scale, out, nvec_dev, gate);
 }
 
 template <typename VT>
@@ -1638,6 +1646,34 @@ __device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState*
 
 __global__ void __launch_bounds__(64) k_gmres_ctl(int mode, KrylovState* __restrict__ ks, int mres, int gated) {
     gmres_ctl_body(Grid1(), mode, ks, mres, gated);
+}
+
+// Start of an inner GMRES solve on the unit vector s .* v: residual norm 1
+// in every column, basis scale s, no column converged (the inner tolerance
+// is 0: the solve runs its fixed number of steps).
+__global__ void __launch_bounds__(64) k_inner_init(KrylovState* __restrict__ ki, const double* __restrict__ vscale,
+                                                   const int32_t* __restrict__ gate) {
+    if (gate && *gate == 0) return;
+    const int c = threadIdx.x;
+    if (c < NC) {
+        ki->scale[0][c] = vscale[c];
+        for (int j = 0; j <= MAXM; ++j) ki->g[j][c] = 0.0;
+        ki->g[0][c] = 1.0;
+        ki->st.bnorm[c] = 1.0;
+        ki->st.beta[c] = 1.0;
+        ki->st.est[c] = 1.0;
+        ki->st.active[c] = 1;
+        ki->st.conv[c] = 0;
+        ki->st.its[c] = 0;
+    }
+    if (c == 0) {
+        ki->st.k = 0;
+        ki->st.run = 1;
+        ki->st.fin = 0;
+        ki->st.total = 0;
+        ki->st.cycles = 1;
+        ki->st.reorths = 0;
+    }
 }
 
 struct CtlArgs {
@@ -2593,7 +2629,7 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
 // reductions; their LDS areas are per wave).
 static inline int sweep_tpb(int64_t rows) { return rows >= 2 * 256 * (int64_t)TPB ? TPB : 64; }
 
-static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate, int q) {
     using ACC = double;
     const DevMesh& D = m->d;
     float* b = m->w.bf;
@@ -2602,7 +2638,7 @@ static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale
     const auto& lp = D.lev_ptr;
     const int nl = (int)lp.size() - 1;
     const double VF = VB / 2;
-    for (int sw = 0; sw < m->prm.inner_iters; ++sw) {
+    for (int sw = 0; sw < q; ++sw) {
         const bool first = sw == 0;
         for (int l = 0; l < nl; ++l) {
             const int r0 = lp[l], r1 = lp[l + 1];
@@ -2635,7 +2671,7 @@ static void mx_sweeps_general(gks_mesh* m, const double* v, const double* vscale
     }
 }
 
-static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate, int q) {
     using ACC = double;
     const DevMesh& D = m->d;
     float* b = m->w.bf;
@@ -2643,7 +2679,6 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
     float* t = m->w.df;
     const auto& lp = D.lev_ptr;
     const int nl = (int)lp.size() - 1;
-    const int q = m->prm.inner_iters;
     const double VF = VB / 2;
     auto fwd = [&](int l, bool first) {
         const int r0 = lp[l], r1 = lp[l + 1];
@@ -2693,11 +2728,52 @@ static void mx_sweeps_split(gks_mesh* m, const double* v, const double* vscale, 
     }
 }
 
-void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+static void mx_sweeps(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate, int q) {
     if (m->d.split)
-        mx_sweeps_split(m, v, vscale, z, gate);
+        mx_sweeps_split(m, v, vscale, z, gate, q);
     else
-        mx_sweeps_general(m, v, vscale, z, gate);
+        mx_sweeps_general(m, v, vscale, z, gate, q);
+}
+
+// Inner GMRES of the mixed form (inner_solver = GKS_INNER_GMRES): z
+// approximately solves K z = s .* v by inner_iters steps of GMRES from z = 0,
+// right-preconditioned by one FP32 BILU(0) application (the first of the
+// split-form or general sweeps), with the FP64 matrix and an FP64 Arnoldi
+// process (classical Gram-Schmidt with the selective second pass), its own
+// basis U, preconditioned basis T (FP32) and Krylov state.  s .* v has unit
+// norm (an outer basis vector), so the inner residual starts at 1.  No host
+// read: the step count is fixed, and a breakdown (an exact inner solution)
+// stops the inner control step from advancing.  z = sum_j y_j t_j in FP32.
+static void launch_inner_gmres(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+    Work& w = m->w;
+    KrylovState* ki = w.ks_in;
+    const int mi = m->prm.inner_iters;
+    const int n = m->d.n;
+    const int64_t vs = (int64_t)(n + 1) * CB;
+    PROFB(KC_MISC, 2.0 * vs * sizeof(double), hipLaunchKernelGGL(k_copy, dim3(nblocks(vs)), dim3(TPB), 0, m->stream, vs, w.U, v));
+    PROF(KC_MISC, hipLaunchKernelGGL(k_inner_init, dim3(1), dim3(64), 0, m->stream, ki, vscale, gate));
+    for (int j = 0; j < mi; ++j) {
+        const double* uj = w.U + (int64_t)j * vs;
+        double* uj1 = w.U + (int64_t)(j + 1) * vs;
+        float* tj = w.T + (int64_t)j * vs;
+        mx_sweeps(m, uj, &ki->scale[j][0], tj, gate, 1);
+        launch_spmv64_f32x_dots(m, tj, w.w, w.U, vs, j + 1, &ki->scale[0][0], &ki->h1[0][0], gate);
+        launch_axpy_dots(m, w.U, vs, j + 1, &ki->h1[0][0], &ki->scale[0][0], w.w, uj1, &ki->h2[0][0], gate, ki->sq);
+        launch_ctl_ks(m, ki, 4, mi);
+        launch_axpy(m, w.U, vs, j + 1, &ki->h2[0][0], &ki->scale[0][0], uj1, uj1, &ki->reorth, ki->sq, true);
+        launch_ctl_ks(m, ki, 2, mi);
+    }
+    launch_ctl_ks(m, ki, 3, mi);
+    const dim3 g(nblocks((int64_t)n * Grp<float>::T)), b(TPB);
+    PROFB(KC_COMBINE, (double)n * (mi * VB / 2 + VB / 2),
+          hipLaunchKernelGGL((k_combine_f32out), g, b, 0, m->stream, n, w.T, vs, mi, &ki->y[0][0], w.ones, z, &ki->st.k, gate));
+}
+
+void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+    if (m->prm.inner_solver == GKS_INNER_GMRES)
+        launch_inner_gmres(m, v, vscale, z, gate);
+    else
+        mx_sweeps(m, v, vscale, z, gate, m->prm.inner_iters);
 }
 
 // FP64 BILU(0) solve out = M^-1 (s .* in), level by level.  Bytes: stored
@@ -2787,6 +2863,10 @@ void launch_combine_f32(gks_mesh* m, const float* V, int64_t vstride, int nvec, 
 void launch_acc(gks_mesh* m, double* X, const double* z, const int32_t* gate) {
     const int64_t len = (int64_t)m->d.n * CB;
     PROFB(KC_AXPY, (double)len * 24.0, hipLaunchKernelGGL(k_acc, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, X, z, gate));
+}
+
+void launch_ctl_ks(gks_mesh* m, KrylovState* ks, int mode, int mres) {
+    PROF(KC_MISC, hipLaunchKernelGGL(k_gmres_ctl, dim3(1), dim3(64), 0, m->stream, mode, ks, mres, 0));
 }
 
 void launch_ctl(gks_mesh* m, int mode, bool gated) {
