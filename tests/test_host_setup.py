@@ -173,6 +173,13 @@ def test_invalid_meshes_are_rejected():
         g.host_inspect(nonmanifold)
     with pytest.raises(g.GksError):
         g.host_inspect(m, restart=0)
+    # solver parameters: the second-pass threshold in [0, 1), a known inner
+    # solver, at most 8 inner GMRES steps (the fused Gram-Schmidt range)
+    for bad_kw in ({"reorth_tol": -1e-8}, {"reorth_tol": 1.0}, {"inner_solver": 2},
+                   {"inner_solver": g.GKS_INNER_GMRES, "inner_iters": 9}):
+        with pytest.raises(g.GksError):
+            g.host_inspect(m, **bad_kw)
+    g.host_inspect(m, inner_solver=g.GKS_INNER_GMRES, inner_iters=8, reorth_tol=0.0)
     # two triangles: each cell's gradient along the shared edge is bound only
     # to the other's, so the CLS matrix is singular (the oracle's direct
     # solver fails too)
