@@ -109,7 +109,8 @@ typedef struct {
     int32_t precision;       /* GKS_FP64 or GKS_MIXED                            */
     int32_t ordering;        /* GKS_ORDER_MULTICOLOR or GKS_ORDER_RCM            */
     int32_t inner_iters;     /* GKS_MIXED: FP32 preconditioned sweeps (or inner
-                                GMRES steps) per outer iteration (5)            */
+                                GMRES steps) per outer iteration (4; see
+                                inner_iters_first)                              */
     int32_t exact_time;      /* 0: time coefficients c_1..c_8 of Eq.
                                 Nomenclature2 as printed; 1: exact integrals     */
     int32_t nonphys_fallback;/* 0: non-physical Gauss-point state -> GKS_ENONPHYS;
@@ -143,6 +144,11 @@ typedef struct {
                                 step, GKS_INNER_RICHARDSON (default) or
                                 GKS_INNER_GMRES (then 1 <= inner_iters <= 8;
                                 not with gks_batch_step)                      */
+    int32_t inner_iters_first; /* GKS_MIXED, Richardson: sweeps in the first
+                                outer step of each GMRES cycle (6), the later
+                                steps take inner_iters; 0: inner_iters in
+                                every step.  gks_apply_precond applies
+                                inner_iters sweeps                            */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -176,7 +182,8 @@ typedef struct {
 
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
  * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
- * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8. */
+ * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8, mixed
+ * form with 6 Richardson sweeps in the first outer step and 4 after. */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

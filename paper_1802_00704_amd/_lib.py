@@ -54,7 +54,7 @@ class Params(C.Structure):
                 ("precision", C.c_int32), ("ordering", C.c_int32), ("inner_iters", C.c_int32),
                 ("exact_time", C.c_int32), ("nonphys_fallback", C.c_int32), ("all_quadratic", C.c_int32),
                 ("graphs", C.c_int32), ("graph_budget", C.c_int32), ("limiter", C.c_int32),
-                ("reorth_tol", C.c_double), ("inner_solver", C.c_int32)]
+                ("reorth_tol", C.c_double), ("inner_solver", C.c_int32), ("inner_iters_first", C.c_int32)]
 
 
 class SolveInfo(C.Structure):

@@ -1237,7 +1237,7 @@ void arnoldi_step(gks_mesh* m, int k, const int32_t* gate) {
     const bool fused = k + 1 <= FUSED_DOTS_MAX;
     if (m->prm.precision == GKS_MIXED) {
         float* zk = w.Z + (int64_t)k * vs;
-        launch_mx_precond(m, vk, sk, zk, gate);
+        launch_mx_precond(m, vk, sk, zk, gate, outer_step_sweeps(m, k));
         if (fused)
             launch_spmv64_f32x_dots(m, zk, w.w, w.V, vs, k + 1, &ks->scale[0][0], &ks->h1[0][0], gate);
         else
@@ -1505,6 +1505,7 @@ bool params_ok(const gks_params& p) {
            (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
            (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC) &&
            p.reorth_tol >= 0.0 && p.reorth_tol < 1.0 &&
+           p.inner_iters_first >= 0 &&
            (p.inner_solver == GKS_INNER_RICHARDSON ||
             (p.inner_solver == GKS_INNER_GMRES && p.inner_iters <= FUSED_DOTS_MAX));
 }
@@ -1533,7 +1534,8 @@ void gks_params_default(gks_params* p) {
     p->max_iter = 500;
     p->precision = GKS_FP64;
     p->ordering = GKS_ORDER_MULTICOLOR;
-    p->inner_iters = 5;
+    p->inner_iters = 4;
+    p->inner_iters_first = 6;
     p->exact_time = 0;
     p->nonphys_fallback = 0;
     p->all_quadratic = 0;

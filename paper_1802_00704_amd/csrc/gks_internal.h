@@ -234,7 +234,11 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
 void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* tmp, double* out,
                 const int32_t* gate = nullptr);
 // z = P(s .* v): the mixed form's inner iteration, inner_iters sweeps
-void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate = nullptr);
+void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate = nullptr,
+                       int q = 0);
+// Richardson sweeps of the mixed form's preconditioner at Arnoldi step k of a
+// cycle: inner_iters_first in the first step (when set), else inner_iters
+int outer_step_sweeps(const gks_mesh* m, int k);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 // second_pass: the gated second Gram-Schmidt pass (profiler class "reorth")

@@ -2618,7 +2618,7 @@ void launch_resid(gks_mesh* m, const double* x, const double* b, double* y, cons
                                           gate));
 }
 
-// The mixed form's inner iteration z = P(s .* v): inner_iters BILU(0)-
+// The mixed form's inner iteration z = P(s .* v): q (default inner_iters) BILU(0)-
 // preconditioned Richardson sweeps in FP32, in the split form when the
 // handle has it (see k_es_fwd/k_es_bwd), else the general fused sweeps
 // (k_mx_fwd/k_mx_bwd).  Bytes: stored blocks (100 B FP32, 4 B index) of each
@@ -2769,11 +2769,15 @@ static void launch_inner_gmres(gks_mesh* m, const double* v, const double* vscal
           hipLaunchKernelGGL((k_combine_f32out), g, b, 0, m->stream, n, w.T, vs, mi, &ki->y[0][0], w.ones, z, &ki->st.k, gate));
 }
 
-void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate) {
+void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate, int q) {
     if (m->prm.inner_solver == GKS_INNER_GMRES)
         launch_inner_gmres(m, v, vscale, z, gate);
     else
-        mx_sweeps(m, v, vscale, z, gate, m->prm.inner_iters);
+        mx_sweeps(m, v, vscale, z, gate, q > 0 ? q : m->prm.inner_iters);
+}
+
+int outer_step_sweeps(const gks_mesh* m, int k) {
+    return k == 0 && m->prm.inner_iters_first > 0 ? m->prm.inner_iters_first : m->prm.inner_iters;
 }
 
 // FP64 BILU(0) solve out = M^-1 (s .* in), level by level.  Bytes: stored
@@ -3308,12 +3312,14 @@ static void gilu(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::ve
 // mx_sweeps_split): sweep sw and level l of each handle in one launch per
 // kernel variant.
 static void gmx_split(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& v,
-                      const std::vector<const double*>& vscale, const std::vector<float*>& z) {
+                      const std::vector<const double*>& vscale, const std::vector<float*>& z, int k) {
     using ACC = double;
     int maxl = 0, maxq = 0;
-    for (gks_mesh* m : ms) {
-        maxl = std::max(maxl, (int)m->d.lev_ptr.size() - 1);
-        maxq = std::max(maxq, m->prm.inner_iters);
+    std::vector<int> qh(ms.size());   // sweeps of each handle at Arnoldi step k
+    for (size_t r = 0; r < ms.size(); ++r) {
+        maxl = std::max(maxl, (int)ms[r]->d.lev_ptr.size() - 1);
+        qh[r] = outer_step_sweeps(ms[r], k);
+        maxq = std::max(maxq, qh[r]);
     }
     for (int sw = 0; sw < maxq; ++sw) {
         const bool first = sw == 0;
@@ -3325,7 +3331,7 @@ static void gmx_split(hipStream_t st, const std::vector<gks_mesh*>& ms, const st
                 const DevMesh& D = m->d;
                 const auto& lp = D.lev_ptr;
                 const int nl = (int)lp.size() - 1;
-                if (sw >= m->prm.inner_iters || l >= nl || lp[l + 1] <= lp[l]) continue;
+                if (sw >= qh[r] || l >= nl || lp[l + 1] <= lp[l]) continue;
                 if (!(first || nl < 2) && l == 0) continue;   // no level-0 forward pass after the first sweep
                 const int last = l == nl - 1;
                 f[last].push_back({EsFwdArgs{D.np, lp[l], lp[l + 1], D.Lsbase[l], lp[1], D.Li, D.Lval32, D.E32,
@@ -3356,7 +3362,7 @@ static void gmx_split(hipStream_t st, const std::vector<gks_mesh*>& ms, const st
                 const DevMesh& D = m->d;
                 const auto& lp = D.lev_ptr;
                 const int nl = (int)lp.size() - 1;
-                if (sw >= m->prm.inner_iters || l > nl - 2 || lp[l + 1] <= lp[l]) continue;
+                if (sw >= qh[r] || l > nl - 2 || lp[l + 1] <= lp[l]) continue;
                 b.push_back({EsBwdArgs{lp[l], lp[l + 1], D.Usbase[l], D.Ui, D.Uval32, l == 0 ? m->w.bf : m->w.yf, z[r],
                                        nullptr},
                              lp[l + 1] - lp[l]});
@@ -3387,7 +3393,7 @@ void glaunch_arnoldi(hipStream_t st, const std::vector<gks_mesh*>& ms, int k) {
         zk.push_back(mixed ? m->w.Z + (int64_t)k * vs : nullptr);
     }
     if (mixed)
-        gmx_split(st, ms, vk, sk, zk);
+        gmx_split(st, ms, vk, sk, zk, k);
     else
         gilu(st, ms, vk, sk, t1, t2);
     std::vector<SumArgs> sa;

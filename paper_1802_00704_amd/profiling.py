@@ -143,14 +143,15 @@ def main_fp64(csv_dir: str) -> int:
     return 0
 
 
-def gathers(mesh, inner_iters: int = 5) -> dict:
+def gathers(mesh, applications=(6, 4)) -> dict:
     """Distinct neighbour rows per level and the mean compulsory gather bytes
-    per launch of each sweep class, for the launch pattern of one
-    preconditioner application: split-form FP32 sweeps (80-byte rows; the
-    first sweep's forward pass covers every level, the later ones skip level
-    0; every sweep's backward pass covers all but the last level) and the
-    FP64 BILU(0) solve (160-byte rows; forward levels 1.., backward all but
-    the last)."""
+    per launch of each sweep class, for the launch pattern of preconditioner
+    applications of the given sweep counts (default: one solve of two outer
+    steps, 6 then 4 sweeps): split-form FP32 sweeps (80-byte rows; the first
+    sweep of an application covers every level in its forward pass, the
+    later ones skip level 0; every sweep's backward pass covers all but the
+    last level) and the FP64 BILU(0) solve (160-byte rows; forward levels
+    1.., backward all but the last)."""
     import numpy as np
     from ._lib import host_inspect
     h = host_inspect(mesh)
@@ -162,8 +163,10 @@ def gathers(mesh, inner_iters: int = 5) -> dict:
         uc = h["ucol"][:, lp[l]:lp[l + 1]]
         lo.append(int(np.unique(lc[lc < nt]).size))
         up.append(int(np.unique(uc[uc < nt]).size))
-    fwd32 = [lo[l] for l in range(nl)] + [lo[l] for _ in range(inner_iters - 1) for l in range(1, nl)]
-    bwd32 = [up[l] for _ in range(inner_iters) for l in range(nl - 2, -1, -1)]
+    fwd32, bwd32 = [], []
+    for q in applications:
+        fwd32 += [lo[l] for l in range(nl)] + [lo[l] for _ in range(q - 1) for l in range(1, nl)]
+        bwd32 += [up[l] for _ in range(q) for l in range(nl - 2, -1, -1)]
     fwd64 = [lo[l] for l in range(1, nl)]
     bwd64 = [up[l] for l in range(nl - 2, -1, -1)]
     mean = lambda rows, b: b * float(np.mean(rows)) if rows else 0.0
