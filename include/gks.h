@@ -149,6 +149,23 @@ typedef struct {
                                 steps take inner_iters; 0: inner_iters in
                                 every step.  gks_apply_precond applies
                                 inner_iters sweeps                            */
+    int32_t adapt_sweeps;    /* GKS_MIXED, Richardson, 1 (default): gks_step
+                                and gks_batch_step adapt the first outer
+                                step's sweep count between steps, from
+                                inner_iters_first (inner_iters when that is
+                                0) down to 2: after 8 solves
+                                in a row that need a single outer step, the
+                                next step tries one sweep fewer; a trial
+                                that needs more outer steps restores the
+                                count and holds it for 64 steps (doubling
+                                with each such trial in a row, up to 1024),
+                                and 4
+                                solves in a row that need more than one
+                                outer step raise it by one (back to at most
+                                the starting count).  The rule reads only the
+                                handle's own outer-step counts, so a handle
+                                takes the same counts alone and in a batch.
+                                0: the count stays inner_iters_first        */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -162,6 +179,8 @@ typedef struct {
     int32_t limited;         /* cells the limiter changed in this step            */
     int32_t reorth;          /* Arnoldi steps that took the second Gram-Schmidt
                                 pass (see gks_params.reorth_tol)               */
+    int32_t first_sweeps;    /* GKS_MIXED, Richardson: sweeps of the solve's
+                                first outer step (see adapt_sweeps); else 0   */
 } gks_solve_info;
 
 /* Mesh statistics. */
@@ -183,7 +202,8 @@ typedef struct {
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
  * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
  * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8, mixed
- * form with 6 Richardson sweeps in the first outer step and 4 after. */
+ * form with 6 Richardson sweeps in the first outer step (adapted between
+ * steps) and 4 after. */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

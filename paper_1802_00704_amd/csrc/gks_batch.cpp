@@ -149,8 +149,9 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
         }
     }
     hipStream_t st = b->stream;
-    std::vector<int> hist(n), all(n);
+    std::vector<int> hist(n), all(n), q1(n);
     for (int r = 0; r < n; ++r) {
+        q1[r] = ms[r]->prm.precision == GKS_MIXED ? outer_step_sweeps(ms[r], 0) : 0;
         hist[r] = ms[r]->hist;
         ms[r]->hist = 0;   // until the step has succeeded
         all[r] = r;
@@ -238,7 +239,10 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 glaunch_commit(st, pick(ms, commit), pick(Wv, commit));
                 BHIP(hipStreamSynchronize(st));
             }
-            for (int r : commit) ms[r]->hist = std::min(hist[r], 3) + 1;
+            for (int r : commit) {
+                ms[r]->hist = std::min(hist[r], 3) + 1;
+                adapt_first_sweeps(ms[r], b->slots[r].st.total);
+            }
         }
         const double call_ms = ms_since(t_call);
         for (int r = 0; r < n; ++r) {
@@ -256,6 +260,7 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 in.call_ms = call_ms;
                 in.limited = 0;
                 in.reorth = sl.st.reorths;
+                in.first_sweeps = q1[r];
             }
         }
         return GKS_OK;

@@ -22,6 +22,62 @@
 
 using namespace gks;
 
+// Sweeps of the mixed form's first outer step, adapted after each successful
+// step from the Arnoldi steps its solve took (the rule is stated with
+// gks_params.adapt_sweeps).  Fewer sweeps cost less per outer step, but a
+// first direction too weak to meet the tolerance costs a whole outer step
+// more; the count that suffices changes as the flow and the extrapolated
+// start change, so the handle probes one sweep lower now and then and backs
+// off at once when that costs an outer step.  The hold after a failed trial
+// doubles with each failure in a row (64 steps up to 1024), so a handle whose
+// count is already the lowest that works probes rarely.
+void gks::sweep_rule(SweepAdapt& s, int outer, int top) {
+    ++s.step;
+    if (s.trial) {
+        s.trial = false;
+        if (outer > 1) {   // the lower count cost an outer step: back, and hold
+            s.q1 = s.prev;
+            s.fails = std::min(s.fails + 1, 5);
+            s.hold_until = s.step + (64 << (s.fails - 1));
+            s.ones = s.hard = 0;
+            return;
+        }
+        s.fails = 0;
+    }
+    if (outer <= 1) {
+        s.hard = 0;
+        if (++s.ones >= 8 && s.q1 > 2 && s.step >= s.hold_until) {
+            s.prev = s.q1;
+            s.q1 -= 1;
+            s.trial = true;
+            s.ones = 0;
+        }
+    } else {
+        s.ones = 0;
+        if (++s.hard >= 4 && s.q1 < top) {
+            s.q1 += 1;
+            s.hard = 0;
+        }
+    }
+}
+
+static bool adapts(const gks_mesh* m) {
+    return m->prm.adapt_sweeps && m->prm.precision == GKS_MIXED && m->prm.inner_solver == GKS_INNER_RICHARDSON;
+}
+
+static int top_sweeps(const gks_params& p) { return p.inner_iters_first > 0 ? p.inner_iters_first : p.inner_iters; }
+
+int gks::next_first_sweeps(const gks_mesh* m, int outer) {
+    if (!adapts(m)) return m->sw.q1;
+    SweepAdapt s = m->sw;
+    sweep_rule(s, outer, top_sweeps(m->prm));
+    return s.q1;
+}
+
+void gks::adapt_first_sweeps(gks_mesh* m, int outer) {
+    if (adapts(m)) sweep_rule(m->sw, outer, top_sweeps(m->prm));
+}
+
 namespace {
 
 thread_local std::string g_create_err;
@@ -1295,6 +1351,8 @@ void fill_info(gks_mesh* m, gks_solve_info* info) {
         info->rel_resid[c] = st->bnorm[c] > 0.0 ? st->beta[c] / st->bnorm[c] : 0.0;
     }
     info->reorth = st->reorths;
+    info->first_sweeps = m->prm.precision == GKS_MIXED && m->prm.inner_solver == GKS_INNER_RICHARDSON
+                             ? outer_step_sweeps(m, 0) : 0;
 }
 
 enum { RESUME_NONE = 0, RESUME_CYCLE_START = 1, RESUME_IN_CYCLE = 2 };
@@ -1405,17 +1463,61 @@ hipGraphExec_t capture(gks_mesh* m, F&& issue) {
     return ex;
 }
 
-// Both step graphs, (re)captured as needed before either is launched.
+// The solve graph for (budget, first-step sweeps q1), from the handle's
+// cache or captured into it; the cache is bounded, the least recently used
+// graph going first (never the current gA).
+hipGraphExec_t solve_graph_for(gks_mesh* m, int budget, int q1) {
+    auto& c = m->gA_cache;
+    auto hit = std::find_if(c.begin(), c.end(),
+                            [&](const gks_mesh::GraphA& e) { return e.budget == budget && e.q1 == q1; });
+    gks_mesh::GraphA e;
+    if (hit != c.end()) {
+        e = *hit;
+        c.erase(hit);
+    } else {
+        if (c.size() >= (size_t)GRAPH_A_CACHE) {
+            auto old = c.begin();
+            if (old->ex == m->gA) ++old;
+            (void)hipGraphExecDestroy(old->ex);
+            c.erase(old);
+        }
+        const int keep = m->sw.q1;
+        m->sw.q1 = q1;   // the count issue_solve_graph reads
+        try {
+            e = {budget, q1, capture(m, [&] { issue_solve_graph(m, budget); })};
+        } catch (...) {
+            m->sw.q1 = keep;
+            throw;
+        }
+        m->sw.q1 = keep;
+    }
+    c.push_back(e);   // most recently used last
+    return e.ex;
+}
+
+// Both step graphs, captured as needed before either is launched.
 void ensure_graphs(gks_mesh* m) {
     const int cap = std::min(m->prm.restart, m->prm.max_iter);
     if (m->prm.graph_budget > 0) m->budget = std::min(cap, m->prm.graph_budget);
     if (m->budget <= 0) m->budget = cap;
     if (!m->gB) m->gB = capture(m, [&] { issue_update_graph(m); });
-    if (!m->gA || m->gA_budget != m->budget) {
-        if (m->gA) (void)hipGraphExecDestroy(m->gA);
-        m->gA = nullptr;
-        m->gA = capture(m, [&] { issue_solve_graph(m, m->budget); });
-        m->gA_budget = m->budget;
+    const int q1 = outer_step_sweeps(m, 0);
+    if (m->gA && m->gA_budget == m->budget && m->gA_q1 == q1) return;
+    m->gA = solve_graph_for(m, m->budget, q1);
+    m->gA_budget = m->budget;
+    m->gA_q1 = q1;
+}
+
+// The solve graph the next step will want, captured while this step's graph
+// B runs on the device (the capture is host work), so that a new budget or
+// sweep count costs the next step no capture.  A failure here only leaves
+// the capture to the next step.
+void prepare_next_graph(gks_mesh* m, int outer) {
+    const int q1 = next_first_sweeps(m, outer);
+    if (m->budget <= 0 || (m->budget == m->gA_budget && q1 == m->gA_q1)) return;
+    try {
+        (void)solve_graph_for(m, m->budget, q1);
+    } catch (const CaptureFailed&) {
     }
 }
 
@@ -1505,7 +1607,7 @@ bool params_ok(const gks_params& p) {
            (p.ordering == GKS_ORDER_MULTICOLOR || p.ordering == GKS_ORDER_RCM) && p.inner_iters >= 1 &&
            (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC) &&
            p.reorth_tol >= 0.0 && p.reorth_tol < 1.0 &&
-           p.inner_iters_first >= 0 &&
+           p.inner_iters_first >= 0 && (p.adapt_sweeps == 0 || p.adapt_sweeps == 1) &&
            (p.inner_solver == GKS_INNER_RICHARDSON ||
             (p.inner_solver == GKS_INNER_GMRES && p.inner_iters <= FUSED_DOTS_MAX));
 }
@@ -1536,6 +1638,7 @@ void gks_params_default(gks_params* p) {
     p->ordering = GKS_ORDER_MULTICOLOR;
     p->inner_iters = 4;
     p->inner_iters_first = 6;
+    p->adapt_sweeps = 1;
     p->exact_time = 0;
     p->nonphys_fallback = 0;
     p->all_quadratic = 0;
@@ -1576,6 +1679,7 @@ int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_
         return GKS_ENOMEM;
     }
     m->prm = p;
+    m->sw.q1 = top_sweeps(p);
     m->stream = (hipStream_t)hip_stream;
     try {
         HIPCHK(hipGetDevice(&m->device));
@@ -1759,6 +1863,8 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         Work& w = m->w;
         // initial guess of the solve: extrapolation of the last solutions
         const int order = std::max(0, std::min(hist, 3) - 1);
+        int outer = 0;   // Arnoldi steps of this step's solve
+        bool speculate = false;
         bool graphs = m->prm.graphs && !m->prof.on && m->capture_failures < 3;
         if (graphs) {
             try {
@@ -1787,7 +1893,9 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
                 m->err = "GMRES did not converge within max_iter";
                 return st;
             }
+            outer = m->w.st_host->total;
             HIPCHK(hipGraphLaunch(m->gB, m->stream));
+            speculate = true;
         } else {
             if (dt > 0.0)
                 launch_set_scalar(m, w.dt_dev, dt);
@@ -1802,6 +1910,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
                 m->err = "GMRES did not converge within max_iter";
                 return st;
             }
+            outer = m->w.st_host->total;
             launch_copyout(m, w.X, w.Xcell);
             if (m->prm.limiter) launch_limit(m, W, w.Xcell, nullptr, w.Xcell, 1.0, m->prm.limiter, w.counters + 2);
             launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
@@ -1809,6 +1918,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         }
         HIPCHK(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int32_t), hipMemcpyDeviceToHost, m->stream));
         HIPCHK(hipMemcpyAsync(w.scal_host, w.dt_dev, sizeof(double), hipMemcpyDeviceToHost, m->stream));
+        if (speculate) prepare_next_graph(m, outer);
         HIPCHK(hipStreamSynchronize(m->stream));
         if (info) {
             info->nonphys = w.counters_host[0];
@@ -1826,6 +1936,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         prof_collect(m);
         if (info) info->call_ms = ms_since(t_call);
         m->hist = std::min(hist, 3) + 1;
+        adapt_first_sweeps(m, outer);
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
@@ -1981,7 +2092,7 @@ void gks_destroy(gks_mesh* m) {
         (void)hipEventDestroy(p.second.second);
     }
     for (auto e : m->prof.pool) (void)hipEventDestroy(e);
-    if (m->gA) (void)hipGraphExecDestroy(m->gA);
+    for (auto& e : m->gA_cache) (void)hipGraphExecDestroy(e.ex);   // gA among them
     if (m->gB) (void)hipGraphExecDestroy(m->gB);
     for (hipGraphExec_t c : m->gC)
         if (c) (void)hipGraphExecDestroy(c);

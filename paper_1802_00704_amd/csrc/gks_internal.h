@@ -36,6 +36,20 @@ constexpr int LW = 3;             // ELL width of the strict lower / upper facto
 constexpr int MAXM = 64;          // largest GMRES restart length
 constexpr int NPROF = 24;         // profiled kernel classes
 constexpr int MAXB = 16;          // handles per grouped launch
+constexpr int GRAPH_A_CACHE = 8;  // solve graphs kept per handle
+
+// State of the rule that adapts the mixed form's first-step sweep count
+// (sweep_rule).
+struct SweepAdapt {
+    int q1 = 0;               // sweeps of the first outer step
+    int64_t step = 0;         // successful steps seen
+    int64_t hold_until = 0;   // no trial of a lower count before this step
+    int ones = 0;             // solves in a row with one outer step
+    int hard = 0;             // solves in a row with more than one
+    int prev = 0;             // the count before the running trial
+    int fails = 0;            // trials in a row that cost an outer step
+    bool trial = false;       // this step tries a count one lower
+};
 
 struct Profile {
     bool on = false;
@@ -186,12 +200,21 @@ struct gks_mesh {
     bool capturing = false;       // a stream capture is in progress (no profiling events)
     bool own_stream = false;      // the handle created m->stream itself
     // captured step graphs (see gks_step): A = solve with a fixed iteration
-    // budget, B = copy-out, flux, update; rebuilt when the budget changes;
-    // C[k] = Arnoldi step k of a cycle still running after A, with the gated
-    // end of cycle (captured on first need)
+    // budget and first-step sweep count (one graph per pair in gA_cache), B =
+    // copy-out, flux, update; C[k] = Arnoldi step k of a cycle still running
+    // after A, with the gated end of cycle (captured on first need)
     hipGraphExec_t gA = nullptr, gB = nullptr;
     std::vector<hipGraphExec_t> gC;
     int gA_budget = 0;            // Arnoldi steps captured in gA
+    int gA_q1 = 0;                // first-step sweeps captured in gA
+    struct GraphA {
+        int budget, q1;
+        hipGraphExec_t ex;
+    };
+    std::vector<GraphA> gA_cache; // solve graphs by (budget, first-step sweeps), gA among them
+    // mixed form: Richardson sweeps of the first outer step, adapted between
+    // steps (see adapt_first_sweeps)
+    gks::SweepAdapt sw;
     int budget = 0;               // steps wanted in gA for the next step
     int need_hist[8] = {0};       // first-cycle lengths of the last steps
     int need_n = 0;               // entries of need_hist filled
@@ -237,8 +260,16 @@ void launch_ilu(gks_mesh* m, const double* in, const double* in_scale, double* t
 void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float* z, const int32_t* gate = nullptr,
                        int q = 0);
 // Richardson sweeps of the mixed form's preconditioner at Arnoldi step k of a
-// cycle: inner_iters_first in the first step (when set), else inner_iters
+// cycle: the handle's first-step count (inner_iters_first, adapted) in the
+// first step, else inner_iters
 int outer_step_sweeps(const gks_mesh* m, int k);
+// the rule's update after a successful step whose solve took outer_steps
+// Arnoldi steps; top = the starting count
+void sweep_rule(SweepAdapt& s, int outer_steps, int top);
+// the handle's count after such a step, without changing the handle
+int next_first_sweeps(const gks_mesh* m, int outer_steps);
+// the rule applied to the handle (a no-op unless adaptation is on)
+void adapt_first_sweeps(gks_mesh* m, int outer_steps);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 // second_pass: the gated second Gram-Schmidt pass (profiler class "reorth")

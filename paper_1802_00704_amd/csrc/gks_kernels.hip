@@ -2777,7 +2777,7 @@ void launch_mx_precond(gks_mesh* m, const double* v, const double* vscale, float
 }
 
 int outer_step_sweeps(const gks_mesh* m, int k) {
-    return k == 0 && m->prm.inner_iters_first > 0 ? m->prm.inner_iters_first : m->prm.inner_iters;
+    return k == 0 ? m->sw.q1 : m->prm.inner_iters;
 }
 
 // FP64 BILU(0) solve out = M^-1 (s .* in), level by level.  Bytes: stored

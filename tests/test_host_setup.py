@@ -174,12 +174,16 @@ def test_invalid_meshes_are_rejected():
     with pytest.raises(g.GksError):
         g.host_inspect(m, restart=0)
     # solver parameters: the second-pass threshold in [0, 1), a known inner
-    # solver, at most 8 inner GMRES steps (the fused Gram-Schmidt range)
+    # solver, at most 8 inner GMRES steps (the fused Gram-Schmidt range), a
+    # first-step sweep count >= 0 and an adaptation switch of 0 or 1
     for bad_kw in ({"reorth_tol": -1e-8}, {"reorth_tol": 1.0}, {"inner_solver": 2},
-                   {"inner_solver": g.GKS_INNER_GMRES, "inner_iters": 9}):
+                   {"inner_solver": g.GKS_INNER_GMRES, "inner_iters": 9}, {"inner_iters_first": -1},
+                   {"adapt_sweeps": 2}, {"adapt_sweeps": -1}):
         with pytest.raises(g.GksError):
             g.host_inspect(m, **bad_kw)
     g.host_inspect(m, inner_solver=g.GKS_INNER_GMRES, inner_iters=8, reorth_tol=0.0)
+    g.host_inspect(m, inner_iters_first=0, adapt_sweeps=0)
+    assert g.default_params().adapt_sweeps == 1
     # two triangles: each cell's gradient along the shared edge is bound only
     # to the other's, so the CLS matrix is singular (the oracle's direct
     # solver fails too)
