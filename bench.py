@@ -214,10 +214,12 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         for _ in range(late_at - done):
             gm.step(W)
         torch.cuda.synchronize()
-        l_iters, l_np, l_first = [], [], []
+        l_iters, l_np, l_first, l_lat = [], [], [], []
         t_l = time.perf_counter()
         for _ in range(steps):
+            t = time.perf_counter()
             _, info = gm.step(W)
+            l_lat.append(time.perf_counter() - t)
             l_iters.append(max(info["iters"]))
             l_np.append(info["nonphys"])
             l_first.append(info["first_sweeps"])
@@ -225,6 +227,8 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         el_l = time.perf_counter() - t_l
         late = {"steps": "%d-%d" % (late_at + 1, late_at + steps), "value": m.nt * steps / el_l,
                 "ms_per_step": el_l * 1e3 / steps, "krylov_iters_per_step": float(np.mean(l_iters)),
+                "step_ms_p50": float(np.percentile(np.array(l_lat) * 1e3, 50)),
+                "step_ms_max": float(np.max(l_lat) * 1e3),
                 "first_step_sweeps": float(np.mean(l_first)),
                 "gauss_point_fallbacks_per_step": float(np.mean(l_np))}
     stats = gm.stats()
