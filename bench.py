@@ -178,6 +178,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
     lat = []
     iters = []
     first = []
+    r0 = []
     limited = []
     nonphys = []
     t_start = time.perf_counter()
@@ -187,6 +188,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         lat.append(time.perf_counter() - t)
         iters.append(max(info["iters"]))
         first.append(info["first_sweeps"])
+        r0.append(info["start_resid"])
         limited.append(info["limited"])
         nonphys.append(info["nonphys"])
     torch.cuda.synchronize()
@@ -214,7 +216,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         for _ in range(late_at - done):
             gm.step(W)
         torch.cuda.synchronize()
-        l_iters, l_np, l_first, l_lat = [], [], [], []
+        l_iters, l_np, l_first, l_lat, l_r0 = [], [], [], [], []
         t_l = time.perf_counter()
         for _ in range(steps):
             t = time.perf_counter()
@@ -223,6 +225,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
             l_iters.append(max(info["iters"]))
             l_np.append(info["nonphys"])
             l_first.append(info["first_sweeps"])
+            l_r0.append(info["start_resid"])
         torch.cuda.synchronize()
         el_l = time.perf_counter() - t_l
         late = {"steps": "%d-%d" % (late_at + 1, late_at + steps), "value": m.nt * steps / el_l,
@@ -230,6 +233,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
                 "step_ms_p50": float(np.percentile(np.array(l_lat) * 1e3, 50)),
                 "step_ms_max": float(np.max(l_lat) * 1e3),
                 "first_step_sweeps": float(np.mean(l_first)),
+                "start_resid_median": float(np.median(l_r0)),
                 "gauss_point_fallbacks_per_step": float(np.mean(l_np))}
     stats = gm.stats()
     gm.close()
@@ -241,6 +245,7 @@ def run_form(m, W0, precision: int, steps: int, warmup: int, profile: bool, grap
         "step_ms_p99": float(np.percentile(lat_ms, 99)),
         "krylov_iters_per_step": float(np.mean(iters)),
         "first_step_sweeps": float(np.mean(first)),
+        "start_resid_median": float(np.median(r0)),
         "limited_cells_per_step": float(np.mean(limited)),
         "gauss_point_fallbacks_per_step": float(np.mean(nonphys)),
         "late_window": late,
@@ -318,20 +323,44 @@ def flux_fp64(prof: dict, n_gauss: int):
     return out
 
 
-def roofline(prof: dict, elapsed_s: float):
+def roofline(prof: dict, elapsed_s: float, n_gauss: int):
+    """Roofline entry of the kernel class with the largest share of kernel
+    time.  The memory-bound classes are priced on their algorithmic bytes
+    against the HBM peak.  The flux kernel is FP64-arithmetic bound: it is
+    priced on the method's FLOPs (the oracle's operation count per Gauss
+    point times the Gauss points of one launch) against the FP64 vector
+    peak, with the FP64 FLOPs it executes (the counters) beside them."""
     if not prof:
         return None
     tot = sum(v["ms"] for v in prof.values())
     name, d = max(prof.items(), key=lambda kv: kv[1]["ms"])
+    shares = {k: round(v["ms"] / tot, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]) if v["ms"] > 0}
+    us = d["ms"] * 1e3 / max(1, d["launches"])
+    common = {"avg_launch_us": round(us, 2), "time_share": shares,
+              "kernel_time_fraction_of_steps": round(tot * 1e-3 / elapsed_s, 4)}
+    if name == "flux":
+        fg = algorithmic_flux_flops()
+        if d["ms"] <= 0 or not fg:
+            return None
+        achieved = fg * n_gauss / (us * 1e-6) / 1e12
+        out = {"bound": "alu", "kernel": name, "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS,
+               "unit": "TFLOP/s", "frac": round(achieved / FP64_PEAK_TFLOPS, 4), "traffic": None,
+               "flop_per_launch": fg * n_gauss, "algorithmic_flop_per_gauss_point": fg}
+        fl = measured_flops("flux")
+        if fl:
+            ex = fl / (us * 1e-6) / 1e12
+            out.update({"executed_flop_per_launch": fl, "executed_TFLOPs": round(ex, 2),
+                        "executed_frac": round(ex / FP64_PEAK_TFLOPS, 4)})
+        out.update(common)
+        return out
     if d["ms"] <= 0 or d["bytes"] <= 0:
         return None
     achieved = d["bytes"] / (d["ms"] * 1e-3) / 1e9
-    shares = {k: round(v["ms"] / tot, 4) for k, v in sorted(prof.items(), key=lambda kv: -kv[1]["ms"]) if v["ms"] > 0}
-    return {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name),
-            "avg_launch_us": round(d["ms"] * 1e3 / max(1, d["launches"]), 2),
-            "bytes_per_launch": d["bytes"] / max(1, d["launches"]),
-            "time_share": shares, "kernel_time_fraction_of_steps": round(tot * 1e-3 / elapsed_s, 4)}
+    out = {"bound": "hbm", "kernel": name, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name),
+           "bytes_per_launch": d["bytes"] / max(1, d["launches"])}
+    out.update(common)
+    return out
 
 
 SAME_WORK_CLASSES = ("rhs", "cfl", "update", "copyout", "extrap", "spmv_resid", "ilu_fwd32", "ilu_bwd32",
@@ -464,7 +493,7 @@ def main():
             prec = g.GKS_MIXED if f == "mixed" else g.GKS_FP64
             ro = run_form(mo, Wo, prec, args.steps, args.warmup, False, args.graphs, extra=extra_o)
             leg[f] = {k: ro[k] for k in ("value", "ms_per_step", "krylov_iters_per_step", "first_step_sweeps",
-                                         "gauss_point_fallbacks_per_step")}
+                                         "start_resid_median", "gauss_point_fallbacks_per_step")}
             print("# %s, %s: %.4g cell-steps/s, %.3f ms/step, %.1f Krylov iterations/step" %
                   (name, f, ro["value"], ro["ms_per_step"], ro["krylov_iters_per_step"]), file=sys.stderr, flush=True)
         others[name] = leg
@@ -489,10 +518,10 @@ def main():
         "config": {"workload": desc, "form": head,
                    "solver": ("multicolour BILU(0); FP64 FGMRES(30) preconditioned by FP32 BILU(0)-Richardson sweeps (6 in the first outer step, adapted down while one outer step suffices; 4 after)"
                               + (" (split form)" if r["stats"].get("split_form") else "")
-                              + "; start extrapolated from the last three solutions") if head == "mixed"
-                   else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from the last three solutions",
+                              + "; start extrapolated from the last five solutions") if head == "mixed"
+                   else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from the last five solutions",
                    "cells": m.nt},
-        "roofline": roofline(r["profile"], r["profiled_elapsed_s"]),
+        "roofline": roofline(r["profile"], r["profiled_elapsed_s"], 2 * int(r["stats"]["nf"])),
         "flux_fp64": flux_fp64(r["profile"], 2 * int(r["stats"]["nf"])),
         "cpu_baseline": cpu,
         "forms": {f: dict({k: v for k, v in res[f].items() if k not in ("profile", "stats", "elapsed_s", "profiled_elapsed_s")},

@@ -166,6 +166,14 @@ typedef struct {
                                 handle's own outer-step counts, so a handle
                                 takes the same counts alone and in a batch.
                                 0: the count stays inner_iters_first        */
+    int32_t extrap_points;   /* starting guess of each step's solve: the
+                                polynomial through the last extrap_points
+                                solutions at their times, evaluated at the
+                                step's time, 1..5 (fewer while the step
+                                sequence has fewer solutions); 0 (default):
+                                5, or 3 with the limiter on.  Only the start
+                                changes: every solve still ends on its true
+                                residual                                      */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -181,6 +189,8 @@ typedef struct {
                                 pass (see gks_params.reorth_tol)               */
     int32_t first_sweeps;    /* GKS_MIXED, Richardson: sweeps of the solve's
                                 first outer step (see adapt_sweeps); else 0   */
+    double  start_resid;     /* largest relative residual of the starting
+                                guess over the columns (see extrap_points)   */
 } gks_solve_info;
 
 /* Mesh statistics. */
@@ -203,7 +213,7 @@ typedef struct {
  * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
  * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8, mixed
  * form with 6 Richardson sweeps in the first outer step (adapted between
- * steps) and 4 after. */
+ * steps) and 4 after, starting guesses extrapolated from 5 solutions (3 with the limiter). */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

@@ -55,20 +55,21 @@ class Params(C.Structure):
                 ("exact_time", C.c_int32), ("nonphys_fallback", C.c_int32), ("all_quadratic", C.c_int32),
                 ("graphs", C.c_int32), ("graph_budget", C.c_int32), ("limiter", C.c_int32),
                 ("reorth_tol", C.c_double), ("inner_solver", C.c_int32), ("inner_iters_first", C.c_int32),
-                ("adapt_sweeps", C.c_int32)]
+                ("adapt_sweeps", C.c_int32), ("extrap_points", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32 * 4), ("restarts", C.c_int32 * 4), ("rel_resid", C.c_double * 4),
                 ("nonphys", C.c_int32), ("solve_ms", C.c_double), ("call_ms", C.c_double),
                 ("limited", C.c_int32), ("reorth", C.c_int32),
-                ("first_sweeps", C.c_int32)]
+                ("first_sweeps", C.c_int32), ("start_resid", C.c_double)]
 
     def as_dict(self):
         return {"iters": list(self.iters), "restarts": list(self.restarts),
                 "rel_resid": list(self.rel_resid), "nonphys": int(self.nonphys),
                 "solve_ms": float(self.solve_ms), "call_ms": float(self.call_ms), "limited": int(self.limited),
-                "reorth": int(self.reorth), "first_sweeps": int(self.first_sweeps)}
+                "reorth": int(self.reorth), "first_sweeps": int(self.first_sweeps),
+                "start_resid": float(self.start_resid)}
 
 
 class Stats(C.Structure):

@@ -173,9 +173,7 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
         glaunch_zero_counters(st, ms, dtv);
         if (!cfl.empty()) glaunch_cfl(st, pick(ms, cfl), pick(Wc, cfl));
         // initial guesses from the solution histories
-        std::vector<int> order(n);
-        for (int r = 0; r < n; ++r) order[r] = std::max(0, std::min(hist[r], 3) - 1);
-        glaunch_extrap(st, ms, order);
+        glaunch_extrap(st, ms, hist);
         // reconstruction: right-hand sides, then lockstep GMRES cycles
         const auto t_solve = std::chrono::steady_clock::now();
         glaunch_rhs(st, ms, Wc);
@@ -240,7 +238,8 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 BHIP(hipStreamSynchronize(st));
             }
             for (int r : commit) {
-                ms[r]->hist = std::min(hist[r], 3) + 1;
+                ms[r]->hist = std::min(hist[r], extrap_points(ms[r]->prm) - 1) + 1;
+                push_step(ms[r], b->slots[r].dt);
                 adapt_first_sweeps(ms[r], b->slots[r].st.total);
             }
         }
@@ -261,6 +260,7 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 in.limited = 0;
                 in.reorth = sl.st.reorths;
                 in.first_sweeps = q1[r];
+                in.start_resid = start_resid(sl.st);
             }
         }
         return GKS_OK;

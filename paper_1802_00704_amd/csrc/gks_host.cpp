@@ -1206,8 +1206,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
             ws.add(&w.ks_in, 1);
         }
     }
-    ws.add(&w.Xp, vec);
-    ws.add(&w.Xpp, vec);
+    for (int i = 0; i < extrap_points(prm) - 1; ++i) ws.add(&w.H[i], vec);
     ws.add(&w.w, vec);
     ws.add(&w.t1, vec);
     ws.add(&w.t2, vec);
@@ -1351,6 +1350,7 @@ void fill_info(gks_mesh* m, gks_solve_info* info) {
         info->rel_resid[c] = st->bnorm[c] > 0.0 ? st->beta[c] / st->bnorm[c] : 0.0;
     }
     info->reorth = st->reorths;
+    info->start_resid = start_resid(*st);
     info->first_sweeps = m->prm.precision == GKS_MIXED && m->prm.inner_solver == GKS_INNER_RICHARDSON
                              ? outer_step_sweeps(m, 0) : 0;
 }
@@ -1608,6 +1608,7 @@ bool params_ok(const gks_params& p) {
            (p.graphs == 0 || p.graphs == 1) && p.graph_budget >= 0 && (p.limiter == 0 || p.limiter == GKS_LIMIT_CONSERVATIVE || p.limiter == GKS_LIMIT_CHARACTERISTIC) &&
            p.reorth_tol >= 0.0 && p.reorth_tol < 1.0 &&
            p.inner_iters_first >= 0 && (p.adapt_sweeps == 0 || p.adapt_sweeps == 1) &&
+           p.extrap_points >= 0 && p.extrap_points <= MAXH + 1 &&
            (p.inner_solver == GKS_INNER_RICHARDSON ||
             (p.inner_solver == GKS_INNER_GMRES && p.inner_iters <= FUSED_DOTS_MAX));
 }
@@ -1639,6 +1640,7 @@ void gks_params_default(gks_params* p) {
     p->inner_iters = 4;
     p->inner_iters_first = 6;
     p->adapt_sweeps = 1;
+    p->extrap_points = 0;
     p->exact_time = 0;
     p->nonphys_fallback = 0;
     p->all_quadratic = 0;
@@ -1713,6 +1715,7 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
     try {
         const int st = run_solve(m, W, info);
         m->hist = st == GKS_OK ? 1 : 0;   // X is a solution, but not of the step sequence
+        std::fill(m->dth, m->dth + MAXH + 1, 0.0);
         launch_copyout(m, m->w.X, X);
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
@@ -1862,7 +1865,6 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
     try {
         Work& w = m->w;
         // initial guess of the solve: extrapolation of the last solutions
-        const int order = std::max(0, std::min(hist, 3) - 1);
         int outer = 0;   // Arnoldi steps of this step's solve
         bool speculate = false;
         bool graphs = m->prm.graphs && !m->prof.on && m->capture_failures < 3;
@@ -1880,7 +1882,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
             // graph path: the step works on the handle's copy of W
             ++m->graph_steps;
             launch_copy(m, w.Wint, W, (int64_t)4 * m->d.nt);
-            launch_extrap(m, order);
+            launch_extrap(m, hist);
             if (dt > 0.0)
                 launch_set_scalar(m, w.dt_dev, dt);
             else
@@ -1902,7 +1904,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
             else
                 launch_cfl(m, W, w.dt_dev);
             launch_zero_i32(m, w.counters, 4);
-            launch_extrap(m, order);
+            launch_extrap(m, hist);
             const int st = run_solve(m, W, info);
             if (st != GKS_OK) {
                 HIPCHK(hipStreamSynchronize(m->stream));
@@ -1935,7 +1937,8 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
         if (info) info->call_ms = ms_since(t_call);
-        m->hist = std::min(hist, 3) + 1;
+        m->hist = std::min(hist, extrap_points(m->prm) - 1) + 1;
+        push_step(m, w.scal_host[0]);
         adapt_first_sweeps(m, outer);
         return GKS_OK;
     } catch (const Fail& f) {

@@ -37,6 +37,7 @@ constexpr int MAXM = 64;          // largest GMRES restart length
 constexpr int NPROF = 24;         // profiled kernel classes
 constexpr int MAXB = 16;          // handles per grouped launch
 constexpr int GRAPH_A_CACHE = 8;  // solve graphs kept per handle
+constexpr int MAXH = 4;           // earlier solutions kept for the extrapolated start
 
 // State of the rule that adapts the mixed form's first-step sweep count
 // (sweep_rule).
@@ -66,6 +67,7 @@ struct Profile {
 struct Status {
     double est[NC];               // |g_{k+1}| / ||R_c|| (estimate of the relative residual)
     double beta[NC];              // ||r_c|| at the start of the cycle (true residual)
+    double beta0[NC];             // ||r_c|| of the starting guess (-1 until the first cycle starts)
     double bnorm[NC];             // ||R_c||
     int32_t k;                    // Arnoldi steps done in this cycle
     int32_t run;                  // 1 while the cycle continues (gates the iteration kernels)
@@ -80,6 +82,15 @@ struct Status {
 
 // default of gks_params.reorth_tol
 constexpr double REORTH_TOL_DEFAULT = 1e-8;
+
+// largest relative residual of a solve's starting guess over the columns
+// with a nonzero right-hand side
+inline double start_resid(const Status& s) {
+    double r = 0.0;
+    for (int c = 0; c < NC; ++c)
+        if (s.bnorm[c] > 0.0 && s.beta0[c] > 0.0) r = r > s.beta0[c] / s.bnorm[c] ? r : s.beta0[c] / s.bnorm[c];
+    return r;
+}
 
 struct KrylovState {
     Status st;
@@ -156,8 +167,8 @@ struct Work {
     float* bf = nullptr;          // [n+1][CB] mixed inner sweeps: FP32 right-hand side
     double* npart = nullptr;      // per-block partial sums of the fused norms: [4][blocks of 10 n threads]
     double* dpart = nullptr;      // per-block partial dots of the fused Gram-Schmidt passes
-    float* Xp = nullptr;          // [n][CB] solution of the step before the last (FP32)
-    float* Xpp = nullptr;         // [n][CB] the one before that (FP32)
+    double* H[MAXH] = {};         // [n][CB] earlier solutions, a ring
+                                  // (extrap_points(prm) - 1 slots; newest at gks_mesh::hring)
     double* w = nullptr;          // [n+1][CB]
     double* t1 = nullptr;         // [n+1][CB]
     double* t2 = nullptr;         // [n+1][CB]
@@ -218,7 +229,10 @@ struct gks_mesh {
     int budget = 0;               // steps wanted in gA for the next step
     int need_hist[8] = {0};       // first-cycle lengths of the last steps
     int need_n = 0;               // entries of need_hist filled
-    int hist = 0;                 // solutions held in X, Xp, Xpp (extrapolated guess)
+    int hist = 0;                 // solutions held in X and the ring w.H (extrapolated guess)
+    int hring = 0;                // slot of w.H holding the newest earlier solution
+    double dth[gks::MAXH + 1] = {}; // time steps taken from X, then from the ring's solutions
+                                  // (newest first; hist of them are valid)
     int64_t graph_steps = 0;      // steps run through the graphs
     int capture_failures = 0;     // captures that failed (3 turn graphs off)
     std::string capture_err;      // the last capture failure
@@ -308,7 +322,15 @@ void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell);
 void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
 // initial guess of a step's solve from the last solutions (order 0, 1, 2)
 // and shift of the history
-void launch_extrap(gks_mesh* m, int order);
+// solutions the starting guess extrapolates from: gks_params.extrap_points,
+// or when that is 0, 5 (3 with the limiter on: limited cells switching
+// between steps make the solutions less smooth in time)
+inline int extrap_points(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points : (p.limiter ? 3 : 5); }
+// starting guess from npts (1..extrap_points) solutions: X and npts - 1 ring
+// slots; stores X in the ring and rotates it
+void launch_extrap(gks_mesh* m, int npts);
+// after a successful step of size dt
+void push_step(gks_mesh* m, double dt);
 void launch_flux(gks_mesh* m, const double* W, const double* X, const double* dt_dev, double* F);
 // DWBAP limiter: Xout = limited X where IS_i >= threshold (count += limited cells)
 // DWBAP limiter: cells whose indicator reaches threshold get limited
@@ -340,7 +362,7 @@ void glaunch_gather(hipStream_t st, const std::vector<gks_mesh*>& ms, const std:
 // counters = 0 and, where dt[r] > 0, the step's dt set to it
 void glaunch_zero_counters(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<double>& dt);
 void glaunch_cfl(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W);
-void glaunch_extrap(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& order);
+void glaunch_extrap(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& npts);
 void glaunch_rhs(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<const double*>& W);
 void glaunch_ctl(hipStream_t st, const std::vector<gks_mesh*>& ms, int mode);
 void glaunch_mask_cols(hipStream_t st, const std::vector<gks_mesh*>& ms);

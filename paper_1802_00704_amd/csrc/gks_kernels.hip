@@ -1570,9 +1570,11 @@ __device__ __forceinline__ void gmres_ctl_body(GRID grid, int mode, KrylovState*
             st.bnorm[c] = b;
             st.active[c] = b > 0.0;
             st.its[c] = 0;
+            st.beta0[c] = -1.0;
         } else if (mode == 1) {
             const double b = sqrt(ks->sq[c]);
             st.beta[c] = b;
+            if (st.beta0[c] < 0.0) st.beta0[c] = b;
             ks->scale[0][c] = b > 0.0 ? 1.0 / b : 0.0;
             for (int j = 0; j <= MAXM; ++j) ks->g[j][c] = 0.0;
             ks->g[0][c] = b;
@@ -1728,44 +1730,44 @@ __global__ void __launch_bounds__(TPB) kg_copyout(Group<CopyoutArgs<T>> g) {
 }
 
 
-// Initial guess for the next step's solve by polynomial extrapolation in
-// time of the last solutions (uniform steps): order 0 X, order 1 2X - Xp,
-// order 2 3X - 3Xp + Xpp; the history shifts (Xpp <- Xp, Xp <- X).  The
-// history is kept in FP32: it only shapes the starting point, which the
-// solve then corrects to its tolerance.
-template <class GRID>
-__device__ __forceinline__ void extrap_body(GRID grid, int64_t len, int order, double* __restrict__ X, float* __restrict__ Xp, float* __restrict__ Xpp) {
-    const int64_t e = (int64_t)grid.b() * blockDim.x + threadIdx.x;
-    if (e >= len) return;
-    const double x = X[e];
-    const float p = Xp[e];
-    double g = x;
-    if (order == 1) g = 2.0 * x - (double)p;
-    if (order >= 2) g = 3.0 * (x - (double)p) + (double)Xpp[e];
-    X[e] = g;
-    Xpp[e] = p;
-    Xp[e] = (float)x;
-}
-
-__global__ void __launch_bounds__(TPB) k_extrap(int64_t len, int order, double* __restrict__ X,
-                                                float* __restrict__ Xp, float* __restrict__ Xpp) {
-    extrap_body(Grid1(), len, order, X, Xp, Xpp);
-}
-
+// Initial guess for the next step's solve: the polynomial through the last
+// npts solutions at their times, evaluated at the current time:
+// g = c[0] x + c[1] h0 + c[2] h1 + ..., with x the last solution, h0, h1, ...
+// the earlier ones (newest first) and c the Lagrange weights the host
+// computes from the step sizes (at uniform steps the alternating binomial
+// ones: x; 2x - h0; 3x - 3h0 + h1; ...).  The earlier solutions are kept in
+// FP64 in a ring: the larger coefficients of the longer
+// polynomials would amplify the rounding of FP32 copies above the
+// extrapolation error of smooth flows.  x goes into the ring's oldest slot
+// (hout, which may be the slot read as the oldest term: each element is read
+// before it is overwritten).
 struct ExtrapArgs {
     int64_t len;
-    int order;
+    int npts;
+    double c[MAXH + 1];     // weights of x, h0, h1, ...
     double* X;
-    float* Xp;
-    float* Xpp;
+    const double* h[MAXH];  // newest first
+    double* hout;           // null without a ring
 };
+
+template <class GRID>
+__device__ __forceinline__ void extrap_body(GRID grid, const ExtrapArgs& a) {
+    const int64_t e = (int64_t)grid.b() * blockDim.x + threadIdx.x;
+    if (e >= a.len) return;
+    const double x = a.X[e];
+    double g = a.c[0] * x;
+    for (int i = 1; i < a.npts; ++i) g = fma(a.c[i], a.h[i - 1][e], g);
+    a.X[e] = g;
+    if (a.hout) a.hout[e] = x;
+}
+
+__global__ void __launch_bounds__(TPB) k_extrap(ExtrapArgs a) { extrap_body(Grid1(), a); }
 
 __global__ void __launch_bounds__(TPB) kg_extrap(Group<ExtrapArgs> g) {
     GridV v;
     const int r = group_locate(g, v);
     if (r < 0) return;
-    const ExtrapArgs& a = g.a[r];
-    extrap_body(v, a.len, a.order, a.X, a.Xp, a.Xpp);
+    extrap_body(v, g.a[r]);
 }
 
 
@@ -2894,10 +2896,50 @@ void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell) {
     PROF(KC_COPYOUT, hipLaunchKernelGGL(k_copyout<float>, dim3(nblocks(nt)), dim3(TPB), 0, m->stream, nt, m->d.iperm, Xs, Xcell));
 }
 
-void launch_extrap(gks_mesh* m, int order) {
-    const int64_t len = (int64_t)m->d.n * CB;
-    PROFB(KC_EXTRAP, (double)len * 32.0, hipLaunchKernelGGL(k_extrap, dim3(nblocks(len)), dim3(TPB), 0, m->stream, len, order,
-                                                          m->w.X, m->w.Xp, m->w.Xpp));
+// Arguments of the extrapolation for npts solutions; rotates the handle's
+// ring (the slot receiving X becomes the newest).
+static ExtrapArgs extrap_args(gks_mesh* m, int npts) {
+    const int S = extrap_points(m->prm) - 1;
+    ExtrapArgs a{};
+    a.len = (int64_t)m->d.n * CB;
+    // the solutions used must have their step sizes (a reconstruction
+    // outside the step sequence clears them)
+    int known = 0;
+    while (known < S + 1 && m->dth[known] > 0.0) ++known;
+    a.npts = std::max(1, std::min(std::min(npts, S + 1), known));
+    // Lagrange weights at time 0 of the solutions at tau_0 = -dth[0],
+    // tau_i = tau_{i-1} - dth[i]
+    double tau[MAXH + 1];
+    double t = 0.0;
+    for (int i = 0; i < a.npts; ++i) tau[i] = t -= m->dth[i];
+    for (int i = 0; i < a.npts; ++i) {
+        double w = 1.0;
+        for (int j = 0; j < a.npts; ++j)
+            if (j != i) w *= (0.0 - tau[j]) / (tau[i] - tau[j]);
+        a.c[i] = w;
+    }
+    a.X = m->w.X;
+    for (int i = 0; i < S; ++i) a.h[i] = m->w.H[(m->hring + i) % S];
+    if (S > 0) {
+        a.hout = m->w.H[(m->hring + S - 1) % S];
+        m->hring = (m->hring + S - 1) % S;
+    }
+    return a;
+}
+
+void push_step(gks_mesh* m, double dt) {
+    for (int i = MAXH; i > 0; --i) m->dth[i] = m->dth[i - 1];
+    m->dth[0] = dt;
+}
+
+// algorithmic bytes: X read and written, the ring slots read, one written
+static double extrap_bytes(const ExtrapArgs& a) {
+    return (double)a.len * (16.0 + 8.0 * (a.npts - 1) + (a.hout ? 8.0 : 0.0));
+}
+
+void launch_extrap(gks_mesh* m, int npts) {
+    const ExtrapArgs a = extrap_args(m, npts);
+    PROFB(KC_EXTRAP, extrap_bytes(a), hipLaunchKernelGGL(k_extrap, dim3(nblocks(a.len)), dim3(TPB), 0, m->stream, a));
 }
 
 void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs) {
@@ -3190,12 +3232,11 @@ void glaunch_cfl(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::ve
     glaunch(st, kg_cfl_final, 64, b, KC_CFL);
 }
 
-void glaunch_extrap(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& order) {
+void glaunch_extrap(hipStream_t st, const std::vector<gks_mesh*>& ms, const std::vector<int>& npts) {
     std::vector<std::pair<ExtrapArgs, int>> it;
     for (size_t r = 0; r < ms.size(); ++r) {
-        gks_mesh* m = ms[r];
-        const int64_t len = (int64_t)m->d.n * CB;
-        it.push_back({ExtrapArgs{len, order[r], m->w.X, m->w.Xp, m->w.Xpp}, nblocks(len)});
+        const ExtrapArgs a = extrap_args(ms[r], npts[r]);
+        it.push_back({a, nblocks(a.len)});
     }
     glaunch(st, kg_extrap, TPB, it, KC_EXTRAP);
 }

@@ -50,7 +50,7 @@ def test_roofline_arithmetic(monkeypatch):
     monkeypatch.setattr(b, "measured_flops", lambda cls: 3.2e10)
     prof = {"ilu_fwd32": {"ms": 6.0, "launches": 100, "bytes": 100 * 2.4e8},
             "flux": {"ms": 2.4, "launches": 3, "bytes": 3 * 9e8}}
-    r = b.roofline(prof, 0.01)
+    r = b.roofline(prof, 0.01, 3_000_000)
     assert r["kernel"] == "ilu_fwd32" and r["unit"] == "GB/s" and r["bound"] == "hbm"
     assert r["achieved"] == pytest.approx(2.4e8 / 60e-6 / 1e9, rel=1e-3)
     assert r["frac"] == pytest.approx(r["achieved"] / 8000.0, rel=1e-3)
@@ -61,3 +61,19 @@ def test_roofline_arithmetic(monkeypatch):
     assert f["executed_flop_per_gauss_point"] == pytest.approx(3.2e10 / 3e6, rel=1e-3)
     fg = b.algorithmic_flux_flops()
     assert fg and f["algorithmic_rate_TFLOPs"] == pytest.approx(fg * 3e6 / 0.8e-3 / 1e12, rel=1e-3)
+
+
+def test_roofline_of_the_flux_when_it_dominates(monkeypatch):
+    """The FP64-bound flux is priced on the method's FLOPs against the FP64
+    vector peak, with the executed FLOPs beside them."""
+    b = load_bench()
+    monkeypatch.setattr(b, "measured_flops", lambda cls: 3.2e10)
+    prof = {"ilu_fwd32": {"ms": 2.0, "launches": 100, "bytes": 100 * 2.4e8},
+            "flux": {"ms": 2.4, "launches": 3, "bytes": 3 * 9e8}}
+    r = b.roofline(prof, 0.01, 3_000_000)
+    fg = b.algorithmic_flux_flops()
+    assert r["kernel"] == "flux" and r["bound"] == "alu" and r["unit"] == "TFLOP/s" and r["peak"] == 78.6
+    assert r["achieved"] == pytest.approx(fg * 3e6 / 0.8e-3 / 1e12, rel=1e-3)
+    assert r["frac"] == pytest.approx(r["achieved"] / 78.6, rel=1e-3)
+    assert r["executed_TFLOPs"] == pytest.approx(3.2e10 / 0.8e-3 / 1e12, rel=1e-3)
+    assert r["executed_frac"] == pytest.approx(r["executed_TFLOPs"] / 78.6, rel=1e-3)
