@@ -170,10 +170,19 @@ typedef struct {
                                 polynomial through the last extrap_points
                                 solutions at their times, evaluated at the
                                 step's time, 1..5 (fewer while the step
-                                sequence has fewer solutions); 0 (default):
-                                5, or 3 with the limiter on.  Only the start
-                                changes: every solve still ends on its true
-                                residual                                      */
+                                sequence has fewer solutions).  0 (default):
+                                the count adapts between steps, from 5 (3
+                                with the limiter on) within 2..5.  Once the
+                                starting residual r0 is below 50 (2^P - 1)
+                                tol (the previous solves' residuals amplified
+                                by the weights), a step tries P - 1; while it
+                                is above 1000 (2^P - 1) tol, P + 1.  A trial
+                                comes after at least 24 steps at P and is
+                                kept if its r0 is below 0.7 times the median
+                                of the last four at P; else no trial follows
+                                for 48 steps, doubling with each failure in a
+                                row up to 384.  Only the start changes: every
+                                solve still ends on its true residual        */
 } gks_params;
 
 /* Per-solve report (one entry per conserved variable). */
@@ -191,6 +200,7 @@ typedef struct {
                                 first outer step (see adapt_sweeps); else 0   */
     double  start_resid;     /* largest relative residual of the starting
                                 guess over the columns (see extrap_points)   */
+    int32_t start_points;    /* solutions the starting guess took            */
 } gks_solve_info;
 
 /* Mesh statistics. */
@@ -207,13 +217,18 @@ typedef struct {
                                 has no off-diagonal fill (U = K_U, L = K_L D^-1)
                                 and the mixed form's inner sweeps run in the
                                 split form without products by all of K        */
+    int32_t graph_captures;  /* step graphs captured (solve graphs per budget
+                                and first-step sweep count, continuations, the
+                                flux-and-update graph)                         */
+    double  capture_ms;      /* host time spent capturing and instantiating    */
 } gks_mesh_stats;
 
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
  * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
  * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8, mixed
  * form with 6 Richardson sweeps in the first outer step (adapted between
- * steps) and 4 after, starting guesses extrapolated from 5 solutions (3 with the limiter). */
+ * steps) and 4 after, starting guesses extrapolated from an adapted number of solutions
+ * (from 5; 3 with the limiter). */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

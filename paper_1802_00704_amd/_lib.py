@@ -62,20 +62,22 @@ class SolveInfo(C.Structure):
     _fields_ = [("iters", C.c_int32 * 4), ("restarts", C.c_int32 * 4), ("rel_resid", C.c_double * 4),
                 ("nonphys", C.c_int32), ("solve_ms", C.c_double), ("call_ms", C.c_double),
                 ("limited", C.c_int32), ("reorth", C.c_int32),
-                ("first_sweeps", C.c_int32), ("start_resid", C.c_double)]
+                ("first_sweeps", C.c_int32), ("start_resid", C.c_double),
+                ("start_points", C.c_int32)]
 
     def as_dict(self):
         return {"iters": list(self.iters), "restarts": list(self.restarts),
                 "rel_resid": list(self.rel_resid), "nonphys": int(self.nonphys),
                 "solve_ms": float(self.solve_ms), "call_ms": float(self.call_ms), "limited": int(self.limited),
                 "reorth": int(self.reorth), "first_sweeps": int(self.first_sweeps),
-                "start_resid": float(self.start_resid)}
+                "start_resid": float(self.start_resid), "start_points": int(self.start_points)}
 
 
 class Stats(C.Structure):
     _fields_ = [("nt", C.c_int32), ("nf", C.c_int32), ("nf_boundary", C.c_int32), ("n_levels", C.c_int32),
                 ("n_colors", C.c_int32), ("rcm_bandwidth", C.c_int32), ("device_bytes", C.c_int64),
-                ("graph_steps", C.c_int64), ("capture_failures", C.c_int32), ("split_form", C.c_int32)]
+                ("graph_steps", C.c_int64), ("capture_failures", C.c_int32), ("split_form", C.c_int32),
+                ("graph_captures", C.c_int32), ("capture_ms", C.c_double)]
 
 
 class HostSystem(C.Structure):

@@ -238,9 +238,10 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 BHIP(hipStreamSynchronize(st));
             }
             for (int r : commit) {
-                ms[r]->hist = std::min(hist[r], extrap_points(ms[r]->prm) - 1) + 1;
+                ms[r]->hist = std::min(hist[r], ring_slots(ms[r]->prm)) + 1;
                 push_step(ms[r], b->slots[r].dt);
                 adapt_first_sweeps(ms[r], b->slots[r].st.total);
+                adapt_points(ms[r], start_resid(b->slots[r].st), ms[r]->last_npts);
             }
         }
         const double call_ms = ms_since(t_call);
@@ -261,6 +262,7 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 in.reorth = sl.st.reorths;
                 in.first_sweeps = q1[r];
                 in.start_resid = start_resid(sl.st);
+                in.start_points = ms[r]->last_npts;
             }
         }
         return GKS_OK;

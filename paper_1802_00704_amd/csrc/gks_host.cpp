@@ -61,6 +61,60 @@ void gks::sweep_rule(SweepAdapt& s, int outer, int top) {
     }
 }
 
+// Points of the extrapolated start (gks_params.extrap_points = 0).  Each
+// point added cuts the extrapolation error of a smooth flow about ten-fold,
+// but the weights grow (their absolute sum is 2^P - 1 at uniform steps), and
+// they amplify what the earlier solves left: residuals up to tol each.  Once
+// the starting residual r0 comes within 50 (2^P - 1) tol of that floor, a
+// point fewer may start closer; while it stays above 1000 (2^P - 1) tol, a
+// point more may (up to 5).  Such a step tries it once, after at least 24
+// steps at the current count, and keeps it if its starting residual is
+// below 0.7 times the median of the last four at the current count; else
+// the count goes back and no trial follows for 48 steps, doubling with each
+// failure in a row up to 384.  Steps whose start took fewer points (a short
+// history) or met the tolerance outright leave the rule alone.
+void gks::points_rule(PointsAdapt& s, double r0, int used, double tol) {
+    ++s.step;
+    if (used != s.P || !(r0 > 0.0)) return;
+    if (s.trial) {
+        s.trial = false;
+        double v[4];
+        std::copy(s.r0, s.r0 + s.nr, v);
+        std::sort(v, v + s.nr);
+        const double med = s.nr % 2 ? v[s.nr / 2] : 0.5 * (v[s.nr / 2 - 1] + v[s.nr / 2]);
+        if (r0 < 0.7 * med) {   // the trial count starts closer: keep it
+            s.nr = 0;
+            s.since = 0;
+            s.fails = 0;
+            return;
+        }
+        s.P = s.prev;
+        s.fails = std::min(s.fails + 1, 4);
+        s.hold_until = s.step + (24 << s.fails);
+        s.since = 0;
+        return;
+    }
+    for (int i = 3; i > 0; --i) s.r0[i] = s.r0[i - 1];
+    s.r0[0] = r0;
+    s.nr = std::min(s.nr + 1, 4);
+    ++s.since;
+    if (s.nr < 4 || s.since < 24 || s.step < s.hold_until) return;
+    const double floor = ((1 << s.P) - 1) * tol;
+    int np = 0;
+    if (s.P > 2 && r0 < 50.0 * floor) np = s.P - 1;
+    else if (s.P < MAXH + 1 && r0 > 1000.0 * floor) np = s.P + 1;
+    if (np) {
+        s.prev = s.P;
+        s.P = np;
+        s.trial = true;
+        s.since = 0;
+    }
+}
+
+void gks::adapt_points(gks_mesh* m, double r0, int used) {
+    if (m->prm.extrap_points == 0) points_rule(m->pts, r0, used, m->prm.tol);
+}
+
 static bool adapts(const gks_mesh* m) {
     return m->prm.adapt_sweeps && m->prm.precision == GKS_MIXED && m->prm.inner_solver == GKS_INNER_RICHARDSON;
 }
@@ -1206,7 +1260,7 @@ void setup(gks_mesh* m, const gks_mesh_desc* de) {
             ws.add(&w.ks_in, 1);
         }
     }
-    for (int i = 0; i < extrap_points(prm) - 1; ++i) ws.add(&w.H[i], vec);
+    for (int i = 0; i < ring_slots(prm); ++i) ws.add(&w.H[i], vec);
     ws.add(&w.w, vec);
     ws.add(&w.t1, vec);
     ws.add(&w.t2, vec);
@@ -1351,6 +1405,7 @@ void fill_info(gks_mesh* m, gks_solve_info* info) {
     }
     info->reorth = st->reorths;
     info->start_resid = start_resid(*st);
+    info->start_points = m->last_npts;
     info->first_sweeps = m->prm.precision == GKS_MIXED && m->prm.inner_solver == GKS_INNER_RICHARDSON
                              ? outer_step_sweeps(m, 0) : 0;
 }
@@ -1434,6 +1489,15 @@ struct CaptureFailed {
 
 template <typename F>
 hipGraphExec_t capture(gks_mesh* m, F&& issue) {
+    const auto t0 = std::chrono::steady_clock::now();
+    struct Count {
+        gks_mesh* m;
+        std::chrono::steady_clock::time_point t0;
+        ~Count() {
+            ++m->captures;
+            m->capture_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+        }
+    } count{m, t0};
     std::lock_guard<std::mutex> lk(g_dev_mu);
     hipError_t e = hipStreamBeginCapture(m->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) throw CaptureFailed{std::string("hipStreamBeginCapture: ") + hipGetErrorString(e)};
@@ -1682,6 +1746,7 @@ int gks_mesh_create(const gks_mesh_desc* desc, const gks_params* prm, void* hip_
     }
     m->prm = p;
     m->sw.q1 = top_sweeps(p);
+    m->pts.P = start_points(p);
     m->stream = (hipStream_t)hip_stream;
     try {
         HIPCHK(hipGetDevice(&m->device));
@@ -1865,7 +1930,8 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
     try {
         Work& w = m->w;
         // initial guess of the solve: extrapolation of the last solutions
-        int outer = 0;   // Arnoldi steps of this step's solve
+        int outer = 0;     // Arnoldi steps of this step's solve
+        double r0s = 0.0;  // relative residual of its starting guess
         bool speculate = false;
         bool graphs = m->prm.graphs && !m->prof.on && m->capture_failures < 3;
         if (graphs) {
@@ -1896,6 +1962,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
                 return st;
             }
             outer = m->w.st_host->total;
+            r0s = start_resid(*m->w.st_host);
             HIPCHK(hipGraphLaunch(m->gB, m->stream));
             speculate = true;
         } else {
@@ -1913,6 +1980,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
                 return st;
             }
             outer = m->w.st_host->total;
+            r0s = start_resid(*m->w.st_host);
             launch_copyout(m, w.X, w.Xcell);
             if (m->prm.limiter) launch_limit(m, W, w.Xcell, nullptr, w.Xcell, 1.0, m->prm.limiter, w.counters + 2);
             launch_flux(m, W, w.Xcell, w.dt_dev, w.F);
@@ -1937,9 +2005,10 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         HIPCHK(hipStreamSynchronize(m->stream));
         prof_collect(m);
         if (info) info->call_ms = ms_since(t_call);
-        m->hist = std::min(hist, extrap_points(m->prm) - 1) + 1;
+        m->hist = std::min(hist, ring_slots(m->prm)) + 1;
         push_step(m, w.scal_host[0]);
         adapt_first_sweeps(m, outer);
+        adapt_points(m, r0s, m->last_npts);
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);
@@ -1968,6 +2037,8 @@ int gks_mesh_get_stats(const gks_mesh* m, gks_mesh_stats* st) {
     st->graph_steps = m->graph_steps;
     st->capture_failures = m->capture_failures;
     st->split_form = m->d.split ? 1 : 0;
+    st->graph_captures = m->captures;
+    st->capture_ms = m->capture_ms;
     return GKS_OK;
 }
 

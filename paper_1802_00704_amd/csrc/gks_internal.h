@@ -39,6 +39,20 @@ constexpr int MAXB = 16;          // handles per grouped launch
 constexpr int GRAPH_A_CACHE = 8;  // solve graphs kept per handle
 constexpr int MAXH = 4;           // earlier solutions kept for the extrapolated start
 
+// State of the rule that adapts the points of the extrapolated start
+// (points_rule).
+struct PointsAdapt {
+    int P = 0;                // points the starting guess takes
+    int64_t step = 0;         // successful steps seen
+    int64_t hold_until = 0;   // no trial before this step
+    double r0[4] = {};        // starting residuals of the last steps at P
+    int nr = 0;               // entries of r0 filled
+    int since = 0;            // steps at P since the last trial or change
+    int prev = 0;             // the count before the running trial
+    int fails = 0;            // trials in a row that did not start closer
+    bool trial = false;       // this step tries prev - 1 or prev + 1 points
+};
+
 // State of the rule that adapts the mixed form's first-step sweep count
 // (sweep_rule).
 struct SweepAdapt {
@@ -168,7 +182,7 @@ struct Work {
     double* npart = nullptr;      // per-block partial sums of the fused norms: [4][blocks of 10 n threads]
     double* dpart = nullptr;      // per-block partial dots of the fused Gram-Schmidt passes
     double* H[MAXH] = {};         // [n][CB] earlier solutions, a ring
-                                  // (extrap_points(prm) - 1 slots; newest at gks_mesh::hring)
+                                  // (ring_slots(prm) of them; newest at gks_mesh::hring)
     double* w = nullptr;          // [n+1][CB]
     double* t1 = nullptr;         // [n+1][CB]
     double* t2 = nullptr;         // [n+1][CB]
@@ -226,6 +240,10 @@ struct gks_mesh {
     // mixed form: Richardson sweeps of the first outer step, adapted between
     // steps (see adapt_first_sweeps)
     gks::SweepAdapt sw;
+    // points of the extrapolated start, adapted between steps when
+    // extrap_points is 0 (see points_rule)
+    gks::PointsAdapt pts;
+    int last_npts = 0;            // points the last starting guess took
     int budget = 0;               // steps wanted in gA for the next step
     int need_hist[8] = {0};       // first-cycle lengths of the last steps
     int need_n = 0;               // entries of need_hist filled
@@ -235,6 +253,8 @@ struct gks_mesh {
                                   // (newest first; hist of them are valid)
     int64_t graph_steps = 0;      // steps run through the graphs
     int capture_failures = 0;     // captures that failed (3 turn graphs off)
+    int captures = 0;             // captures attempted
+    double capture_ms = 0.0;      // host time in them
     std::string capture_err;      // the last capture failure
     void* scratch = nullptr;      // device address of the static limiter scratch on this
                                   // handle's device (gks_limit_noalloc), or null
@@ -284,6 +304,11 @@ void sweep_rule(SweepAdapt& s, int outer_steps, int top);
 int next_first_sweeps(const gks_mesh* m, int outer_steps);
 // the rule applied to the handle (a no-op unless adaptation is on)
 void adapt_first_sweeps(gks_mesh* m, int outer_steps);
+// the points rule's update after a successful step whose start took used
+// points and had relative residual r0; tol = the solve tolerance
+void points_rule(PointsAdapt& s, double r0, int used, double tol);
+// the rule applied to the handle (a no-op unless extrap_points is 0)
+void adapt_points(gks_mesh* m, double r0, int used);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 // second_pass: the gated second Gram-Schmidt pass (profiler class "reorth")
@@ -322,10 +347,13 @@ void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell);
 void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
 // initial guess of a step's solve from the last solutions (order 0, 1, 2)
 // and shift of the history
-// solutions the starting guess extrapolates from: gks_params.extrap_points,
-// or when that is 0, 5 (3 with the limiter on: limited cells switching
-// between steps make the solutions less smooth in time)
-inline int extrap_points(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points : (p.limiter ? 3 : 5); }
+// earlier solutions kept for the starting guess: extrap_points - 1, or all
+// MAXH slots when the point count adapts (extrap_points = 0)
+inline int ring_slots(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points - 1 : MAXH; }
+// point count a handle starts with: extrap_points, or when that is 0, 5 (3
+// with the limiter on: limited cells switching between steps make the
+// solutions less smooth in time)
+inline int start_points(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points : (p.limiter ? 3 : 5); }
 // starting guess from npts (1..extrap_points) solutions: X and npts - 1 ring
 // slots; stores X in the ring and rotates it
 void launch_extrap(gks_mesh* m, int npts);

@@ -2899,14 +2899,15 @@ void launch_copyout_f32(gks_mesh* m, const float* Xs, double* Xcell) {
 // Arguments of the extrapolation for npts solutions; rotates the handle's
 // ring (the slot receiving X becomes the newest).
 static ExtrapArgs extrap_args(gks_mesh* m, int npts) {
-    const int S = extrap_points(m->prm) - 1;
+    const int S = ring_slots(m->prm);
     ExtrapArgs a{};
     a.len = (int64_t)m->d.n * CB;
     // the solutions used must have their step sizes (a reconstruction
     // outside the step sequence clears them)
     int known = 0;
     while (known < S + 1 && m->dth[known] > 0.0) ++known;
-    a.npts = std::max(1, std::min(std::min(npts, S + 1), known));
+    a.npts = std::max(1, std::min(std::min(std::min(npts, S + 1), m->pts.P), known));
+    m->last_npts = a.npts;
     // Lagrange weights at time 0 of the solutions at tau_0 = -dth[0],
     // tau_i = tau_{i-1} - dth[i]
     double tau[MAXH + 1];

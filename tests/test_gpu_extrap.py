@@ -11,7 +11,11 @@ forms, 12 steps with 1 to 5 extrapolation points:
   * the default (0) takes 5 points, and 3 with the limiter on.
 A reconstruction outside the step sequence clears the step sizes, so the
 steps after it extrapolate only from solutions of the sequence (finite,
-converged starts).
+converged starts).  With the default, the point count adapts: on FP64
+density advection (section 4.1), which starts near the floor the earlier
+solves' residuals set, steps try fewer points; the counts follow the stated
+rule, replayed here from the reported starting residuals, and a batch takes
+the same counts with bitwise the same state.
 """
 import numpy as np
 import pytest
@@ -80,3 +84,85 @@ def test_steps_after_a_reconstruction():
         assert np.isfinite(info["start_resid"]) and max(info["rel_resid"]) <= 1e-10
     assert np.isfinite(W.cpu().numpy()).all()
     gm.close()
+
+
+def replay_points(r0s, used, tol, P=5):
+    """The point counts the adaptive rule gives, from the reported starting
+    residuals and points (the rule as stated with gks_params.extrap_points)."""
+    step = hold = nr = since = prev = fails = 0
+    ring = [0.0] * 4
+    trial = False
+    out = []
+    for r0, u in zip(r0s, used):
+        out.append(P)
+        step += 1
+        if u != P or not r0 > 0.0:
+            continue
+        if trial:
+            trial = False
+            v = sorted(ring[:nr])
+            med = v[nr // 2] if nr % 2 else 0.5 * (v[nr // 2 - 1] + v[nr // 2])
+            if r0 < 0.7 * med:
+                nr = since = fails = 0
+                continue
+            P = prev
+            fails = min(fails + 1, 4)
+            hold = step + (24 << fails)
+            since = 0
+            continue
+        ring = [r0] + ring[:3]
+        nr = min(nr + 1, 4)
+        since += 1
+        if nr < 4 or since < 24 or step < hold:
+            continue
+        floor = ((1 << P) - 1) * tol
+        np_ = 0
+        if P > 2 and r0 < 50.0 * floor:
+            np_ = P - 1
+        elif P < 5 and r0 > 1000.0 * floor:
+            np_ = P + 1
+        if np_:
+            prev, P, trial, since = P, np_, True, 0
+    return out
+
+
+def adv(n=48, seed=2):
+    m = gi.jss_mesh(n, n, seed)
+    return m, gi.density_advection_ic(m)
+
+
+def test_points_adapt_by_the_rule_alone_and_in_a_batch():
+    """FP64 density advection (section 4.1): the smooth flow starts within a
+    few times the solve tolerance, where fewer points start closer."""
+    steps = 90
+    m, W0 = adv()
+    gm = g.GksMesh(m, precision=g.GKS_FP64, tol=1e-10)
+    W = torch.tensor(W0, device="cuda")
+    r0s, used = [], []
+    for _ in range(steps):
+        _, info = gm.step(W)
+        assert max(info["rel_resid"]) <= 1e-10
+        r0s.append(info["start_resid"])
+        used.append(info["start_points"])
+    gm.close()
+    P = replay_points(r0s, used, 1e-10)
+    print("points used", used, flush=True)
+    print("starting residuals", ["%.1e" % r for r in r0s], flush=True)
+    assert used == [max(1, min(i, p)) for i, p in enumerate(P)]
+    assert min(used[10:]) < 5
+    # the same handle in a batch beside a shock-vortex request
+    ms, Ws = sv(30, 15)
+    ha = g.GksMesh(m, precision=g.GKS_FP64, tol=1e-10)
+    hb = g.GksMesh(ms, precision=g.GKS_FP64, tol=1e-10, nonphys_fallback=1)
+    Ta, Tb = torch.tensor(W0, device="cuda"), torch.tensor(Ws, device="cuda")
+    b = g.GksBatch()
+    ub = []
+    for _ in range(steps):
+        res = b.step([ha, hb], [Ta, Tb])
+        assert all(code == 0 for code, _, _ in res)
+        ub.append(res[0][2]["start_points"])
+    b.close()
+    ha.close()
+    hb.close()
+    assert ub == used
+    assert np.array_equal(Ta.cpu().numpy(), W.cpu().numpy())
