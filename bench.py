@@ -549,7 +549,7 @@ def main():
         "dtype": "f64+f32" if head == "mixed" else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "form": head,
-                   "solver": ("multicolour BILU(0); FP64 FGMRES(30) preconditioned by FP32 BILU(0)-Richardson sweeps (6 in the first outer step, adapted down while one outer step suffices; 4 after)"
+                   "solver": ("multicolour BILU(0); FP64 FGMRES(30) preconditioned by FP32 BILU(0)-Richardson sweeps (7 in the first outer step, adapted down while one outer step suffices; 4 after)"
                               + (" (split form)" if r["stats"].get("split_form") else "")
                               + "; start extrapolated from the last five solutions") if head == "mixed"
                    else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from the last five solutions",

@@ -145,7 +145,7 @@ typedef struct {
                                 GKS_INNER_GMRES (then 1 <= inner_iters <= 8;
                                 not with gks_batch_step)                      */
     int32_t inner_iters_first; /* GKS_MIXED, Richardson: sweeps in the first
-                                outer step of each GMRES cycle (6), the later
+                                outer step of each GMRES cycle (7), the later
                                 steps take inner_iters; 0: inner_iters in
                                 every step.  gks_apply_precond applies
                                 inner_iters sweeps                            */
@@ -226,7 +226,7 @@ typedef struct {
 /* Fill p with the paper's parameters: gamma 1.4, inviscid, tau_eps 0.01,
  * w = 0.3 (Eq. A:B:b:3), CFL 0.5, tol 1e-10, GMRES(30), FP64, multicolour,
  * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8, mixed
- * form with 6 Richardson sweeps in the first outer step (adapted between
+ * form with 7 Richardson sweeps in the first outer step (adapted between
  * steps) and 4 after, starting guesses extrapolated from an adapted number of solutions
  * (from 5; 3 with the limiter). */
 void gks_params_default(gks_params* p);

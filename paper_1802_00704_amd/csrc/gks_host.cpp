@@ -1702,7 +1702,7 @@ void gks_params_default(gks_params* p) {
     p->precision = GKS_FP64;
     p->ordering = GKS_ORDER_MULTICOLOR;
     p->inner_iters = 4;
-    p->inner_iters_first = 6;
+    p->inner_iters_first = 7;
     p->adapt_sweeps = 1;
     p->extrap_points = 0;
     p->exact_time = 0;
