@@ -396,7 +396,7 @@ def roofline(prof: dict, elapsed_s: float, n_gauss: int):
     return out
 
 
-SAME_WORK_CLASSES = ("rhs", "cfl", "update", "copyout", "extrap", "spmv_resid", "ilu_fwd32", "ilu_bwd32",
+SAME_WORK_CLASSES = ("rhs", "cfl", "update", "copyout", "spmv_resid", "ilu_fwd32", "ilu_bwd32",
                      "ilu_fwd", "ilu_bwd")
 
 

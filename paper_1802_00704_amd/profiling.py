@@ -143,11 +143,11 @@ def main_fp64(csv_dir: str) -> int:
     return 0
 
 
-def gathers(mesh, applications=(6, 4)) -> dict:
+def gathers(mesh, applications=(7, 4)) -> dict:
     """Distinct neighbour rows per level and the mean compulsory gather bytes
     per launch of each sweep class, for the launch pattern of preconditioner
     applications of the given sweep counts (default: one solve of two outer
-    steps, 6 then 4 sweeps): split-form FP32 sweeps (80-byte rows; the first
+    steps, 7 then 4 sweeps): split-form FP32 sweeps (80-byte rows; the first
     sweep of an application covers every level in its forward pass, the
     later ones skip level 0; every sweep's backward pass covers all but the
     last level) and the FP64 BILU(0) solve (160-byte rows; forward levels
