@@ -261,7 +261,9 @@ int gks_flux(gks_mesh* m, const double* W, const double* X, double dt, double* F
 
 /* One step of Eq. fvm3: dt from the CFL rule when dt <= 0 (the paper gives
  * none: dt = CFL min_i |Omega_i| / sum_f S_f (|U_i . n_f| + c_i)), then the
- * reconstruction, the fluxes and the update W <- W - (1/|Omega|) sum s F.
+ * reconstruction (started from the extrapolation of the handle's earlier
+ * solutions, see gks_params.extrap_points), the fluxes and the update
+ * W <- W - (1/|Omega|) sum s F.
  * W: device [4][nt], updated in place only on success.  dt_used and info may
  * be NULL.  Synchronises the stream before returning.
  * Errors: GKS_EINVAL, GKS_ENOCONV, GKS_ENONPHYS, GKS_EHIP (W unchanged). */
