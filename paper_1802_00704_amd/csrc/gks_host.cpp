@@ -1778,6 +1778,7 @@ int gks_cls_reconstruct(gks_mesh* m, const double* W, double* X, gks_solve_info*
         return GKS_EINVAL;
     }
     try {
+        m->last_npts = 1;   // warm start from the handle's last solution
         const int st = run_solve(m, W, info);
         m->hist = st == GKS_OK ? 1 : 0;   // X is a solution, but not of the step sequence
         std::fill(m->dth, m->dth + MAXH + 1, 0.0);
