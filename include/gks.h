@@ -177,8 +177,8 @@ typedef struct {
                                 tol (the previous solves' residuals amplified
                                 by the weights), a step tries P - 1; while it
                                 is above 1000 (2^P - 1) tol, P + 1.  A trial
-                                comes after at least 24 steps at P and is
-                                kept if its r0 is below 0.7 times the median
+                                comes after at least 8 steps at P and is
+                                kept if its r0 is below 0.8 times the median
                                 of the last four at P; else no trial follows
                                 for 48 steps, doubling with each failure in a
                                 row up to 384.  Only the start changes: every

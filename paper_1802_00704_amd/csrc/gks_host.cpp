@@ -67,9 +67,9 @@ void gks::sweep_rule(SweepAdapt& s, int outer, int top) {
 // they amplify what the earlier solves left: residuals up to tol each.  Once
 // the starting residual r0 comes within 50 (2^P - 1) tol of that floor, a
 // point fewer may start closer; while it stays above 1000 (2^P - 1) tol, a
-// point more may (up to 5).  Such a step tries it once, after at least 24
+// point more may (up to 5).  Such a step tries it once, after at least 8
 // steps at the current count, and keeps it if its starting residual is
-// below 0.7 times the median of the last four at the current count; else
+// below 0.8 times the median of the last four at the current count; else
 // the count goes back and no trial follows for 48 steps, doubling with each
 // failure in a row up to 384.  Steps whose start took fewer points (a short
 // history) or met the tolerance outright leave the rule alone.
@@ -82,7 +82,7 @@ void gks::points_rule(PointsAdapt& s, double r0, int used, double tol) {
         std::copy(s.r0, s.r0 + s.nr, v);
         std::sort(v, v + s.nr);
         const double med = s.nr % 2 ? v[s.nr / 2] : 0.5 * (v[s.nr / 2 - 1] + v[s.nr / 2]);
-        if (r0 < 0.7 * med) {   // the trial count starts closer: keep it
+        if (r0 < 0.8 * med) {   // the trial count starts closer: keep it
             s.nr = 0;
             s.since = 0;
             s.fails = 0;
@@ -98,7 +98,7 @@ void gks::points_rule(PointsAdapt& s, double r0, int used, double tol) {
     s.r0[0] = r0;
     s.nr = std::min(s.nr + 1, 4);
     ++s.since;
-    if (s.nr < 4 || s.since < 24 || s.step < s.hold_until) return;
+    if (s.nr < 4 || s.since < 8 || s.step < s.hold_until) return;
     const double floor = ((1 << s.P) - 1) * tol;
     int np = 0;
     if (s.P > 2 && r0 < 50.0 * floor) np = s.P - 1;
