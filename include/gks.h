@@ -153,16 +153,15 @@ typedef struct {
                                 and gks_batch_step adapt the first outer
                                 step's sweep count between steps, from
                                 inner_iters_first (inner_iters when that is
-                                0) down to 2: after 8 solves
-                                in a row that need a single outer step, the
-                                next step tries one sweep fewer; a trial
-                                that needs more outer steps restores the
-                                count and holds it for 64 steps (doubling
-                                with each such trial in a row, up to 1024),
-                                and 4
-                                solves in a row that need more than one
-                                outer step raise it by one (back to at most
-                                the starting count).  The rule reads only the
+                                0) down to 2.  After 8 solves in a row that
+                                need a single outer step, the next step
+                                tries one sweep fewer; a trial that needs
+                                more outer steps restores the count and
+                                holds it for 64 steps (doubling with each
+                                such trial in a row, up to 1024); 4 solves
+                                in a row that need more than one outer step
+                                raise it by one (back to at most the
+                                starting count).  The rule reads only the
                                 handle's own outer-step counts, so a handle
                                 takes the same counts alone and in a batch.
                                 0: the count stays inner_iters_first        */
