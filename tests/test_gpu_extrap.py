@@ -9,13 +9,15 @@ forms, 12 steps with 1 to 5 extrapolation points:
     full history shrinks with each point added up to 3, and 5 points beat 3
     (the CPU study of this workload: about 100 times);
   * the default (0) takes 5 points, and 3 with the limiter on.
-A reconstruction outside the step sequence clears the step sizes, so the
-steps after it extrapolate only from solutions of the sequence (finite,
-converged starts).  With the default, the point count adapts: on FP64
-density advection (section 4.1), which starts near the floor the earlier
-solves' residuals set, steps try fewer points; the counts follow the stated
-rule, replayed here from the reported starting residuals, and a batch takes
-the same counts with bitwise the same state.
+With alternating step sizes the starts match the Lagrange polynomial
+through the oracle's solutions at their times.  A reconstruction outside the step sequence
+clears the step sizes, so the steps after it extrapolate only from
+solutions of the sequence (finite, converged starts).  With the default,
+the point count adapts: on FP64 density advection (section 4.1), which
+starts near the floor the earlier solves' residuals set, steps try fewer
+points; the counts follow the stated rule, replayed here from the reported
+starting residuals, and a batch takes the same counts with bitwise the same
+state.
 """
 import numpy as np
 import pytest
@@ -73,6 +75,67 @@ def test_limiter_default_takes_three_points():
     Wd, r0d = run(g.GKS_MIXED, 0, steps=10, **kw)
     W3, r03 = run(g.GKS_MIXED, 3, steps=10, **kw)
     assert np.array_equal(Wd, W3) and r0d == r03
+
+
+def lagrange_start(Xs, dts):
+    """The polynomial through the solutions Xs (newest first) taken dts[i]
+    before the next one, evaluated at the current time."""
+    tau = -np.cumsum(dts[:len(Xs)])
+    out = np.zeros_like(Xs[0])
+    for i, X in enumerate(Xs):
+        w = 1.0
+        for j in range(len(Xs)):
+            if j != i:
+                w *= (0.0 - tau[j]) / (tau[i] - tau[j])
+        out += w * X
+    return out
+
+
+def test_varying_steps_use_their_times():
+    """Alternating step sizes (half and 0.3 of the CFL step): the GPU's
+    starting residuals match those of the Lagrange start through the
+    oracle's own solutions at the same times, and are well below those of
+    uniform-step weights (3, -3, 1) on the same solutions."""
+    from oracle import scheme
+    m, W0 = sv(60, 30)
+    s = scheme.Solver(m)
+    K = s.K.tocsr()
+    nt = m.nt
+    probe = g.GksMesh(m, precision=g.GKS_FP64, tol=1e-10)
+    dt0, _ = probe.step(torch.tensor(W0, device="cuda"))
+    probe.close()
+    dts = [dt0 * (0.5 if k % 2 else 0.3) for k in range(10)]
+
+    def cols(X):
+        return np.stack([X[c].T.reshape(-1) for c in range(4)], 1)
+
+    def rel(B, X):
+        return float((np.linalg.norm(B - K @ X, axis=0) / np.linalg.norm(B, axis=0)).max())
+
+    W, hist, lag, uni = W0.copy(), [], [], []
+    for k, dt in enumerate(dts):
+        B = s.rhs(W).reshape(4, 5 * nt).T
+        if k >= 3:
+            lag.append(rel(B, lagrange_start(hist[:3], np.array(dts[k - 1::-1]))))
+            uni.append(rel(B, 3 * hist[0] - 3 * hist[1] + hist[2]))
+        X = s.reconstruct(W)
+        hist.insert(0, cols(X))
+        W = scheme.update(s.geo, W, s.flux(W, X, dt))
+    gm = g.GksMesh(m, precision=g.GKS_FP64, tol=1e-10, extrap_points=3)
+    Wg = torch.tensor(W0, device="cuda")
+    r0 = []
+    for k, dt in enumerate(dts):
+        used, info = gm.step(Wg, dt)
+        assert used == dt and max(info["rel_resid"]) <= 1e-10
+        if k >= 3:
+            r0.append(info["start_resid"])
+    gm.close()
+    print("GPU starting residuals", ["%.2e" % r for r in r0], flush=True)
+    print("oracle, Lagrange start", ["%.2e" % r for r in lag], flush=True)
+    print("oracle, uniform weights", ["%.2e" % r for r in uni], flush=True)
+    for a, b, u in zip(r0, lag, uni):
+        assert abs(a - b) <= 0.02 * b   # the earlier solves differ by their 1e-10 residuals
+        assert u > 10.0 * b
 
 
 def test_steps_after_a_reconstruction():
