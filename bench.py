@@ -551,8 +551,8 @@ def main():
         "config": {"workload": desc, "form": head,
                    "solver": ("multicolour BILU(0); FP64 FGMRES(30) preconditioned by FP32 BILU(0)-Richardson sweeps (7 in the first outer step, adapted down while one outer step suffices; 4 after)"
                               + (" (split form)" if r["stats"].get("split_form") else "")
-                              + "; start extrapolated from the last five solutions") if head == "mixed"
-                   else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from the last five solutions",
+                              + "; start extrapolated from up to six past solutions") if head == "mixed"
+                   else "multicolour BILU(0); FP64 GMRES(30); start extrapolated from up to six past solutions",
                    "cells": m.nt},
         "roofline": roofline(r["profile"], r["profiled_elapsed_s"], 2 * int(r["stats"]["nf"])),
         "flux_fp64": flux_fp64(r["profile"], 2 * int(r["stats"]["nf"])),

@@ -168,19 +168,21 @@ typedef struct {
     int32_t extrap_points;   /* starting guess of each step's solve: the
                                 polynomial through the last extrap_points
                                 solutions at their times, evaluated at the
-                                step's time, 1..5 (fewer while the step
+                                step's time, 1..6 (fewer while the step
                                 sequence has fewer solutions).  0 (default):
-                                the count adapts between steps, from 5 (3
-                                with the limiter on) within 2..5.  Once the
+                                the count adapts between steps, from 6 (3
+                                with the limiter on) within 2..6.  Once the
                                 starting residual r0 is below 50 (2^P - 1)
                                 tol (the previous solves' residuals amplified
                                 by the weights), a step tries P - 1; while it
                                 is above 1000 (2^P - 1) tol, P + 1.  A trial
-                                comes after at least 8 steps at P and is
-                                kept if its r0 is below 0.8 times the median
-                                of the last four at P; else no trial follows
-                                for 48 steps, doubling with each failure in a
-                                row up to 384.  Only the start changes: every
+                                comes after at least 8 steps at P (2 when r0
+                                is below 5 (2^P - 1) tol) and is kept if its
+                                r0 is below 0.8 times the median of the last
+                                four at P or its solve took fewer Arnoldi
+                                steps than theirs; else no trial follows for
+                                48 steps, doubling with each failure in a row
+                                up to 384.  Only the start changes: every
                                 solve still ends on its true residual        */
 } gks_params;
 
@@ -227,7 +229,7 @@ typedef struct {
  * graph replay on, second Gram-Schmidt pass above reorth_tol 1e-8, mixed
  * form with 7 Richardson sweeps in the first outer step (adapted between
  * steps) and 4 after, starting guesses extrapolated from an adapted number of solutions
- * (from 5; 3 with the limiter). */
+ * (from 6; 3 with the limiter). */
 void gks_params_default(gks_params* p);
 
 /* Build the per-mesh state (section 3.1 geometry and Eq. h; the normal

@@ -241,7 +241,7 @@ int gks_batch_step(gks_batch* b, int32_t n, gks_mesh* const* meshes, double* con
                 ms[r]->hist = std::min(hist[r], ring_slots(ms[r]->prm)) + 1;
                 push_step(ms[r], b->slots[r].dt);
                 adapt_first_sweeps(ms[r], b->slots[r].st.total);
-                adapt_points(ms[r], start_resid(b->slots[r].st), ms[r]->last_npts);
+                adapt_points(ms[r], start_resid(b->slots[r].st), ms[r]->last_npts, b->slots[r].st.total);
             }
         }
         const double call_ms = ms_since(t_call);

@@ -64,25 +64,32 @@ void gks::sweep_rule(SweepAdapt& s, int outer, int top) {
 // Points of the extrapolated start (gks_params.extrap_points = 0).  Each
 // point added cuts the extrapolation error of a smooth flow about ten-fold,
 // but the weights grow (their absolute sum is 2^P - 1 at uniform steps), and
-// they amplify what the earlier solves left: residuals up to tol each.  Once
-// the starting residual r0 comes within 50 (2^P - 1) tol of that floor, a
-// point fewer may start closer; while it stays above 1000 (2^P - 1) tol, a
-// point more may (up to 5).  Such a step tries it once, after at least 8
-// steps at the current count, and keeps it if its starting residual is
-// below 0.8 times the median of the last four at the current count; else
-// the count goes back and no trial follows for 48 steps, doubling with each
-// failure in a row up to 384.  Steps whose start took fewer points (a short
-// history) or met the tolerance outright leave the rule alone.
-void gks::points_rule(PointsAdapt& s, double r0, int used, double tol) {
+// they amplify what the earlier solves left: residuals up to tol each, in
+// the directions the solver resolves slowest.  Once the starting residual
+// r0 comes within 50 (2^P - 1) tol of that floor, a point fewer may do
+// better; while it stays above 1000 (2^P - 1) tol, a point more may (up to
+// 6).  Such a step tries it once, after at least 8 steps at the current
+// count (2 when r0 is within 5 (2^P - 1) tol), and keeps it if its start is
+// below 0.8 times the median of the last four at the current count or its
+// solve took fewer Arnoldi steps than their median; else the count goes
+// back and no trial follows for 48 steps, doubling with each failure in a
+// row up to 384.  Steps whose start took fewer points (a short history) or
+// met the tolerance outright leave the rule alone.
+void gks::points_rule(PointsAdapt& s, double r0, int used, int outer, double tol) {
     ++s.step;
     if (used != s.P || !(r0 > 0.0)) return;
     if (s.trial) {
         s.trial = false;
         double v[4];
+        int o[4];
         std::copy(s.r0, s.r0 + s.nr, v);
+        std::copy(s.outer, s.outer + s.nr, o);
         std::sort(v, v + s.nr);
-        const double med = s.nr % 2 ? v[s.nr / 2] : 0.5 * (v[s.nr / 2 - 1] + v[s.nr / 2]);
-        if (r0 < 0.8 * med) {   // the trial count starts closer: keep it
+        std::sort(o, o + s.nr);
+        const int h = s.nr / 2;
+        const double med = s.nr % 2 ? v[h] : 0.5 * (v[h - 1] + v[h]);
+        const double omed = s.nr % 2 ? o[h] : 0.5 * (o[h - 1] + o[h]);
+        if (r0 < 0.8 * med || outer < omed) {   // the trial count does better: keep it
             s.nr = 0;
             s.since = 0;
             s.fails = 0;
@@ -94,12 +101,17 @@ void gks::points_rule(PointsAdapt& s, double r0, int used, double tol) {
         s.since = 0;
         return;
     }
-    for (int i = 3; i > 0; --i) s.r0[i] = s.r0[i - 1];
+    for (int i = 3; i > 0; --i) {
+        s.r0[i] = s.r0[i - 1];
+        s.outer[i] = s.outer[i - 1];
+    }
     s.r0[0] = r0;
+    s.outer[0] = outer;
     s.nr = std::min(s.nr + 1, 4);
     ++s.since;
-    if (s.nr < 4 || s.since < 8 || s.step < s.hold_until) return;
     const double floor = ((1 << s.P) - 1) * tol;
+    const int wait = r0 < 5.0 * floor ? 2 : 8;
+    if (s.nr < 2 || s.since < wait || s.step < s.hold_until) return;
     int np = 0;
     if (s.P > 2 && r0 < 50.0 * floor) np = s.P - 1;
     else if (s.P < MAXH + 1 && r0 > 1000.0 * floor) np = s.P + 1;
@@ -111,8 +123,8 @@ void gks::points_rule(PointsAdapt& s, double r0, int used, double tol) {
     }
 }
 
-void gks::adapt_points(gks_mesh* m, double r0, int used) {
-    if (m->prm.extrap_points == 0) points_rule(m->pts, r0, used, m->prm.tol);
+void gks::adapt_points(gks_mesh* m, double r0, int used, int outer) {
+    if (m->prm.extrap_points == 0) points_rule(m->pts, r0, used, outer, m->prm.tol);
 }
 
 static bool adapts(const gks_mesh* m) {
@@ -2009,7 +2021,7 @@ int gks_step(gks_mesh* m, double* W, double dt, double* dt_used, gks_solve_info*
         m->hist = std::min(hist, ring_slots(m->prm)) + 1;
         push_step(m, w.scal_host[0]);
         adapt_first_sweeps(m, outer);
-        adapt_points(m, r0s, m->last_npts);
+        adapt_points(m, r0s, m->last_npts, outer);
         return GKS_OK;
     } catch (const Fail& f) {
         return fail(m, f);

@@ -37,7 +37,7 @@ constexpr int MAXM = 64;          // largest GMRES restart length
 constexpr int NPROF = 24;         // profiled kernel classes
 constexpr int MAXB = 16;          // handles per grouped launch
 constexpr int GRAPH_A_CACHE = 8;  // solve graphs kept per handle
-constexpr int MAXH = 4;           // earlier solutions kept for the extrapolated start
+constexpr int MAXH = 5;           // earlier solutions kept for the extrapolated start
 
 // State of the rule that adapts the points of the extrapolated start
 // (points_rule).
@@ -46,7 +46,8 @@ struct PointsAdapt {
     int64_t step = 0;         // successful steps seen
     int64_t hold_until = 0;   // no trial before this step
     double r0[4] = {};        // starting residuals of the last steps at P
-    int nr = 0;               // entries of r0 filled
+    int outer[4] = {};        // and their solves' Arnoldi steps
+    int nr = 0;               // entries of r0 and outer filled
     int since = 0;            // steps at P since the last trial or change
     int prev = 0;             // the count before the running trial
     int fails = 0;            // trials in a row that did not start closer
@@ -305,10 +306,11 @@ int next_first_sweeps(const gks_mesh* m, int outer_steps);
 // the rule applied to the handle (a no-op unless adaptation is on)
 void adapt_first_sweeps(gks_mesh* m, int outer_steps);
 // the points rule's update after a successful step whose start took used
-// points and had relative residual r0; tol = the solve tolerance
-void points_rule(PointsAdapt& s, double r0, int used, double tol);
+// points and had relative residual r0, and whose solve took outer Arnoldi
+// steps; tol = the solve tolerance
+void points_rule(PointsAdapt& s, double r0, int used, int outer, double tol);
 // the rule applied to the handle (a no-op unless extrap_points is 0)
-void adapt_points(gks_mesh* m, double r0, int used);
+void adapt_points(gks_mesh* m, double r0, int used, int outer);
 void launch_dots_reduce(gks_mesh* m, int kc, const double* V, int64_t vstride, int nvec, const double* w,
                         const double* scale, double* out, const int32_t* gate = nullptr);
 // second_pass: the gated second Gram-Schmidt pass (profiler class "reorth")
@@ -350,10 +352,10 @@ void launch_copyin(gks_mesh* m, const double* Xcell, double* Xs);
 // earlier solutions kept for the starting guess: extrap_points - 1, or all
 // MAXH slots when the point count adapts (extrap_points = 0)
 inline int ring_slots(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points - 1 : MAXH; }
-// point count a handle starts with: extrap_points, or when that is 0, 5 (3
+// point count a handle starts with: extrap_points, or when that is 0, 6 (3
 // with the limiter on: limited cells switching between steps make the
 // solutions less smooth in time)
-inline int start_points(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points : (p.limiter ? 3 : 5); }
+inline int start_points(const gks_params& p) { return p.extrap_points > 0 ? p.extrap_points : (p.limiter ? 3 : 6); }
 // starting guess from npts (1..extrap_points) solutions: X and npts - 1 ring
 // slots; stores X in the ring and rotates it
 void launch_extrap(gks_mesh* m, int npts);

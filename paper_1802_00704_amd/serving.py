@@ -74,9 +74,9 @@ def estimate_footprint(nt: int, precision: int = 0, restart: int = 30) -> int:
     """Device bytes one request holds for nt cells (upper estimate of the
     allocations of gks_mesh_create plus its state W): FP64 matrix, factors
     and geometry, solver vectors and the Krylov basis, FP32 copies and the
-    FP32 basis in the mixed form, and up to four earlier solutions for the
+    FP32 basis in the mixed form, and up to five earlier solutions for the
     extrapolated start."""
-    per_cell = 2300 + 380 + (7 + restart) * 160 + 400 + 32 + 480
+    per_cell = 2300 + 380 + (7 + restart) * 160 + 400 + 32 + 640
     if precision == GKS_MIXED:
         per_cell += 1100 + (restart + 2) * 80
     return int(nt * per_cell * 1.05) + (1 << 20)
