@@ -373,7 +373,8 @@ def roofline(prof: dict, elapsed_s: float, n_gauss: int):
         fl = measured_flops("flux")
         if d["ms"] <= 0:
             return None
-        out = {"bound": "alu", "kernel": name, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "traffic": None}
+        out = {"bound": "alu", "kernel": name, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+               "traffic": measured_traffic(name)}
         if fl:
             ex = fl / (us * 1e-6) / 1e12
             out.update({"achieved": round(ex, 2), "frac": round(ex / FP64_PEAK_TFLOPS, 4),
